@@ -1,0 +1,297 @@
+"""CPU oracle for the Fast Dispersion Measure Transform and its adjoint.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import, call or
+execute this module; only the tests, the smoke check and the benchmark's
+CPU-baseline leg use it. It shares no code, headers, tables or constants
+with the HIP library.
+
+It follows Zackay & Ofek, "An accurate and efficient algorithm for detection
+of radio bursts with an unknown dispersion measure" (arXiv:1411.5373),
+Sec. 3 ("The FDMT Algorithm") and Algorithm 1, step by step, in plain NumPy:
+one vector add per (iteration, sub-band, delay) row, as in the paper's
+vectorised form (caption of Fig. 2). Integer inputs are summed in int64,
+floating inputs in float64 after an exact upcast.
+
+Notation. I[f][t]: input, channel 0 = lowest frequency, t contiguous.
+A_{f0}^{f2}(t0, dt): sum along the dispersion curve that enters the
+sub-band [f0, f2) at time t0 (its lowest frequency) and leaves it dt samples
+earlier (Eq. parametrization). All planes are indexed [dt][t0].
+
+Readings where the paper is silent, garbled or inconsistent (each one is
+listed with its justification in the design notes):
+  R-f1   f1 in the addition rule is the border frequency between the two
+         sub-bands, i.e. the midpoint of [f0, f2] (Sec. 3.2, "Dealing with the
+         case Nf != 2^k", names it the border frequency; "(f2-f0)/2" is a typo).
+  R-t2   the upper half is A_{f1}^{f2}(t1, t1 - t2) (the second statement of the
+         rule repeats it as t1 - t0, a typo).
+  R-init the Option-1 partial sums run backwards in time,
+         A_f^{f+df}(t, dt) = sum_{i=0}^{dt} I(f, t - i): a curve leaves a
+         channel earlier at its upper edge, as t1 < t0 in the addition rule.
+  R-copy the alternative (copy) rule for t1 < 0 equals treating I as zero at
+         negative times; outputs with t0 < dt are partial paths.
+  R-round t0 - t1 = C*dt is rounded half up in float64: d_lo = floor(dt*C + 0.5);
+         the upper sub-band's delay is dt - d_lo and its shift is d_lo, so the
+         two halves meet at one shared sample time t1 = t0 - d_lo.
+  R-rows row counts are derived top-down from the Nd output rows, child rows
+         = largest index the parent reads + 1 (the paper's dt_max formula is
+         its continuous estimate of the same quantity).
+  R-fp   1/f^2 is evaluated as 1.0/(f*f); C = (1/f1^2 - 1/f0^2)/(1/f2^2 - 1/f0^2)
+         in that order, IEEE float64, no fused multiply-add.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+# ----------------------------------------------------------------------------
+# Frequency grid and merge coefficient (Sec. 1 Eq. DtD, Sec. 3 Eq. Cf2f0)
+# ----------------------------------------------------------------------------
+
+def channel_edges(nf, f_min, f_max):
+    """Edges e_k = f_min + k*delta_f, delta_f = (f_max - f_min)/N_f (Sec. 3,
+    definition of delta_f under the simple initialization), k = 0..N_f."""
+    delta_f = (f_max - f_min) / nf
+    return [f_min + k * delta_f for k in range(nf + 1)]
+
+
+def _inv_sq(f):
+    return 1.0 / (f * f)
+
+
+def merge_coefficient(f0, f1, f2):
+    """Eq. (Cf2f0): C_{f2,f0} = (f1^-2 - f0^-2) / (f2^-2 - f0^-2), the fraction of
+    the sub-band delay spent between f0 and the border frequency f1."""
+    return (_inv_sq(f1) - _inv_sq(f0)) / (_inv_sq(f2) - _inv_sq(f0))
+
+
+def round_half_up(x):
+    """Reading R-round: nearest integer, ties upward."""
+    return int(math.floor(x + 0.5))
+
+
+# ----------------------------------------------------------------------------
+# Delay tables (Sec. 3: t1 = t0 - C*dt; dt_max decided before the computation)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Tables:
+    nf: int
+    nd: int
+    f_min: float
+    f_max: float
+    levels: int                 # log2(nf)
+    rows: list                  # rows[l][j]: number of dt rows of sub-band j at iteration l
+    split: list                 # split[l][j][dt] = (d_lo, s, d_hi) for l >= 1
+
+    @property
+    def leaf_rows(self):
+        return self.rows[0]
+
+
+def build_tables(nf, nd, f_min, f_max):
+    """Per iteration l = 1..log2(Nf) and sub-band j (channels j*2^l .. (j+1)*2^l - 1,
+    f0 = e[j*2^l], f1 = e[(2j+1)*2^(l-1)], f2 = e[(j+1)*2^l]):
+        for each dt: t0 - t1 = d_lo = round(C_{f2,f0} * dt)   (lower half's delay)
+                     s = d_lo                                  (upper half's start shift)
+                     t1 - t2 = d_hi = dt - d_lo                (upper half's delay)
+    Row counts run top-down from Nd at the last iteration (reading R-rows)."""
+    if nf < 1 or nf & (nf - 1):
+        raise ValueError("Nf must be a power of two")
+    if nd < 1:
+        raise ValueError("Nd must be >= 1")
+    if not (0.0 < f_min < f_max):
+        raise ValueError("need 0 < f_min < f_max")
+    levels = nf.bit_length() - 1
+    e = channel_edges(nf, f_min, f_max)
+    rows = [None] * (levels + 1)
+    split = [None] * (levels + 1)
+    rows[levels] = [nd]
+    for l in range(levels, 0, -1):
+        nsub = nf >> l
+        rows[l - 1] = [0] * (2 * nsub)
+        split[l] = []
+        for j in range(nsub):
+            f0 = e[j << l]
+            f1 = e[(2 * j + 1) << (l - 1)]
+            f2 = e[(j + 1) << l]
+            c = merge_coefficient(f0, f1, f2)
+            triples = []
+            for dt in range(rows[l][j]):
+                d_lo = round_half_up(dt * c)
+                triples.append((d_lo, d_lo, dt - d_lo))
+            split[l].append(triples)
+            last = triples[-1]
+            rows[l - 1][2 * j] = last[0] + 1
+            rows[l - 1][2 * j + 1] = last[2] + 1
+    return Tables(nf, nd, f_min, f_max, levels, rows, split)
+
+
+# ----------------------------------------------------------------------------
+# Forward transform (Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def _acc_dtype(x):
+    return np.int64 if np.asarray(x).dtype.kind in "iub" else np.float64
+
+
+def initialize(img, tables):
+    """Option 1 (Sec. 3): A_f^{f+df}(t, dt) = sum_{i=0}^{dt} I(f, t - i) for
+    dt = 0..rows[0][k]-1, with I = 0 before the record starts (readings R-init,
+    R-copy). Built as the chain A(t, dt) = A(t, dt-1) + I(f, t - dt)."""
+    img = np.asarray(img)
+    nf, nt = img.shape
+    acc = _acc_dtype(img)
+    x = img.astype(acc)
+    planes = []
+    for k in range(nf):
+        n = tables.rows[0][k]
+        a = np.zeros((n, nt), dtype=acc)
+        a[0] = x[k]
+        for dt in range(1, n):
+            a[dt] = a[dt - 1]
+            if dt < nt:
+                a[dt, dt:] += x[k, : nt - dt]
+        planes.append(a)
+    return planes
+
+
+def iterate(planes, tables, nt):
+    """The iterations of Algorithm 1: for i = 1..log2(Nf), for each sub-band pair,
+    for each dt, for each t0:
+        A_{f0}^{f2}(t0, dt) = A_{f0}^{f1}(t0, d_lo) + A_{f1}^{f2}(t0 - s, d_hi)   (t0 >= s)
+        A_{f0}^{f2}(t0, dt) = A_{f0}^{f1}(t0, d_lo)                             (t0 <  s)
+    where the second line is the alternative (copy) rule for t1 = t0 - s < 0."""
+    for l in range(1, tables.levels + 1):
+        merged = []
+        for j in range(tables.nf >> l):
+            lower, upper = planes[2 * j], planes[2 * j + 1]
+            out = np.empty((tables.rows[l][j], nt), dtype=lower.dtype)
+            for dt, (d_lo, s, d_hi) in enumerate(tables.split[l][j]):
+                if s < nt:
+                    out[dt, s:] = lower[d_lo, s:] + upper[d_hi, : nt - s]
+                    out[dt, :s] = lower[d_lo, :s]
+                else:
+                    out[dt] = lower[d_lo]
+            merged.append(out)
+        planes = merged
+    return planes[0]
+
+
+def fdmt(img, f_min, f_max, nd, tables=None):
+    """A_{f_min}^{f_max}(t0, dt) for dt = 0..nd-1, t0 = 0..nt-1; shape [nd][nt]."""
+    img = np.asarray(img)
+    nf, nt = img.shape
+    if tables is None:
+        tables = build_tables(nf, nd, f_min, f_max)
+    return iterate(initialize(img, tables), tables, nt)
+
+
+def fdmt_batch(imgs, f_min, f_max, nd):
+    tables = build_tables(imgs.shape[-2], nd, f_min, f_max)
+    return np.stack([fdmt(x, f_min, f_max, nd, tables) for x in imgs])
+
+
+# ----------------------------------------------------------------------------
+# Adjoint (transpose of the linear map above, term by term)
+# ----------------------------------------------------------------------------
+
+def fdmt_adjoint(grad, f_min, f_max, nf, tables=None):
+    """Transpose of fdmt(): grad [nd][nt] -> [nf][nt].
+
+    Each forward term out[dt][t0] += lower[d_lo][t0] becomes
+    lower_bar[d_lo][t0] += out_bar[dt][t0]; each out[dt][t0] += upper[d_hi][t0 - s]
+    (t0 >= s) becomes upper_bar[d_hi][t] += out_bar[dt][t + s] (t + s < nt); each
+    init term A(t, dt) += I(f, t - i) becomes I_bar(f, t) += A_bar(t + i, dt).
+    Iterations run from the last to the first; within a sub-band, dt ascends."""
+    grad = np.asarray(grad)
+    nd, nt = grad.shape
+    if tables is None:
+        tables = build_tables(nf, nd, f_min, f_max)
+    acc = _acc_dtype(grad)
+    planes = [grad.astype(acc)]
+    for l in range(tables.levels, 0, -1):
+        split_planes = []
+        for j, g in enumerate(planes):
+            lo_bar = np.zeros((tables.rows[l - 1][2 * j], nt), dtype=acc)
+            hi_bar = np.zeros((tables.rows[l - 1][2 * j + 1], nt), dtype=acc)
+            for dt, (d_lo, s, d_hi) in enumerate(tables.split[l][j]):
+                lo_bar[d_lo] += g[dt]
+                if s < nt:
+                    hi_bar[d_hi, : nt - s] += g[dt, s:]
+            split_planes += [lo_bar, hi_bar]
+        planes = split_planes
+    out = np.zeros((nf, nt), dtype=acc)
+    for k in range(nf):
+        a_bar = planes[k]
+        for dt in range(tables.rows[0][k]):
+            for i in range(min(dt, nt - 1) + 1):
+                out[k, : nt - i] += a_bar[dt, i:]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Path walk: which samples each output adds (used by brute-force checks)
+# ----------------------------------------------------------------------------
+
+def path(tables, dt):
+    """Descend the tables from output row dt to the channels. Returns per channel
+    k the pair (sigma_k, delta_k): channel k contributes I[k][t0 - sigma_k - i]
+    for i = 0..delta_k."""
+    nodes = [(0, dt)]
+    for l in range(tables.levels, 0, -1):
+        nxt = []
+        for j, (sigma, d) in enumerate(nodes):
+            d_lo, s, d_hi = tables.split[l][j][d]
+            nxt.append((sigma, d_lo))
+            nxt.append((sigma + s, d_hi))
+        nodes = nxt
+    return nodes
+
+
+def brute_point(img, tables, dt, t0):
+    """One output by explicit summation along its path (plain loops)."""
+    img = np.asarray(img)
+    nt = img.shape[1]
+    total = 0 if img.dtype.kind in "iub" else 0.0
+    for k, (sigma, delta) in enumerate(path(tables, dt)):
+        for i in range(delta + 1):
+            t = t0 - sigma - i
+            if 0 <= t < nt:
+                total += int(img[k, t]) if img.dtype.kind in "iub" else float(img[k, t])
+    return total
+
+
+def brute_row(img, tables, dt):
+    """One whole output row by explicit summation along its path, vectorised over t0."""
+    img = np.asarray(img)
+    nf, nt = img.shape
+    acc = _acc_dtype(img)
+    out = np.zeros(nt, dtype=acc)
+    for k, (sigma, delta) in enumerate(path(tables, dt)):
+        for i in range(delta + 1):
+            sh = sigma + i
+            if sh < nt:
+                out[sh:] += img[k, : nt - sh].astype(acc)
+    return out
+
+
+def brute_ideal(img, f_min, f_max, nd):
+    """Brute-force dedispersion along the exact law (prior-art comparator, Sec. 2):
+    each channel contributes I[k][t0 - round(dt * phi(centre_k))]."""
+    img = np.asarray(img)
+    nf, nt = img.shape
+    e = channel_edges(nf, f_min, f_max)
+    acc = _acc_dtype(img)
+    out = np.zeros((nd, nt), dtype=acc)
+    den = _inv_sq(f_min) - _inv_sq(f_max)
+    for k in range(nf):
+        centre = 0.5 * (e[k] + e[k + 1])
+        phi = (_inv_sq(f_min) - _inv_sq(centre)) / den
+        for dt in range(nd):
+            sh = round_half_up(dt * phi)
+            if sh < nt:
+                out[dt, sh:] += img[k, : nt - sh].astype(acc)
+    return out

@@ -1,0 +1,294 @@
+"""Pins for the CPU oracle: each test ties it to something other than itself
+(a hand-worked example, a closed form, a bound from the dispersion law, an
+invariant of the transform, brute force on tiny inputs, or a textbook
+reduction). Together they are chosen so that a dropped term, a wrong sign or
+index, or a swapped operand in the oracle fails at least one of them."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from oracle import (brute_ideal, brute_point, brute_row, build_tables, fdmt,
+                    fdmt_adjoint, path)
+import workloads as W
+
+BANDS = [(1.2, 1.6), (0.4, 0.8), (1.0, 2.0)]
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------- worked examples
+
+@pytest.mark.parametrize("name", ["tiny_nf2_nd3.txt", "tiny_nf4_nd4.txt"])
+def test_hand_derived_examples(name):
+    """Hand-derived outputs of one and two iterations (fixtures cite the
+    addition rule, Eq. Cf2f0 and Option-1 init); pins direction of shifts,
+    which half is shifted, and the per-sub-band f0/f1/f2."""
+    f_min, f_max, nd, img, expect = read_golden(name)
+    np.testing.assert_array_equal(fdmt(img, f_min, f_max, nd), expect)
+
+
+# ---------------------------------------------------------------- delay tables
+
+@pytest.mark.parametrize("nf,nd", [(2, 3), (8, 8), (64, 64), (256, 100), (1024, 1024), (4096, 2048)])
+@pytest.mark.parametrize("band", BANDS)
+def test_table_invariants(nf, nd, band):
+    """Each split is a partition of the delay (d_lo + d_hi = dt, s = d_lo), the
+    maps are monotone with unit steps, and every child row exists."""
+    t = build_tables(nf, nd, *band)
+    assert t.rows[t.levels] == [nd]
+    for l in range(1, t.levels + 1):
+        for j, trip in enumerate(t.split[l]):
+            assert len(trip) == t.rows[l][j]
+            prev = None
+            for dt, (d_lo, s, d_hi) in enumerate(trip):
+                assert 0 <= d_lo <= dt and s == d_lo and d_lo + d_hi == dt
+                assert d_lo < t.rows[l - 1][2 * j] and d_hi < t.rows[l - 1][2 * j + 1]
+                if prev is not None:
+                    assert d_lo - prev[0] in (0, 1) and d_hi - prev[2] in (0, 1)
+                prev = (d_lo, s, d_hi)
+            assert trip[-1][0] + 1 == t.rows[l - 1][2 * j]
+            assert trip[-1][2] + 1 == t.rows[l - 1][2 * j + 1]
+
+
+@pytest.mark.parametrize("nf,nd", [(16, 40), (64, 64), (1024, 1024), (4096, 2048)])
+@pytest.mark.parametrize("band", BANDS)
+def test_path_follows_dispersion_law(nf, nd, band):
+    """Closed-form bound from Eq. (DtD): along every output path the start shift
+    of channel k deviates from the exact law dt*phi(e_k) by at most
+    log2(Nf)/2 samples (each iteration rounds once, by <= 1/2, and carries a
+    convex combination of its parent's errors). The runs of consecutive
+    channels tile [t0 - dt, t0], sharing one sample per channel border."""
+    f_min, f_max = band
+    t = build_tables(nf, nd, f_min, f_max)
+    e = np.array([f_min + k * (f_max - f_min) / nf for k in range(nf)])
+    phi = (f_min ** -2 - e ** -2) / (f_min ** -2 - f_max ** -2)
+    bound = 0.5 * t.levels + 1e-9
+    step = max(1, nd // 97)
+    for dt in list(range(0, nd, step)) + [nd - 1]:
+        p = np.array(path(t, dt))
+        sig, dlt = p[:, 0], p[:, 1]
+        assert sig[0] == 0
+        np.testing.assert_array_equal(sig[1:], sig[:-1] + dlt[:-1])
+        assert sig[-1] + dlt[-1] == dt
+        assert np.max(np.abs(sig - dt * phi)) <= bound
+
+
+def test_work_below_paper_bound():
+    """Sec. 3.1: additions <= 2*Nf*Nt + Nt*Nd*log2(Nf) (per unit Nt)."""
+    for nf, nd in [(64, 64), (1024, 1024), (4096, 2048), (1024, 512)]:
+        t = build_tables(nf, nd, 1.2, 1.6)
+        adds = sum(sum(r) for r in t.rows[1:]) + sum(n - 1 for n in t.rows[0])
+        assert adds <= 2 * nf + nd * t.levels
+
+
+# ---------------------------------------------------------------- recursion
+
+@pytest.mark.parametrize("nf,nt,nd", [(1, 20, 7), (2, 16, 5), (8, 40, 12), (16, 64, 30), (32, 50, 64)])
+@pytest.mark.parametrize("band", BANDS)
+def test_recursion_equals_path_brute_force(nf, nt, nd, band):
+    """Bottom-up recursion == top-down path summation, exact in int64, including
+    partial paths (t0 < dt: copy rule) and Nt < Nd."""
+    img = _rng(nf * 1000 + nt).integers(-50, 200, size=(nf, nt))
+    t = build_tables(nf, nd, *band)
+    out = fdmt(img, band[0], band[1], nd, t)
+    for dt in range(nd):
+        np.testing.assert_array_equal(out[dt], brute_row(img, t, dt))
+    for dt, t0 in [(0, 0), (nd - 1, nt - 1), (nd // 2, nt // 3), (nd - 1, 0)]:
+        assert out[dt, t0] == brute_point(img, t, dt, t0)
+
+
+@pytest.mark.parametrize("nf,nd", [(8, 8), (64, 64), (256, 300)])
+def test_zero_delay_row_is_channel_sum(nf, nd):
+    """At dt = 0 the curve is vertical: row 0 = sum over frequencies of I[f][t0]."""
+    img = _rng(nf).integers(0, 256, size=(nf, 300))
+    np.testing.assert_array_equal(fdmt(img, 1.2, 1.6, nd)[0], img.sum(axis=0))
+
+
+@pytest.mark.parametrize("nf,nd", [(4, 9), (64, 64), (128, 200)])
+def test_all_ones_closed_form(nf, nd):
+    """A complete path (t0 >= dt) through all-ones data adds Nf + dt samples
+    (Nf channel runs whose lengths add to dt + Nf); no term is dropped or doubled."""
+    nt = nd + 40
+    out = fdmt(np.ones((nf, nt), dtype=np.int64), 1.2, 1.6, nd)
+    for dt in range(nd):
+        np.testing.assert_array_equal(out[dt, dt:], nf + dt)
+
+
+def test_single_channel_is_running_box_sum():
+    """Nf = 1 (no iterations): A(t0, dt) = sum_{i=0}^{dt} I(t0 - i), i.e. a
+    difference of cumulative sums (textbook moving sum)."""
+    x = _rng(5).integers(-9, 10, size=(1, 64))
+    out = fdmt(x, 1.2, 1.6, 20)
+    c = np.concatenate([[0], np.cumsum(x[0])])
+    for dt in range(20):
+        t0 = np.arange(64)
+        expect = c[t0 + 1] - c[np.maximum(t0 - dt, 0)]
+        np.testing.assert_array_equal(out[dt], expect)
+
+
+def test_linearity_exact():
+    a = _rng(1).integers(-100, 100, size=(32, 80))
+    b = _rng(2).integers(-100, 100, size=(32, 80))
+    fa, fb = fdmt(a, 1.2, 1.6, 40), fdmt(b, 1.2, 1.6, 40)
+    np.testing.assert_array_equal(fdmt(3 * a - 2 * b, 1.2, 1.6, 40), 3 * fa - 2 * fb)
+
+
+def test_time_shift_equivariance():
+    """Delaying every channel by tau (zero fill) delays every output row by tau."""
+    x = _rng(3).integers(0, 50, size=(16, 100))
+    tau = 13
+    xs = np.zeros_like(x)
+    xs[:, tau:] = x[:, :-tau]
+    a, b = fdmt(x, 1.2, 1.6, 24), fdmt(xs, 1.2, 1.6, 24)
+    np.testing.assert_array_equal(b[:, tau:], a[:, :-tau])
+    np.testing.assert_array_equal(b[:, :tau], 0)
+
+
+def test_causal_window():
+    """Output (dt, t0) reads only input times in [t0 - dt, t0]."""
+    nf, nt, nd = 16, 90, 30
+    x = _rng(4).integers(0, 50, size=(nf, nt))
+    base = fdmt(x, 1.2, 1.6, nd)
+    tp = 40
+    y = x.copy()
+    y[:, tp] += 1000
+    diff = fdmt(y, 1.2, 1.6, nd) - base
+    for dt in range(nd):
+        assert np.all(diff[dt, :tp] == 0)
+        assert np.all(diff[dt, tp + dt + 1:] == 0)
+        assert diff[dt, tp] != 0  # channel 0 is always read at t0
+
+
+def test_commutes_with_causal_time_filter():
+    """Sec. 3.2 (pulse profile): convolving every channel's time series with the
+    same profile commutes with the transform (exact in integers)."""
+    x = _rng(6).integers(-20, 20, size=(32, 120))
+    h = np.array([3, -1, 2, 5])
+
+    def filt(a):
+        out = np.zeros_like(a)
+        for i, hi in enumerate(h):
+            out[..., i:] += hi * a[..., : a.shape[-1] - i]
+        return out
+
+    np.testing.assert_array_equal(fdmt(filt(x), 1.2, 1.6, 48), filt(fdmt(x, 1.2, 1.6, 48)))
+
+
+def test_blocked_streaming_equals_one_shot():
+    """Processing time in blocks with Nd-1 samples of history per channel
+    reproduces the one-shot transform exactly (outputs only look back dt)."""
+    nf, nt, nd = 32, 400, 50
+    x = _rng(7).integers(0, 255, size=(nf, nt))
+    full = fdmt(x, 1.2, 1.6, nd)
+    for t_start, t_end in [(0, 130), (130, 131), (131, 290), (290, 400)]:
+        h = max(0, t_start - (nd - 1))
+        blk = fdmt(x[:, h:t_end], 1.2, 1.6, nd)
+        np.testing.assert_array_equal(blk[:, t_start - h:], full[:, t_start:t_end])
+
+
+def test_init_rows_are_partial_sums():
+    """Option-1 init (with the backward-in-time reading) is what a single-channel
+    sub-band holds: with Nf = 1 the output equals the partial sums directly."""
+    x = np.array([[1, 2, 4, 8, 16]])
+    out = fdmt(x, 1.0, 2.0, 3)
+    np.testing.assert_array_equal(out, [[1, 2, 4, 8, 16], [1, 3, 6, 12, 24], [1, 3, 7, 14, 28]])
+
+
+# ---------------------------------------------------------------- pulse recovery
+
+def test_c1_pulse_recovered():
+    """A dispersed pulse (Eq. DtD) peaks at its (dt, T) in the transform."""
+    img, pulses = W.make_c1()
+    w = W.WORKLOADS["c1"]
+    out = fdmt(img, w.f_min, w.f_max, w.nd)
+    dt, t_arr, amp = pulses[0]
+    i, j = np.unravel_index(np.argmax(out), out.shape)
+    assert abs(i - dt) <= 2 and abs(j - t_arr) <= 2
+    assert out[i, j] >= 0.6 * w.nf * amp
+
+
+@pytest.mark.parametrize("nf,nd,band", [(256, 256, (1.2, 1.6)), (256, 512, (0.4, 0.8)), (1024, 300, (1.2, 1.6))])
+def test_noiseless_pulses_recovered(nf, nd, band):
+    """Noiseless width-1 pulses at several delays: the transform's peak sits within
+    2 samples of the truth in both axes (2*Nd/Nf in delay when Nd > Nf, where each
+    channel spans several delay samples and neighbouring delays tie) and captures
+    >= 60% of the pulse; the brute-force law integration (Sec. 2) captures all of
+    it at the truth."""
+    rng = _rng(nf + nd)
+    nt = nd + 200
+    tol_dt = 2 * max(1, nd // nf)
+    for dt in [0, nd // 5, nd // 2, nd - 1]:
+        t_arr = int(rng.integers(nd, nt))
+        img = np.zeros((nf, nt), dtype=np.int64)
+        W.inject_pulses(img, band[0], band[1], [(dt, t_arr, 1.0)])
+        out = fdmt(img, band[0], band[1], nd)
+        i, j = np.unravel_index(np.argmax(out), out.shape)
+        assert abs(i - dt) <= tol_dt and abs(j - t_arr) <= 2, (dt, t_arr, i, j)
+        assert out[i, j] >= 0.6 * nf
+    ideal = brute_ideal(img, band[0], band[1], nd)
+    assert ideal[dt, t_arr] == nf
+
+
+# ---------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("nf,nt,nd", [(1, 30, 9), (8, 40, 16), (32, 64, 64), (64, 50, 90)])
+@pytest.mark.parametrize("band", [(1.2, 1.6), (0.4, 0.8)])
+def test_adjoint_dot_product_exact(nf, nt, nd, band):
+    """<A x, y> = <x, A^T y>, exact in int64."""
+    rng = _rng(nf * 7 + nt)
+    x = rng.integers(-30, 30, size=(nf, nt))
+    y = rng.integers(-30, 30, size=(nd, nt))
+    ax = fdmt(x, band[0], band[1], nd)
+    aty = fdmt_adjoint(y, band[0], band[1], nf)
+    assert int(np.sum(ax * y)) == int(np.sum(x * aty))
+
+
+def test_adjoint_matches_explicit_matrix():
+    """A^T from the adjoint equals the transpose of the matrix assembled column by
+    column from forward transforms of unit impulses."""
+    nf, nt, nd = 8, 12, 10
+    cols = []
+    for k in range(nf):
+        for t in range(nt):
+            e = np.zeros((nf, nt), dtype=np.int64)
+            e[k, t] = 1
+            cols.append(fdmt(e, 1.2, 1.6, nd).ravel())
+    a = np.stack(cols, axis=1)
+    for r in range(nd * nt):
+        y = np.zeros(nd * nt, dtype=np.int64)
+        y[r] = 1
+        np.testing.assert_array_equal(fdmt_adjoint(y.reshape(nd, nt), 1.2, 1.6, nf).ravel(), a[r])
+
+
+def _lse(z):
+    m = z.max()
+    return m + math.log(np.exp(z - m).sum())
+
+
+def test_adjoint_finite_differences_fp64():
+    """Loss = logsumexp over the DM-time plane on the Nf=32, Nt=256, Nd=32 slice of
+    the 0.4-0.8 GHz workload; gradient A^T softmax(Ax) vs central differences."""
+    nf, nt, nd, band = 32, 256, 32, (0.4, 0.8)
+    x = W.make_c5(batch=1, nf=nf, nt=nt)[0].astype(np.float64)
+    ax = fdmt(x, *band, nd)
+    p = np.exp(ax - ax.max())
+    p /= p.sum()
+    grad = fdmt_adjoint(p, *band, nf)
+    rng = _rng(11)
+    h = 1e-5
+    for _ in range(8):
+        v = rng.standard_normal((nf, nt))
+        fd = (_lse(fdmt(x + h * v, *band, nd)) - _lse(fdmt(x - h * v, *band, nd))) / (2 * h)
+        an = float(np.sum(grad * v))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+    gmax = np.abs(grad).max()
+    for _ in range(64):
+        k, t = int(rng.integers(nf)), int(rng.integers(nt))
+        e = np.zeros((nf, nt))
+        e[k, t] = 1.0
+        fd = (_lse(fdmt(x + h * e, *band, nd)) - _lse(fdmt(x - h * e, *band, nd))) / (2 * h)
+        assert abs(fd - grad[k, t]) <= 1e-6 * gmax
