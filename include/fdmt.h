@@ -1,0 +1,149 @@
+/*
+ * fdmt.h - C ABI of the MI355X (gfx950) Fast Dispersion Measure Transform.
+ *
+ * The transform is the one of Zackay & Ofek, arXiv:1411.5373, Sec. 3 and
+ * Algorithm 1: the input is an intensity matrix I[f][t] (channel 0 = lowest
+ * frequency f_min, time contiguous, Sec. 3.2 "Memory access"), the output is
+ * A[dt][t0] = the sum of I along the dispersion curve of Eq. (DtD) that
+ * reaches f_min at sample t0 and spans dt samples across the band
+ * (Eq. parametrization), for dt = 0 .. Nd-1 and t0 = 0 .. Nt-1.
+ *
+ * Discretisation (the paper leaves it to the implementation, Sec. 3.2
+ * "Rounding and binning"):
+ *   - channel k covers [f_min + k*df, f_min + (k+1)*df), df = (f_max-f_min)/Nf;
+ *   - the addition rule merges sub-bands [f0,f1) and [f1,f2) with f1 their
+ *     border frequency, t0 - t1 = round_half_up(dt * C_{f2,f0}) (Eq. Cf2f0,
+ *     evaluated in IEEE float64 as (1/(f1*f1) - 1/(f0*f0)) / (1/(f2*f2) - 1/(f0*f0)),
+ *     no fused multiply-add), the upper half shifted by that same amount;
+ *   - Option-1 initialisation: A_f(t, d) = sum_{i=0}^{d} I[f][t-i];
+ *   - samples before t = 0 are zero (the alternative addition rule for t1 < 0),
+ *     so outputs with t0 < dt are sums over the part of the path inside the record;
+ *   - the rows each sub-band needs are derived top-down from Nd.
+ *
+ * Layout: all device arrays are dense, row-major, time fastest:
+ *   forward input   [batch][Nf][Nt]   of the plan's input dtype
+ *   forward output  [batch][Nd][Nt]   of the plan's accumulation dtype
+ *   adjoint input   [batch][Nd][Nt]   accumulation dtype
+ *   adjoint output  [batch][Nf][Nt]   accumulation dtype
+ *
+ * Ownership: the caller owns every input, output and workspace buffer (device
+ * memory of the plan's device, e.g. tensors of a framework's allocator). The
+ * plan owns its host tables and one device table buffer, allocated by
+ * fdmt_plan() and released by fdmt_plan_destroy(). fdmt_forward() and
+ * fdmt_adjoint() allocate nothing, never synchronise the host, and enqueue
+ * their kernels on the given HIP stream (NULL = the null stream), so they are
+ * stream-ordered and may be captured into a HIP graph. A plan is immutable
+ * after creation and may be used from several threads and streams at once,
+ * each call with its own workspace.
+ *
+ * Errors: every call returns a status; nothing aborts or throws across the
+ * ABI. All argument checks happen before any launch, so a call that returns an
+ * error other than FDMT_E_DEVICE has enqueued nothing. fdmt_last_error()
+ * returns a thread-local description of the most recent failure.
+ */
+#ifndef FDMT_H_
+#define FDMT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdmt_plan_s *fdmt_plan_t;
+
+typedef enum {
+  FDMT_OK = 0,
+  FDMT_E_INVALID = 1,     /* null pointer, size out of range, f_min >= f_max, f_min <= 0, ... */
+  FDMT_E_UNSUPPORTED = 2, /* Nf not a power of two, unsupported dtype pair, host-only plan */
+  FDMT_E_NOMEM = 3,       /* host or device allocation failed inside fdmt_plan() */
+  FDMT_E_DEVICE = 4,      /* a HIP call or kernel launch failed */
+  FDMT_E_WORKSPACE = 5    /* workspace null or smaller than fdmt_workspace_bytes() */
+} fdmt_status_t;
+
+typedef enum {
+  FDMT_F32 = 0, /* IEEE binary32 */
+  FDMT_F16 = 1, /* IEEE binary16 (input only) */
+  FDMT_U8 = 2,  /* unsigned 8-bit integer (input only) */
+  FDMT_I32 = 3  /* signed 32-bit integer */
+} fdmt_dtype_t;
+
+/* Supported (in_dtype -> acc_dtype) pairs:
+ *   F32 -> F32, F16 -> F32, U8 -> F32   (FP32 accumulation; U8 -> F32 is exact
+ *                                         while every path sum stays below 2^24)
+ *   U8 -> I32, I32 -> I32                (integer path, exact barring int32 overflow)
+ * The adjoint always reads and writes the accumulation dtype. */
+
+#define FDMT_PLAN_HOST_ONLY 0x1u /* build the tables only; no device memory is touched
+                                    and forward/adjoint return FDMT_E_UNSUPPORTED */
+#define FDMT_PLAN_UNFUSED 0x2u   /* run one kernel per iteration (reference schedule,
+                                    same results; used to cross-check the fused one) */
+
+typedef struct {
+  int32_t in_dtype;  /* fdmt_dtype_t of the forward input */
+  int32_t acc_dtype; /* FDMT_F32 or FDMT_I32 */
+  int32_t reserved;  /* must be 0 */
+  uint32_t flags;    /* FDMT_PLAN_* bits */
+} fdmt_options_t;
+
+/* Build a plan: the delay tables of every iteration (Sec. 3: "this decision
+ * can be made prior to the computation") and the kernel schedule, then upload
+ * the tables to the current HIP device.
+ *   nf     channels, a power of two, 1 <= nf <= 65536
+ *   nt     samples per beam, 1 <= nt <= 2^31 - 1
+ *   nd     delay trials (output rows), 1 <= nd <= 65536
+ *   f_min, f_max  band edges in any one unit, 0 < f_min < f_max
+ *   opt    NULL = F32 -> F32, no flags
+ * On success *out holds the plan; on failure *out is NULL. */
+fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, double f_min,
+                        double f_max, const fdmt_options_t *opt);
+
+/* Device workspace (bytes) that fdmt_forward/fdmt_adjoint need for `batch`
+ * beams of the plan's Nt; 0 if the plan is NULL or batch < 1. The workspace
+ * must be 256-byte aligned; its contents on entry are irrelevant. */
+size_t fdmt_workspace_bytes(fdmt_plan_t p, int32_t batch);
+
+/* Forward transform (Algorithm 1) of `batch` independent beams.
+ * in  : device [batch][Nf][Nt], plan input dtype, read only
+ * out : device [batch][Nd][Nt], plan accumulation dtype, fully overwritten
+ * in and out must not overlap each other or the workspace. */
+fdmt_status_t fdmt_forward(fdmt_plan_t p, const void *in, void *out, int32_t batch, void *ws,
+                           size_t ws_bytes, void *hip_stream);
+
+/* Adjoint (transpose) of the forward map, i.e. the gradient of a scalar loss
+ * with respect to I given its gradient with respect to A: term by term the
+ * transpose of the Option-1 sums and of the addition rule, evaluated as a
+ * gather over precomputed inverse delay tables (no atomics; deterministic).
+ * grad_out : device [batch][Nd][Nt], accumulation dtype, read only
+ * grad_in  : device [batch][Nf][Nt], accumulation dtype, fully overwritten */
+fdmt_status_t fdmt_adjoint(fdmt_plan_t p, const void *grad_out, void *grad_in, int32_t batch,
+                           void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Host copy of one sub-band's delay table (for inspection and table tests).
+ * level 0: sub = channel, *n_rows = rows of its Option-1 partial sums, no
+ *          triples are written.
+ * level l in 1..log2(Nf): sub = sub-band index; for each row dt < *n_rows,
+ *          d_lo[dt] = t0 - t1, s[dt] = shift of the upper half, d_hi[dt] = t1 - t2,
+ *          written only if cap >= *n_rows (pointers may be NULL when cap = 0). */
+fdmt_status_t fdmt_plan_tables(fdmt_plan_t p, int32_t level, int32_t sub, int32_t *d_lo,
+                               int32_t *s, int32_t *d_hi, int32_t cap, int32_t *n_rows);
+
+/* Plan shape: *levels = log2(Nf); rows_per_level[l] (l = 0..levels, if not NULL
+ * and cap > levels) = total rows of iteration l's planes. */
+fdmt_status_t fdmt_plan_info(fdmt_plan_t p, int32_t *levels, int64_t *rows_per_level, int32_t cap);
+
+/* Release the plan and its device tables (must not be in use by queued work). NULL is a no-op. */
+fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p);
+
+/* Static description of a status code. */
+const char *fdmt_status_string(fdmt_status_t s);
+
+/* Thread-local detail of the last failed call on this thread ("" if none). */
+const char *fdmt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDMT_H_ */

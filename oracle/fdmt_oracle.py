@@ -10,7 +10,11 @@ of radio bursts with an unknown dispersion measure" (arXiv:1411.5373),
 Sec. 3 ("The FDMT Algorithm") and Algorithm 1, step by step, in plain NumPy:
 one vector add per (iteration, sub-band, delay) row, as in the paper's
 vectorised form (caption of Fig. 2). Integer inputs are summed in int64,
-floating inputs in float64 after an exact upcast.
+floating inputs in float64 after an exact upcast. An explicit `acc=np.float32`
+evaluates the same recursion in IEEE binary32 (one rounding per addition, in
+the order written here); the paper does not fix a precision, and every
+output's sum is a fixed tree of single additions, so this mode is the exact
+reference for a binary32 implementation of the same recursion.
 
 Notation. I[f][t]: input, channel 0 = lowest frequency, t contiguous.
 A_{f0}^{f2}(t0, dt): sum along the dispersion curve that enters the
@@ -133,17 +137,22 @@ def build_tables(nf, nd, f_min, f_max):
 # Forward transform (Algorithm 1)
 # ----------------------------------------------------------------------------
 
-def _acc_dtype(x):
+def _acc_dtype(x, acc=None):
+    """int64 for integer input, float64 for floating input, unless `acc` names
+    the accumulation type explicitly (np.float32: the same recursion evaluated
+    in IEEE binary32, one rounding per addition, in the order written here)."""
+    if acc is not None:
+        return np.dtype(acc).type
     return np.int64 if np.asarray(x).dtype.kind in "iub" else np.float64
 
 
-def initialize(img, tables):
+def initialize(img, tables, acc=None):
     """Option 1 (Sec. 3): A_f^{f+df}(t, dt) = sum_{i=0}^{dt} I(f, t - i) for
     dt = 0..rows[0][k]-1, with I = 0 before the record starts (readings R-init,
     R-copy). Built as the chain A(t, dt) = A(t, dt-1) + I(f, t - dt)."""
     img = np.asarray(img)
     nf, nt = img.shape
-    acc = _acc_dtype(img)
+    acc = _acc_dtype(img, acc)
     x = img.astype(acc)
     planes = []
     for k in range(nf):
@@ -180,25 +189,25 @@ def iterate(planes, tables, nt):
     return planes[0]
 
 
-def fdmt(img, f_min, f_max, nd, tables=None):
+def fdmt(img, f_min, f_max, nd, tables=None, acc=None):
     """A_{f_min}^{f_max}(t0, dt) for dt = 0..nd-1, t0 = 0..nt-1; shape [nd][nt]."""
     img = np.asarray(img)
     nf, nt = img.shape
     if tables is None:
         tables = build_tables(nf, nd, f_min, f_max)
-    return iterate(initialize(img, tables), tables, nt)
+    return iterate(initialize(img, tables, acc), tables, nt)
 
 
-def fdmt_batch(imgs, f_min, f_max, nd):
+def fdmt_batch(imgs, f_min, f_max, nd, acc=None):
     tables = build_tables(imgs.shape[-2], nd, f_min, f_max)
-    return np.stack([fdmt(x, f_min, f_max, nd, tables) for x in imgs])
+    return np.stack([fdmt(x, f_min, f_max, nd, tables, acc) for x in imgs])
 
 
 # ----------------------------------------------------------------------------
 # Adjoint (transpose of the linear map above, term by term)
 # ----------------------------------------------------------------------------
 
-def fdmt_adjoint(grad, f_min, f_max, nf, tables=None):
+def fdmt_adjoint(grad, f_min, f_max, nf, tables=None, acc=None):
     """Transpose of fdmt(): grad [nd][nt] -> [nf][nt].
 
     Each forward term out[dt][t0] += lower[d_lo][t0] becomes
@@ -210,7 +219,7 @@ def fdmt_adjoint(grad, f_min, f_max, nf, tables=None):
     nd, nt = grad.shape
     if tables is None:
         tables = build_tables(nf, nd, f_min, f_max)
-    acc = _acc_dtype(grad)
+    acc = _acc_dtype(grad, acc)
     planes = [grad.astype(acc)]
     for l in range(tables.levels, 0, -1):
         split_planes = []

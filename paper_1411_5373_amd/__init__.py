@@ -1,0 +1,8 @@
+"""MI355X-native Fast Dispersion Measure Transform (Zackay & Ofek, arXiv:1411.5373).
+
+The transform runs in libfdmt.so (hand-written HIP for gfx950); this package
+only marshals tensors and streams into its C ABI.
+"""
+from .binding import (EXPORTED, FDMTError, FDMTFunction, Plan, fdmt, fdmt_adjoint, fdmt_forward,
+                   fdmt_last_error, fdmt_plan, fdmt_plan_destroy, fdmt_plan_info,
+                   fdmt_plan_tables, fdmt_status_string, fdmt_workspace_bytes, library_path, load)

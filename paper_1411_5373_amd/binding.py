@@ -1,0 +1,231 @@
+"""Python binding of libfdmt.so (argument marshalling only).
+
+Every step of the transform runs in the HIP library; PyTorch supplies device
+memory (tensors, the workspace) and the current HIP stream. The functions
+carry the C ABI's names; `Plan` and `FDMTFunction` are thin tensor-level
+conveniences over them. If the library is not built this module raises on
+first use: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # imported first so the library binds to torch's HIP runtime
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfdmt.so")
+_lib = None
+
+FDMT_OK, FDMT_E_INVALID, FDMT_E_UNSUPPORTED, FDMT_E_NOMEM, FDMT_E_DEVICE, FDMT_E_WORKSPACE = range(6)
+FDMT_F32, FDMT_F16, FDMT_U8, FDMT_I32 = range(4)
+FDMT_PLAN_HOST_ONLY = 0x1
+FDMT_PLAN_UNFUSED = 0x2
+
+EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
+            "fdmt_plan_tables", "fdmt_plan_info", "fdmt_plan_destroy",
+            "fdmt_status_string", "fdmt_last_error")
+
+_TORCH_TO_CODE = {torch.float32: FDMT_F32, torch.float16: FDMT_F16,
+                  torch.uint8: FDMT_U8, torch.int32: FDMT_I32}
+_CODE_TO_TORCH = {v: k for k, v in _TORCH_TO_CODE.items()}
+
+
+class FDMTError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(message)
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("in_dtype", ctypes.c_int32), ("acc_dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load libfdmt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1411_5373_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    p_i32 = ctypes.POINTER(ctypes.c_int32)
+    lib.fdmt_plan.argtypes = [ctypes.POINTER(vp), i32, i64, i32, ctypes.c_double, ctypes.c_double,
+                              ctypes.POINTER(_Options)]
+    lib.fdmt_plan.restype = ctypes.c_int
+    lib.fdmt_workspace_bytes.argtypes = [vp, i32]
+    lib.fdmt_workspace_bytes.restype = sz
+    for name in ("fdmt_forward", "fdmt_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+        f.restype = ctypes.c_int
+    lib.fdmt_plan_tables.argtypes = [vp, i32, i32, p_i32, p_i32, p_i32, i32, p_i32]
+    lib.fdmt_plan_tables.restype = ctypes.c_int
+    lib.fdmt_plan_info.argtypes = [vp, p_i32, ctypes.POINTER(ctypes.c_int64), i32]
+    lib.fdmt_plan_info.restype = ctypes.c_int
+    lib.fdmt_plan_destroy.argtypes = [vp]
+    lib.fdmt_plan_destroy.restype = ctypes.c_int
+    lib.fdmt_status_string.argtypes = [ctypes.c_int]
+    lib.fdmt_status_string.restype = ctypes.c_char_p
+    lib.fdmt_last_error.argtypes = []
+    lib.fdmt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != FDMT_OK:
+        lib = load()
+        raise FDMTError(status, f"{what}: {lib.fdmt_status_string(status).decode()}: "
+                                f"{lib.fdmt_last_error().decode()}")
+
+
+# ----------------------------------------------------------------- C ABI names
+
+def fdmt_status_string(status):
+    return load().fdmt_status_string(int(status)).decode()
+
+
+def fdmt_last_error():
+    return load().fdmt_last_error().decode()
+
+
+def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0):
+    """Returns an opaque plan handle (int); raises FDMTError on failure."""
+    h = ctypes.c_void_p()
+    opt = _Options(int(in_dtype), int(acc_dtype), 0, int(flags))
+    _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
+                            ctypes.byref(opt)), "fdmt_plan")
+    return h.value
+
+
+def fdmt_workspace_bytes(plan, batch):
+    return int(load().fdmt_workspace_bytes(plan, int(batch)))
+
+
+def fdmt_forward(plan, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_forward(plan, in_ptr, out_ptr, int(batch), ws_ptr, int(ws_bytes), stream),
+           "fdmt_forward")
+
+
+def fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, batch, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, int(batch), ws_ptr, int(ws_bytes),
+                               stream), "fdmt_adjoint")
+
+
+def fdmt_plan_tables(plan, level, sub):
+    """Returns (d_lo, s, d_hi) as lists (empty for level 0) and the row count."""
+    n = ctypes.c_int32()
+    _check(load().fdmt_plan_tables(plan, int(level), int(sub), None, None, None, 0, ctypes.byref(n)),
+           "fdmt_plan_tables")
+    if level == 0:
+        return [], [], [], n.value
+    arr = ctypes.c_int32 * n.value
+    a, b, c = arr(), arr(), arr()
+    _check(load().fdmt_plan_tables(plan, int(level), int(sub), a, b, c, n.value, ctypes.byref(n)),
+           "fdmt_plan_tables")
+    return list(a), list(b), list(c), n.value
+
+
+def fdmt_plan_info(plan):
+    lv = ctypes.c_int32()
+    _check(load().fdmt_plan_info(plan, ctypes.byref(lv), None, 0), "fdmt_plan_info")
+    rows = (ctypes.c_int64 * (lv.value + 1))()
+    _check(load().fdmt_plan_info(plan, ctypes.byref(lv), rows, lv.value + 1), "fdmt_plan_info")
+    return lv.value, list(rows)
+
+
+def fdmt_plan_destroy(plan):
+    if plan:
+        _check(load().fdmt_plan_destroy(plan), "fdmt_plan_destroy")
+
+
+# ----------------------------------------------------------------- tensor layer
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """Owns one plan handle. forward/adjoint take and return device tensors
+    shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
+
+    def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
+                 host_only=False, unfused=False):
+        self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
+        self.f_min, self.f_max = float(f_min), float(f_max)
+        self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
+        flags = (FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0)
+        self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
+        self.handle = None
+        self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
+                                _TORCH_TO_CODE[acc_dtype], flags)
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.fdmt_plan_destroy(h)
+
+    def workspace_bytes(self, batch=1):
+        return fdmt_workspace_bytes(self.handle, batch)
+
+    def workspace(self, batch=1):
+        n = self.workspace_bytes(batch)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+
+    def _run(self, fn, x, out, rows_in, rows_out, dtype_in, dtype_out, ws):
+        if x.device != self.device:
+            raise ValueError(f"tensor on {x.device}, plan on {self.device}")
+        if x.dtype != dtype_in:
+            raise TypeError(f"expected {dtype_in}, got {x.dtype}")
+        if x.shape[-2:] != (rows_in, self.nt):
+            raise ValueError(f"expected [..., {rows_in}, {self.nt}], got {tuple(x.shape)}")
+        if x.dim() not in (2, 3):
+            raise ValueError("expected a 2-D or 3-D tensor")
+        x = x.contiguous()
+        batch = 1 if x.dim() == 2 else x.shape[0]
+        shape = (rows_out, self.nt) if x.dim() == 2 else (batch, rows_out, self.nt)
+        if out is None:
+            out = torch.empty(shape, dtype=dtype_out, device=self.device)
+        elif out.shape != shape or out.dtype != dtype_out or not out.is_contiguous():
+            raise ValueError("out has the wrong shape, dtype or layout")
+        if ws is None:
+            ws = self.workspace(batch)
+        fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch,
+           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(self.device))
+        return out
+
+    def forward(self, x, out=None, ws=None):
+        return self._run(fdmt_forward, x, out, self.nf, self.nd, self.in_dtype, self.acc_dtype, ws)
+
+    def adjoint(self, g, out=None, ws=None):
+        return self._run(fdmt_adjoint, g, out, self.nd, self.nf, self.acc_dtype, self.acc_dtype, ws)
+
+    def tables(self, level, sub):
+        return fdmt_plan_tables(self.handle, level, sub)
+
+    def info(self):
+        return fdmt_plan_info(self.handle)
+
+
+class FDMTFunction(torch.autograd.Function):
+    """y = FDMT(x); the backward pass is the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, x, plan):
+        ctx.plan = plan
+        return plan.forward(x)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        return ctx.plan.adjoint(grad_y.contiguous()), None
+
+
+def fdmt(x, plan):
+    return FDMTFunction.apply(x, plan)

@@ -1,0 +1,231 @@
+// C ABI of the FDMT library: argument validation, plan lifetime, table
+// upload and error reporting. See include/fdmt.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/fdmt.h"
+#include "fdmt_plan.h"
+
+struct fdmt_plan_s {
+  fdmt::Plan plan;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fdmt_status_t fail(fdmt_status_t s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+fdmt_status_t device_fail(hipError_t e, const char *where) {
+  return fail(FDMT_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool pair_supported(int in, int acc) {
+  if (acc == FDMT_F32) return in == FDMT_F32 || in == FDMT_F16 || in == FDMT_U8;
+  if (acc == FDMT_I32) return in == FDMT_U8 || in == FDMT_I32;
+  return false;
+}
+
+// Copies every table into one device allocation and records typed pointers.
+fdmt_status_t upload(fdmt::Plan &p) {
+  const fdmt::Tables &T = p.tab;
+  size_t bytes = 0;
+  auto reserve = [&](size_t n) {
+    size_t off = bytes;
+    bytes += fdmt::round_up(static_cast<int64_t>(n), 256);
+    return off;
+  };
+  size_t off_merge[32] = {}, off_adj[32] = {};
+  for (int l = 1; l <= T.levels; ++l) {
+    off_merge[l] = reserve(T.merge[l].size() * sizeof(fdmt::MergeRow));
+    off_adj[l] = reserve(T.adj[l].size() * sizeof(fdmt::AdjRow));
+  }
+  const size_t off_leaf_off = reserve(T.leaf_off.size() * sizeof(int32_t));
+  const size_t off_leaf_rows = reserve(T.leaf_rows.size() * sizeof(int32_t));
+
+  std::vector<unsigned char> host(bytes, 0);
+  for (int l = 1; l <= T.levels; ++l) {
+    std::memcpy(host.data() + off_merge[l], T.merge[l].data(), T.merge[l].size() * sizeof(fdmt::MergeRow));
+    std::memcpy(host.data() + off_adj[l], T.adj[l].data(), T.adj[l].size() * sizeof(fdmt::AdjRow));
+  }
+  std::memcpy(host.data() + off_leaf_off, T.leaf_off.data(), T.leaf_off.size() * sizeof(int32_t));
+  std::memcpy(host.data() + off_leaf_rows, T.leaf_rows.data(), T.leaf_rows.size() * sizeof(int32_t));
+
+  hipError_t e = hipGetDevice(&p.device);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  e = hipMalloc(&p.dbuf, bytes);
+  if (e != hipSuccess) {
+    p.dbuf = nullptr;
+    return fail(FDMT_E_NOMEM, std::string("hipMalloc of delay tables: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(p.dbuf, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(e, "hipMemcpy of delay tables");
+  auto *base = static_cast<unsigned char *>(p.dbuf);
+  for (int l = 1; l <= T.levels; ++l) {
+    p.dev.merge[l] = reinterpret_cast<const int4 *>(base + off_merge[l]);
+    p.dev.adj[l] = reinterpret_cast<const int4 *>(base + off_adj[l]);
+  }
+  p.dev.leaf_off = reinterpret_cast<const int32_t *>(base + off_leaf_off);
+  p.dev.leaf_rows = reinterpret_cast<const int32_t *>(base + off_leaf_rows);
+  return FDMT_OK;
+}
+
+fdmt_status_t check_call(fdmt_plan_t p, const void *a, const void *b, int32_t batch, void *ws,
+                         size_t ws_bytes) {
+  if (!p) return fail(FDMT_E_INVALID, "plan is NULL");
+  if (!a || !b) return fail(FDMT_E_INVALID, "input or output pointer is NULL");
+  if (a == b) return fail(FDMT_E_INVALID, "input and output alias");
+  if (batch < 1 || batch > 65535) return fail(FDMT_E_INVALID, "batch must be in [1, 65535]");
+  const size_t need = fdmt::workspace_bytes(p->plan, batch);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(FDMT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
+                                      std::to_string(ws ? ws_bytes : 0));
+  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+    return fail(FDMT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (p->plan.flags & FDMT_PLAN_HOST_ONLY)
+    return fail(FDMT_E_UNSUPPORTED, "plan was built with FDMT_PLAN_HOST_ONLY");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev != p->plan.device)
+    return fail(FDMT_E_INVALID, "current device differs from the plan's device");
+  return FDMT_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, double f_min,
+                        double f_max, const fdmt_options_t *opt) {
+  if (!out) return fail(FDMT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0};
+  if (opt) o = *opt;
+  if (nf < 1 || nf > 65536) return fail(FDMT_E_INVALID, "Nf must be in [1, 65536]");
+  if ((nf & (nf - 1)) != 0) return fail(FDMT_E_UNSUPPORTED, "Nf must be a power of two");
+  if (nt < 1 || nt > INT32_MAX) return fail(FDMT_E_INVALID, "Nt must be in [1, 2^31 - 1]");
+  if (nd < 1 || nd > 65536) return fail(FDMT_E_INVALID, "Nd must be in [1, 65536]");
+  if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
+    return fail(FDMT_E_INVALID, "need 0 < f_min < f_max (finite)");
+  if (o.reserved != 0) return fail(FDMT_E_INVALID, "options.reserved must be 0");
+  if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED))
+    return fail(FDMT_E_INVALID, "unknown option flag");
+  if (!pair_supported(o.in_dtype, o.acc_dtype))
+    return fail(FDMT_E_UNSUPPORTED, "unsupported (input, accumulation) dtype pair");
+
+  auto *h = new (std::nothrow) fdmt_plan_s;
+  if (!h) return fail(FDMT_E_NOMEM, "host allocation of the plan failed");
+  fdmt::Plan &p = h->plan;
+  try {
+    const std::string err = fdmt::build_tables(p.tab, nf, nd, f_min, f_max);
+    if (!err.empty()) {
+      delete h;
+      return fail(FDMT_E_INVALID, err);
+    }
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(FDMT_E_NOMEM, "host allocation of the delay tables failed");
+  }
+  p.nt = nt;
+  p.ntp = fdmt::round_up(nt, fdmt::kRowAlign);
+  p.in_dtype = o.in_dtype;
+  p.acc_dtype = o.acc_dtype;
+  p.flags = o.flags;
+  for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
+  if (!(o.flags & FDMT_PLAN_HOST_ONLY)) {
+    const fdmt_status_t s = upload(p);
+    if (s != FDMT_OK) {
+      if (p.dbuf) (void)hipFree(p.dbuf);
+      delete h;
+      return s;
+    }
+  }
+  *out = h;
+  return FDMT_OK;
+}
+
+size_t fdmt_workspace_bytes(fdmt_plan_t p, int32_t batch) {
+  if (!p || batch < 1) return 0;
+  return fdmt::workspace_bytes(p->plan, batch);
+}
+
+fdmt_status_t fdmt_forward(fdmt_plan_t p, const void *in, void *out, int32_t batch, void *ws,
+                           size_t ws_bytes, void *hip_stream) {
+  fdmt_status_t s = check_call(p, in, out, batch, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  hipError_t e = fdmt::launch_forward(p->plan, in, out, batch, ws, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "fdmt_forward launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_adjoint(fdmt_plan_t p, const void *grad_out, void *grad_in, int32_t batch,
+                           void *ws, size_t ws_bytes, void *hip_stream) {
+  fdmt_status_t s = check_call(p, grad_out, grad_in, batch, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  hipError_t e = fdmt::launch_adjoint(p->plan, grad_out, grad_in, batch, ws, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "fdmt_adjoint launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_plan_tables(fdmt_plan_t p, int32_t level, int32_t sub, int32_t *d_lo, int32_t *s,
+                               int32_t *d_hi, int32_t cap, int32_t *n_rows) {
+  if (!p || !n_rows) return fail(FDMT_E_INVALID, "plan or n_rows is NULL");
+  const fdmt::Tables &T = p->plan.tab;
+  if (level < 0 || level > T.levels) return fail(FDMT_E_INVALID, "level out of range");
+  if (sub < 0 || sub >= (T.nf >> level)) return fail(FDMT_E_INVALID, "sub-band out of range");
+  const int32_t n = T.rows[level][sub];
+  *n_rows = n;
+  if (level == 0 || cap <= 0) return FDMT_OK;
+  if (cap < n) return fail(FDMT_E_INVALID, "cap smaller than the row count");
+  if (!d_lo || !s || !d_hi) return fail(FDMT_E_INVALID, "table pointer is NULL");
+  const int64_t base = T.row_off[level][sub];
+  for (int32_t dt = 0; dt < n; ++dt) {
+    d_lo[dt] = T.d_lo[level][base + dt];
+    s[dt] = T.shift[level][base + dt];
+    d_hi[dt] = T.d_hi[level][base + dt];
+  }
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_plan_info(fdmt_plan_t p, int32_t *levels, int64_t *rows_per_level, int32_t cap) {
+  if (!p || !levels) return fail(FDMT_E_INVALID, "plan or levels is NULL");
+  const fdmt::Tables &T = p->plan.tab;
+  *levels = T.levels;
+  if (rows_per_level && cap > T.levels)
+    for (int l = 0; l <= T.levels; ++l) rows_per_level[l] = T.total[l];
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p) {
+  if (!p) return FDMT_OK;
+  fdmt_status_t s = FDMT_OK;
+  if (p->plan.dbuf) {
+    hipError_t e = hipFree(p->plan.dbuf);
+    if (e != hipSuccess) s = device_fail(e, "hipFree of delay tables");
+  }
+  delete p;
+  return s;
+}
+
+const char *fdmt_status_string(fdmt_status_t s) {
+  switch (s) {
+    case FDMT_OK: return "ok";
+    case FDMT_E_INVALID: return "invalid argument";
+    case FDMT_E_UNSUPPORTED: return "unsupported request";
+    case FDMT_E_NOMEM: return "out of memory";
+    case FDMT_E_DEVICE: return "device error";
+    case FDMT_E_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+const char *fdmt_last_error(void) { return g_last_error.c_str(); }
+
+} // extern "C"

@@ -1,0 +1,149 @@
+// Delay-table builder (host, IEEE float64, compiled without FP contraction).
+//
+// Per iteration l = 1..log2(Nf) and sub-band j, the merged band [f0, f2) is
+// split at its border frequency f1 (Sec. 3, addition rule; the border reading
+// is the one Sec. 3.2 gives for unequal sub-bands). Its row dt reads
+//   the lower half [f0, f1) at row d_lo = t0 - t1 = round(dt * C_{f2,f0}) and
+//   the upper half [f1, f2) at row d_hi = t1 - t2 = dt - d_lo, shifted by d_lo,
+// with C_{f2,f0} from Eq. (Cf2f0). Rows are counted top-down from the Nd
+// output rows: a child needs exactly the rows its parent reads, which is the
+// discrete counterpart of the dt_max(i, f0) estimate of Algorithm 1.
+#include "fdmt_tables.h"
+
+#include <cmath>
+
+namespace fdmt {
+
+namespace {
+
+double inv_square(double f) { return 1.0 / (f * f); }
+
+// Eq. (Cf2f0), evaluated exactly in this order.
+double merge_coefficient(double f0, double f1, double f2) {
+  const double num = inv_square(f1) - inv_square(f0);
+  const double den = inv_square(f2) - inv_square(f0);
+  return num / den;
+}
+
+// Nearest integer, ties upward; x >= 0 here.
+int32_t round_half_up(double x) { return static_cast<int32_t>(std::floor(x + 0.5)); }
+
+} // namespace
+
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max) {
+  if (nf < 1 || (nf & (nf - 1)) != 0) return "Nf must be a power of two";
+  if (nd < 1) return "Nd must be >= 1";
+  if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
+    return "need 0 < f_min < f_max (finite)";
+  int levels = 0;
+  while ((1 << levels) < nf) ++levels;
+
+  t = Tables();
+  t.nf = nf;
+  t.nd = nd;
+  t.levels = levels;
+  t.f_min = f_min;
+  t.f_max = f_max;
+
+  const double df = (f_max - f_min) / nf;
+  std::vector<double> edge(nf + 1);
+  for (int k = 0; k <= nf; ++k) edge[k] = f_min + static_cast<double>(k) * df;
+
+  t.rows.assign(levels + 1, {});
+  t.d_lo.assign(levels + 1, {});
+  t.d_hi.assign(levels + 1, {});
+  t.shift.assign(levels + 1, {});
+  t.rows[levels] = {nd};
+
+  // Top-down: split every sub-band of iteration l, which fixes the row counts
+  // of iteration l - 1.
+  std::vector<std::vector<std::vector<int32_t>>> lo_of(levels + 1), hi_of(levels + 1);
+  for (int l = levels; l >= 1; --l) {
+    const int nsub = nf >> l;
+    t.rows[l - 1].assign(2 * nsub, 0);
+    lo_of[l].resize(nsub);
+    hi_of[l].resize(nsub);
+    for (int j = 0; j < nsub; ++j) {
+      const double f0 = edge[static_cast<size_t>(j) << l];
+      const double f1 = edge[static_cast<size_t>(2 * j + 1) << (l - 1)];
+      const double f2 = edge[static_cast<size_t>(j + 1) << l];
+      const double c = merge_coefficient(f0, f1, f2);
+      const int32_t n = t.rows[l][j];
+      auto &lo = lo_of[l][j];
+      auto &hi = hi_of[l][j];
+      lo.resize(n);
+      hi.resize(n);
+      for (int32_t dt = 0; dt < n; ++dt) {
+        const int32_t d = round_half_up(static_cast<double>(dt) * c);
+        if (d < 0 || d > dt) return "merge coefficient outside [0, 1]";
+        lo[dt] = d;
+        hi[dt] = dt - d;
+      }
+      t.rows[l - 1][2 * j] = lo[n - 1] + 1;
+      t.rows[l - 1][2 * j + 1] = hi[n - 1] + 1;
+    }
+  }
+
+  // Row offsets of every plane.
+  t.row_off.assign(levels + 1, {});
+  t.total.assign(levels + 1, 0);
+  for (int l = 0; l <= levels; ++l) {
+    int64_t acc = 0;
+    t.row_off[l].resize(t.rows[l].size());
+    for (size_t j = 0; j < t.rows[l].size(); ++j) {
+      t.row_off[l][j] = acc;
+      acc += t.rows[l][j];
+    }
+    t.total[l] = acc;
+    if (acc > INT32_MAX) return "plane too tall";
+  }
+
+  // Flat per-row tables.
+  t.merge.assign(levels + 1, {});
+  t.adj.assign(levels + 1, {});
+  for (int l = 1; l <= levels; ++l) {
+    const int nsub = nf >> l;
+    auto &m = t.merge[l];
+    m.resize(t.total[l]);
+    t.d_lo[l].resize(t.total[l]);
+    t.d_hi[l].resize(t.total[l]);
+    t.shift[l].resize(t.total[l]);
+    auto &a = t.adj[l];
+    a.assign(t.total[l - 1], AdjRow{0, 0, 0, 0});
+    for (int j = 0; j < nsub; ++j) {
+      const int64_t base = t.row_off[l][j];
+      const int64_t lo_base = t.row_off[l - 1][2 * j];
+      const int64_t hi_base = t.row_off[l - 1][2 * j + 1];
+      for (int32_t dt = 0; dt < t.rows[l][j]; ++dt) {
+        const int32_t dl = lo_of[l][j][dt], dh = hi_of[l][j][dt];
+        const int64_t r = base + dt;
+        m[r] = MergeRow{static_cast<int32_t>(lo_base + dl), static_cast<int32_t>(hi_base + dh), dl, j};
+        t.d_lo[l][r] = dl;
+        t.d_hi[l][r] = dh;
+        t.shift[l][r] = dl;
+        // Inverse maps: the parents of a child row are consecutive because
+        // both d_lo and d_hi are non-decreasing in dt.
+        AdjRow &al = a[lo_base + dl];
+        if (al.count == 0) { al.first = static_cast<int32_t>(r); al.upper = 0; }
+        if (al.first + al.count != r) return "lower-half inverse map not contiguous";
+        ++al.count;
+        AdjRow &ah = a[hi_base + dh];
+        if (ah.count == 0) { ah.first = static_cast<int32_t>(r); ah.upper = 1; }
+        if (ah.first + ah.count != r) return "upper-half inverse map not contiguous";
+        ++ah.count;
+      }
+    }
+    for (const AdjRow &x : a)
+      if (x.count == 0) return "child row with no parent";
+  }
+
+  t.leaf_off.resize(nf);
+  t.leaf_rows.resize(nf);
+  for (int k = 0; k < nf; ++k) {
+    t.leaf_off[k] = static_cast<int32_t>(t.row_off[0][k]);
+    t.leaf_rows[k] = t.rows[0][k];
+  }
+  return "";
+}
+
+} // namespace fdmt

@@ -1,0 +1,48 @@
+// Host-side delay tables of the FDMT (Zackay & Ofek, Sec. 3, Eq. Cf2f0 and
+// Algorithm 1) in the flat, device-friendly form the kernels consume.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fdmt {
+
+// One output row of an iteration: out[t] = plane[lo][t] + plane[hi][t - s]
+// (the second term only for t >= s). lo/hi are rows of the previous
+// iteration's plane (all sub-bands concatenated), s the upper half's shift.
+struct MergeRow {
+  int32_t lo, hi, s, sub;
+};
+
+// One row of the previous iteration's plane seen from the adjoint: it is the
+// lower (upper = 0) or upper (upper = 1) half of `count` consecutive output
+// rows starting at `first` in this iteration's plane.
+struct AdjRow {
+  int32_t first, count, upper, pad;
+};
+
+struct Tables {
+  int nf = 0, nd = 0, levels = 0;
+  double f_min = 0, f_max = 0;
+  // rows[l][j]: dt rows of sub-band j after iteration l (l = 0: channel j's
+  // Option-1 partial sums; l = levels: the single output sub-band, nd rows).
+  std::vector<std::vector<int32_t>> rows;
+  // first row of sub-band j inside iteration l's plane
+  std::vector<std::vector<int64_t>> row_off;
+  // total rows of iteration l's plane
+  std::vector<int64_t> total;
+  // per iteration l >= 1: the sub-band delays of each plane row
+  std::vector<std::vector<int32_t>> d_lo, d_hi, shift;
+  // per iteration l >= 1: one MergeRow per row of plane l
+  std::vector<std::vector<MergeRow>> merge;
+  // per iteration l >= 1: one AdjRow per row of plane l - 1
+  std::vector<std::vector<AdjRow>> adj;
+  // per channel: first row of its partial sums in plane 0 and their count
+  std::vector<int32_t> leaf_off, leaf_rows;
+};
+
+// Builds every table. Returns "" on success or a description of the problem.
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max);
+
+} // namespace fdmt

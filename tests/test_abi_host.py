@@ -1,0 +1,142 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads and exports
+every function include/fdmt.h declares, the C++ delay tables equal the
+oracle's element by element, and every documented error status is returned
+before anything is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from oracle import build_tables
+
+import paper_1411_5373_amd as F
+from paper_1411_5373_amd import binding as B
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "fdmt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdmt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.load()
+    names = _declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(F.EXPORTED)
+
+
+def _host_plan(nf, nd, f_min, f_max, nt=64, **kw):
+    return F.Plan(nf, nt, nd, f_min, f_max, host_only=True, **kw)
+
+
+@pytest.mark.parametrize("nf,nd,band", [
+    (1, 7, (1.2, 1.6)), (2, 3, (1.0, 2.0)), (64, 64, (1.2, 1.6)), (1024, 1024, (1.2, 1.6)),
+    (4096, 2048, (1.2, 1.6)), (1024, 512, (1.2, 1.6)), (1024, 1024, (0.4, 0.8)),
+    (32, 32, (0.4, 0.8)), (256, 1000, (0.11, 0.19)), (8192, 300, (1.0, 1.5)),
+])
+def test_tables_match_oracle(nf, nd, band):
+    ref = build_tables(nf, nd, *band)
+    p = _host_plan(nf, nd, *band)
+    levels, rows = p.info()
+    assert levels == ref.levels
+    assert rows == [sum(r) for r in ref.rows]
+    for k in range(nf):
+        assert p.tables(0, k)[3] == ref.rows[0][k]
+    for l in range(1, levels + 1):
+        for j in range(nf >> l):
+            d_lo, s, d_hi, n = p.tables(l, j)
+            assert n == ref.rows[l][j]
+            assert list(zip(d_lo, s, d_hi)) == ref.split[l][j], (l, j)
+
+
+def test_random_bands_match_oracle():
+    import numpy as np
+    rng = np.random.default_rng(99)
+    for _ in range(20):
+        nf = int(2 ** rng.integers(0, 11))
+        nd = int(rng.integers(1, 2000))
+        f_min = float(rng.uniform(0.05, 3.0))
+        f_max = f_min * float(rng.uniform(1.01, 4.0))
+        ref = build_tables(nf, nd, f_min, f_max)
+        p = _host_plan(nf, nd, f_min, f_max)
+        for l in range(1, ref.levels + 1):
+            for j in range(0, nf >> l, max(1, (nf >> l) // 8)):
+                d_lo, s, d_hi, _ = p.tables(l, j)
+                assert list(zip(d_lo, s, d_hi)) == ref.split[l][j]
+
+
+@pytest.mark.parametrize("args,status", [
+    ((3, 64, 8, 1.2, 1.6), B.FDMT_E_UNSUPPORTED),     # Nf not a power of two
+    ((0, 64, 8, 1.2, 1.6), B.FDMT_E_INVALID),
+    ((131072, 64, 8, 1.2, 1.6), B.FDMT_E_INVALID),
+    ((8, 0, 8, 1.2, 1.6), B.FDMT_E_INVALID),          # Nt < 1
+    ((8, 64, 0, 1.2, 1.6), B.FDMT_E_INVALID),         # Nd < 1
+    ((8, 64, 8, 1.6, 1.2), B.FDMT_E_INVALID),         # f_min >= f_max
+    ((8, 64, 8, 1.2, 1.2), B.FDMT_E_INVALID),
+    ((8, 64, 8, 0.0, 1.2), B.FDMT_E_INVALID),         # f_min <= 0
+    ((8, 64, 8, -1.0, 1.2), B.FDMT_E_INVALID),
+    ((8, 64, 8, 1.2, float("inf")), B.FDMT_E_INVALID),
+    ((8, 64, 8, float("nan"), 1.2), B.FDMT_E_INVALID),
+])
+def test_plan_argument_errors(args, status):
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_plan(*args, flags=B.FDMT_PLAN_HOST_ONLY)
+    assert e.value.status == status
+    assert F.fdmt_last_error() != ""
+
+
+@pytest.mark.parametrize("in_dt,acc_dt", [(B.FDMT_F16, B.FDMT_I32), (B.FDMT_F32, B.FDMT_I32),
+                                          (B.FDMT_I32, B.FDMT_F32), (B.FDMT_F32, B.FDMT_F16), (7, 0)])
+def test_unsupported_dtype_pairs(in_dt, acc_dt):
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_plan(8, 64, 8, 1.2, 1.6, in_dt, acc_dt, B.FDMT_PLAN_HOST_ONLY)
+    assert e.value.status == B.FDMT_E_UNSUPPORTED
+
+
+def test_unknown_flag_rejected():
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_plan(8, 64, 8, 1.2, 1.6, flags=0x80 | B.FDMT_PLAN_HOST_ONLY)
+    assert e.value.status == B.FDMT_E_INVALID
+
+
+def test_call_argument_errors_before_launch():
+    """Fake (never dereferenced) pointers: every check fails before any launch."""
+    lib = F.load()
+    p = _host_plan(64, 64, 1.2, 1.6, nt=1000)
+    h = p.handle
+    need = F.fdmt_workspace_bytes(h, 2)
+    assert need == 2 * 2 * 127 * 1024 * 4  # two planes of the tallest (127-row) plane, padded Nt
+    assert F.fdmt_workspace_bytes(h, 0) == 0 and F.fdmt_workspace_bytes(None, 1) == 0
+    x, y, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000)
+    for fn in (lib.fdmt_forward, lib.fdmt_adjoint):
+        assert fn(None, x, y, 1, ws, need, None) == B.FDMT_E_INVALID
+        assert fn(h, None, y, 1, ws, need, None) == B.FDMT_E_INVALID
+        assert fn(h, x, None, 1, ws, need, None) == B.FDMT_E_INVALID
+        assert fn(h, x, x, 1, ws, need, None) == B.FDMT_E_INVALID
+        assert fn(h, x, y, 0, ws, need, None) == B.FDMT_E_INVALID
+        assert fn(h, x, y, 2, None, need, None) == B.FDMT_E_WORKSPACE
+        assert fn(h, x, y, 2, ws, need - 1, None) == B.FDMT_E_WORKSPACE
+        assert fn(h, x, y, 2, ctypes.c_void_p(0x100010), need, None) == B.FDMT_E_WORKSPACE
+        assert fn(h, x, y, 2, ws, need, None) == B.FDMT_E_UNSUPPORTED  # host-only plan
+
+
+def test_single_channel_needs_no_workspace():
+    p = _host_plan(1, 10, 1.2, 1.6, nt=100)
+    assert p.workspace_bytes(4) == 0
+
+
+def test_table_query_errors():
+    p = _host_plan(8, 8, 1.2, 1.6)
+    with pytest.raises(F.FDMTError):
+        p.tables(4, 0)
+    with pytest.raises(F.FDMTError):
+        p.tables(1, 4)
+    with pytest.raises(F.FDMTError):
+        p.tables(-1, 0)
+    assert F.fdmt_status_string(B.FDMT_E_WORKSPACE).startswith("workspace")
+    assert B.fdmt_plan_destroy(None) is None

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar:
+  * integer inputs: bit-exact against the int64 oracle (int32 accumulation, and
+    FP32 accumulation of uint8 while every path sum is below 2^24);
+  * floating inputs: bit-exact against the oracle's binary32 evaluation of the
+    same recursion, and against the float64 oracle every element inside the
+    rigorous tree-summation bound gamma_D * sum|terms| (tests/numerics.py), with
+    RMS(error)/RMS(output) <= 1e-5; max|error|/RMS(output) is printed."""
+import numpy as np
+import pytest
+
+import workloads as W
+from numerics import adjoint_bound, forward_bound, rel_to_rms, rms_ratio
+from oracle import build_tables, fdmt as ofdmt, fdmt_adjoint as oadj, brute_point, brute_row
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1411_5373_amd as F  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+REL_TOL = 1e-5
+
+SHAPES = [  # nf, nt, nd, band
+    (1, 100, 7, (1.2, 1.6)),
+    (2, 37, 5, (1.0, 2.0)),
+    (8, 1000, 12, (1.2, 1.6)),
+    (32, 50, 64, (0.4, 0.8)),        # Nt < Nd: every output is a partial path
+    (64, 1024, 64, (1.2, 1.6)),      # c1 shape
+    (64, 1030, 100, (1.2, 1.6)),     # ragged time tail, Nd > Nf
+    (256, 3001, 300, (1.2, 1.6)),
+    (512, 2048, 96, (0.4, 0.8)),     # Nd << Nf
+]
+
+
+def _rel(gpu, ref):
+    return rel_to_rms(gpu, ref)
+
+
+def check_forward_float(y, x, band, nd, tag=""):
+    """y: GPU output (float32); x: the input values (exactly representable in f32)."""
+    x32 = np.asarray(x, dtype=np.float32)
+    np.testing.assert_array_equal(y, ofdmt(x32, band[0], band[1], nd, acc=np.float32))
+    ref = ofdmt(x32.astype(np.float64), band[0], band[1], nd)
+    assert np.all(np.abs(y.astype(np.float64) - ref) <= forward_bound(x32, band[0], band[1], nd))
+    assert rms_ratio(y, ref) <= REL_TOL
+    print(f"  {tag} max|err|/RMS = {rel_to_rms(y, ref):.3e}, RMS(err)/RMS = {rms_ratio(y, ref):.3e}")
+
+
+def check_adjoint_float(xb, g, band, nf, tag=""):
+    g32 = np.asarray(g, dtype=np.float32)
+    np.testing.assert_array_equal(xb, oadj(g32, band[0], band[1], nf, acc=np.float32))
+    ref = oadj(g32.astype(np.float64), band[0], band[1], nf)
+    assert np.all(np.abs(xb.astype(np.float64) - ref) <= adjoint_bound(g32, band[0], band[1], nf))
+    assert rms_ratio(xb, ref) <= REL_TOL
+    print(f"  {tag} adjoint max|err|/RMS = {rel_to_rms(xb, ref):.3e}")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", SHAPES)
+@pytest.mark.parametrize("unfused", [False, True])
+def test_forward_f32(nf, nt, nd, band, unfused):
+    print(f"forward f32 nf={nf} nt={nt} nd={nd} unfused={unfused}", flush=True)
+    x = W.random_input((nf, nt), np.float32, seed=nf * 31 + nt)
+    p = F.Plan(nf, nt, nd, *band, unfused=unfused)
+    y = p.forward(_dev(x)).cpu().numpy()
+    check_forward_float(y, x, band, nd)
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", SHAPES)
+@pytest.mark.parametrize("in_dtype,acc_dtype", [(torch.uint8, torch.int32), (torch.int32, torch.int32),
+                                                (torch.uint8, torch.float32)])
+def test_forward_integer_exact(nf, nt, nd, band, in_dtype, acc_dtype):
+    print(f"forward {in_dtype}->{acc_dtype} nf={nf} nt={nt} nd={nd}", flush=True)
+    npdt = np.uint8 if in_dtype == torch.uint8 else np.int32
+    lo, hi = (0, 255) if npdt == np.uint8 else (-100000, 100000)
+    x = W.random_input((nf, nt), npdt, seed=nf + nt + nd, lo=lo, hi=hi)
+    p = F.Plan(nf, nt, nd, *band, in_dtype=in_dtype, acc_dtype=acc_dtype)
+    y = p.forward(_dev(x)).cpu().numpy()
+    ref = ofdmt(x.astype(np.int64), *band, nd)
+    np.testing.assert_array_equal(y.astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", SHAPES[:6])
+def test_forward_f16(nf, nt, nd, band):
+    x = W.random_input((nf, nt), np.float16, seed=7 + nf)
+    p = F.Plan(nf, nt, nd, *band, in_dtype=torch.float16)
+    y = p.forward(_dev(x)).cpu().numpy()
+    check_forward_float(y, x, band, nd, "f16")
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", SHAPES)
+@pytest.mark.parametrize("unfused", [False, True])
+def test_adjoint_f32(nf, nt, nd, band, unfused):
+    print(f"adjoint f32 nf={nf} nt={nt} nd={nd} unfused={unfused}", flush=True)
+    g = W.random_input((nd, nt), np.float32, seed=nd * 17 + nt)
+    p = F.Plan(nf, nt, nd, *band, unfused=unfused)
+    xb = p.adjoint(_dev(g)).cpu().numpy()
+    check_adjoint_float(xb, g, band, nf)
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", SHAPES)
+def test_adjoint_int32_exact(nf, nt, nd, band):
+    g = W.random_input((nd, nt), np.int32, seed=nd + 5, lo=-1000, hi=1000)
+    p = F.Plan(nf, nt, nd, *band, in_dtype=torch.int32, acc_dtype=torch.int32)
+    xb = p.adjoint(_dev(g)).cpu().numpy()
+    np.testing.assert_array_equal(xb.astype(np.int64), oadj(g.astype(np.int64), *band, nf))
+
+
+def test_dot_product_gpu_f32():
+    nf, nt, nd, band = 256, 4096, 256, (1.2, 1.6)
+    p = F.Plan(nf, nt, nd, *band)
+    x = torch.randn(nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(1))
+    y = torch.randn(nd, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(2))
+    ax, aty = p.forward(x), p.adjoint(y)
+    lhs = float((ax.double() * y.double()).sum())
+    rhs = float((x.double() * aty.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(ax.double().norm()) * float(y.double().norm())
+
+
+def test_batch_equals_per_beam_bitwise():
+    nf, nt, nd, band = 128, 2000, 150, (1.2, 1.6)
+    p = F.Plan(nf, nt, nd, *band)
+    x = torch.randn(3, nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
+    yb = p.forward(x)
+    for b in range(3):
+        assert torch.equal(yb[b], p.forward(x[b].contiguous()))
+    g = torch.randn(3, nd, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(4))
+    gb = p.adjoint(g)
+    for b in range(3):
+        assert torch.equal(gb[b], p.adjoint(g[b].contiguous()))
+
+
+def test_deterministic_bitwise():
+    nf, nt, nd, band = 1024, 8192, 1024, (1.2, 1.6)
+    p = F.Plan(nf, nt, nd, *band)
+    x = torch.randn(nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(5))
+    assert torch.equal(p.forward(x), p.forward(x))
+    g = torch.randn(nd, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(6))
+    assert torch.equal(p.adjoint(g), p.adjoint(g))
+
+
+def test_fused_equals_unfused():
+    nf, nt, nd, band = 1024, 5000, 700, (1.2, 1.6)
+    x = torch.randint(0, 256, (nf, nt), device=DEV, dtype=torch.uint8,
+                      generator=torch.Generator(DEV).manual_seed(7))
+    a = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32)
+    b = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, unfused=True)
+    assert torch.equal(a.forward(x), b.forward(x))
+    g = torch.randint(-50, 50, (nd, nt), device=DEV, dtype=torch.int32,
+                      generator=torch.Generator(DEV).manual_seed(8))
+    assert torch.equal(a.adjoint(g), b.adjoint(g))
+
+
+def test_c1_workload():
+    img, pulses = W.make_c1()
+    w = W.WORKLOADS["c1"]
+    p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max)
+    y = p.forward(_dev(img)).cpu().numpy()
+    check_forward_float(y, img, (w.f_min, w.f_max), w.nd, "c1")
+    dt, t_arr, _ = pulses[0]
+    i, j = np.unravel_index(np.argmax(y), y.shape)
+    assert abs(i - dt) <= 2 and abs(j - t_arr) <= 2
+
+
+def test_c2_workload():
+    img, pulses = W.make_c2()
+    w = W.WORKLOADS["c2"]
+    p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max)
+    y = p.forward(_dev(img)).cpu().numpy()
+    check_forward_float(y, img, (w.f_min, w.f_max), w.nd, "c2")
+
+
+def test_c3_full_size_sampled():
+    """Full c3 shape (Nf=4096, Nt=65536, Nd=2048), uint8 input: int32 and FP32
+    accumulation are both bit-exact against the oracle's path sums at sampled
+    outputs and whole sampled rows; row 0 equals the channel sum everywhere."""
+    w = W.WORKLOADS["c3"]
+    u8, f16, pulses = W.make_c3()
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    x = _dev(u8)
+    for acc in (torch.int32, torch.float32):
+        print(f"c3 full u8 -> {acc}", flush=True)
+        p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=acc)
+        y = p.forward(x)
+        torch.cuda.synchronize()
+        y = y.cpu().numpy()
+        np.testing.assert_array_equal(y[0].astype(np.int64), u8.astype(np.int64).sum(axis=0))
+        rng = np.random.default_rng(3)
+        for dt in [1, 777, w.nd - 1]:
+            np.testing.assert_array_equal(y[dt].astype(np.int64), brute_row(u8, tab, dt))
+        for _ in range(40):
+            dt, t0 = int(rng.integers(w.nd)), int(rng.integers(w.nt))
+            assert int(y[dt, t0]) == brute_point(u8, tab, dt, t0)
+        del y, p
+    print("c3 full f16", flush=True)
+    p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.float16)
+    y = p.forward(_dev(f16)).cpu().numpy()
+    xf = f16.astype(np.float64)
+    bound_tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    depth = bound_tab.levels + max(bound_tab.rows[0]) - 1
+    gamma = depth * 2.0 ** -24 / (1 - depth * 2.0 ** -24)
+    for dt in [0, 1000, w.nd - 1]:
+        ref = brute_row(xf, tab, dt)
+        assert np.all(np.abs(y[dt] - ref) <= gamma * brute_row(np.abs(xf), tab, dt))
+        print(f"  c3 f16 row {dt}: max|err|/RMS = {_rel(y[dt], ref):.3e}")
+
+
+def test_autograd_function():
+    """loss = logsumexp over each beam's DM-time plane (the differentiable
+    workload's loss on its Nf=32, Nt=256, Nd=32 slice). The gradient autograd
+    returns is the hand-written adjoint applied to the exact grad_y it received
+    (bit-exact against the binary32 oracle adjoint) and agrees with the float64
+    gradient A^T softmax(Ax)."""
+    nf, nt, nd, band = 32, 256, 32, (0.4, 0.8)
+    x = W.make_c5(batch=2, nf=nf, nt=nt)
+    p = F.Plan(nf, nt, nd, *band)
+    xt = _dev(x).requires_grad_(True)
+    y = F.fdmt(xt, p)
+    seen = {}
+    y.register_hook(lambda g: seen.setdefault("g", g.detach().clone()))
+    loss = torch.logsumexp(y.reshape(2, -1), dim=1).sum()
+    loss.backward()
+    gy = seen["g"].cpu().numpy()
+    for b in range(2):
+        np.testing.assert_array_equal(xt.grad[b].cpu().numpy(), oadj(gy[b], *band, nf, acc=np.float32))
+        ax = ofdmt(x[b].astype(np.float64), *band, nd)
+        pr = np.exp(ax - ax.max())
+        pr /= pr.sum()
+        ref = oadj(pr, *band, nf)
+        assert rms_ratio(xt.grad[b].cpu().numpy(), ref) <= REL_TOL
+
+
+def test_side_stream():
+    nf, nt, nd, band = 64, 1024, 64, (1.2, 1.6)
+    p = F.Plan(nf, nt, nd, *band)
+    x = torch.randn(nf, nt, device=DEV)
+    ref = p.forward(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        y = p.forward(x)
+    s.synchronize()
+    assert torch.equal(y, ref)

@@ -292,3 +292,35 @@ def test_adjoint_finite_differences_fp64():
         e[k, t] = 1.0
         fd = (_lse(fdmt(x + h * e, *band, nd)) - _lse(fdmt(x - h * e, *band, nd))) / (2 * h)
         assert abs(fd - grad[k, t]) <= 1e-6 * gmax
+
+
+# ---------------------------------------------------------------- binary32 mode
+
+def test_binary32_mode_exact_on_representable_data():
+    """With small integers every partial sum is exactly representable in binary32,
+    so the binary32 recursion must reproduce the int64 result exactly."""
+    x = _rng(21).integers(-100, 100, size=(64, 300))
+    ref = fdmt(x, 1.2, 1.6, 64)
+    got = fdmt(x.astype(np.float32), 1.2, 1.6, 64, acc=np.float32)
+    assert got.dtype == np.float32
+    np.testing.assert_array_equal(got.astype(np.int64), ref)
+    g = _rng(22).integers(-100, 100, size=(64, 300))
+    np.testing.assert_array_equal(
+        fdmt_adjoint(g.astype(np.float32), 1.2, 1.6, 64, acc=np.float32).astype(np.int64),
+        fdmt_adjoint(g, 1.2, 1.6, 64))
+
+
+def test_binary32_mode_within_rounding_bound():
+    """binary32 results stay inside the first-order tree-summation bound of the
+    float64 result, and are not identical to it (so rounding really happens)."""
+    from numerics import adjoint_bound, forward_bound
+    x = W.random_input((128, 700), np.float32, seed=23)
+    x[:, 300] += 40.0
+    ref = fdmt(x.astype(np.float64), 0.4, 0.8, 200)
+    got = fdmt(x, 0.4, 0.8, 200, acc=np.float32)
+    assert np.all(np.abs(got - ref) <= forward_bound(x, 0.4, 0.8, 200))
+    assert np.any(got != ref)
+    g = W.random_input((200, 700), np.float32, seed=24)
+    ref_a = fdmt_adjoint(g.astype(np.float64), 0.4, 0.8, 128)
+    got_a = fdmt_adjoint(g, 0.4, 0.8, 128, acc=np.float32)
+    assert np.all(np.abs(got_a - ref_a) <= adjoint_bound(g, 0.4, 0.8, 128))
