@@ -80,11 +80,23 @@ typedef enum {
 #define FDMT_PLAN_UNFUSED 0x2u   /* run one kernel per iteration (reference schedule,
                                     same results; used to cross-check the fused one) */
 
+/* Options of a plan. Zero in any schedule field selects the built-in default;
+ * schedule fields change only the kernel schedule, never the results. */
 typedef struct {
-  int32_t in_dtype;  /* fdmt_dtype_t of the forward input */
-  int32_t acc_dtype; /* FDMT_F32 or FDMT_I32 */
-  int32_t reserved;  /* must be 0 */
-  uint32_t flags;    /* FDMT_PLAN_* bits */
+  int32_t in_dtype;       /* fdmt_dtype_t of the forward input */
+  int32_t acc_dtype;      /* FDMT_F32 or FDMT_I32 */
+  uint32_t flags;         /* FDMT_PLAN_* bits */
+  int32_t first_levels;   /* iterations fused with the initialisation, 1..8 */
+  int32_t later_levels;   /* iterations per later fused pass, 1..8 */
+  int32_t tile;           /* output samples per work block, 64..8192, multiple of 64 */
+  int32_t lds_kib;        /* LDS budget per work block, 16..160 KiB */
+  int32_t max_block_rows; /* cap on the output rows of one work block, 1..4096 */
+  int32_t first_kernel;   /* kernel form of the first pass: 1 staged gather,
+                             2 level-by-level merges in LDS (0 = default: 2) */
+  int32_t later_kernel;   /* kernel form of later passes: 1 staged gather, 2 level-by-level
+                             merges in LDS, 3 gather through the caches (0 = default: 3) */
+  int32_t stream_tiles;   /* time tiles one staged-gather workgroup streams over, 1..65535 */
+  int32_t gather_rows;    /* output rows per cache-gather workgroup: 1, 2, 4, 8 or 16 */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 3: "this decision
@@ -119,6 +131,34 @@ fdmt_status_t fdmt_forward(fdmt_plan_t p, const void *in, void *out, int32_t bat
  * grad_in  : device [batch][Nf][Nt], accumulation dtype, fully overwritten */
 fdmt_status_t fdmt_adjoint(fdmt_plan_t p, const void *grad_out, void *grad_in, int32_t batch,
                            void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Kernel steps. A transform is a fixed sequence of kernel launches ("steps");
+ * running steps 0 .. count-1 in order with the same arguments and workspace is
+ * exactly one fdmt_forward() (adjoint = 0) or fdmt_adjoint() (adjoint = 1)
+ * call. This exists to time and profile individual kernels. */
+typedef struct {
+  int32_t kind;          /* 0 init, 1 one iteration, 2 fused iterations,
+                            3 transpose of one iteration, 4 transpose of the init */
+  int32_t level_first;   /* first iteration covered (0 = the initialisation) */
+  int32_t level_last;    /* last iteration covered */
+  int32_t work_items;    /* workgroups per beam */
+  int64_t lds_bytes;     /* dynamic LDS per workgroup */
+  int64_t bytes_read;    /* algorithmic bytes per beam: each consumed element once */
+  int64_t bytes_written; /* algorithmic bytes per beam: each produced element once */
+  int64_t staged_bytes;  /* bytes per beam the step's work items load, overlaps included */
+  int64_t adds;          /* additions per beam */
+} fdmt_step_info_t;
+
+/* Number of steps of the forward (adjoint = 0) or adjoint (adjoint = 1)
+ * transform; -1 if p is NULL. */
+int32_t fdmt_step_count(fdmt_plan_t p, int32_t adjoint);
+
+/* Describes one step (see fdmt_step_info_t). */
+fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_step_info_t *info);
+
+/* Enqueues one step; arguments as for fdmt_forward()/fdmt_adjoint(). */
+fdmt_status_t fdmt_run_step(fdmt_plan_t p, int32_t adjoint, int32_t step, const void *in, void *out,
+                            int32_t batch, void *ws, size_t ws_bytes, void *hip_stream);
 
 /* Host copy of one sub-band's delay table (for inspection and table tests).
  * level 0: sub = channel, *n_rows = rows of its Option-1 partial sums, no

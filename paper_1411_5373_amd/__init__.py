@@ -5,4 +5,5 @@ only marshals tensors and streams into its C ABI.
 """
 from .binding import (EXPORTED, FDMTError, FDMTFunction, Plan, fdmt, fdmt_adjoint, fdmt_forward,
                    fdmt_last_error, fdmt_plan, fdmt_plan_destroy, fdmt_plan_info,
-                   fdmt_plan_tables, fdmt_status_string, fdmt_workspace_bytes, library_path, load)
+                   fdmt_plan_tables, fdmt_run_step, fdmt_status_string, fdmt_step_count,
+                      fdmt_step_info, fdmt_workspace_bytes, library_path, load)

@@ -22,8 +22,11 @@ FDMT_PLAN_HOST_ONLY = 0x1
 FDMT_PLAN_UNFUSED = 0x2
 
 EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
+            "fdmt_step_count", "fdmt_step_info", "fdmt_run_step",
             "fdmt_plan_tables", "fdmt_plan_info", "fdmt_plan_destroy",
             "fdmt_status_string", "fdmt_last_error")
+
+STEP_KINDS = ("init", "iteration", "fused", "iteration_adjoint", "init_adjoint")
 
 _TORCH_TO_CODE = {torch.float32: FDMT_F32, torch.float16: FDMT_F16,
                   torch.uint8: FDMT_U8, torch.int32: FDMT_I32}
@@ -38,7 +41,19 @@ class FDMTError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("in_dtype", ctypes.c_int32), ("acc_dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("first_levels", ctypes.c_int32),
+                ("later_levels", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("lds_kib", ctypes.c_int32), ("max_block_rows", ctypes.c_int32),
+                ("first_kernel", ctypes.c_int32), ("later_kernel", ctypes.c_int32),
+                ("stream_tiles", ctypes.c_int32), ("gather_rows", ctypes.c_int32)]
+
+
+class _StepInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("level_first", ctypes.c_int32),
+                ("level_last", ctypes.c_int32), ("work_items", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64), ("bytes_read", ctypes.c_int64),
+                ("bytes_written", ctypes.c_int64), ("staged_bytes", ctypes.c_int64),
+                ("adds", ctypes.c_int64)]
 
 
 def library_path():
@@ -65,6 +80,12 @@ def load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, i32, vp, sz, vp]
         f.restype = ctypes.c_int
+    lib.fdmt_step_count.argtypes = [vp, i32]
+    lib.fdmt_step_count.restype = ctypes.c_int32
+    lib.fdmt_step_info.argtypes = [vp, i32, i32, ctypes.POINTER(_StepInfo)]
+    lib.fdmt_step_info.restype = ctypes.c_int
+    lib.fdmt_run_step.argtypes = [vp, i32, i32, vp, vp, i32, vp, sz, vp]
+    lib.fdmt_run_step.restype = ctypes.c_int
     lib.fdmt_plan_tables.argtypes = [vp, i32, i32, p_i32, p_i32, p_i32, i32, p_i32]
     lib.fdmt_plan_tables.restype = ctypes.c_int
     lib.fdmt_plan_info.argtypes = [vp, p_i32, ctypes.POINTER(ctypes.c_int64), i32]
@@ -96,10 +117,14 @@ def fdmt_last_error():
     return load().fdmt_last_error().decode()
 
 
-def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0):
+def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0,
+              first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
+              first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
-    opt = _Options(int(in_dtype), int(acc_dtype), 0, int(flags))
+    opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
+                   int(later_levels), int(tile), int(lds_kib), int(max_block_rows),
+                   int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -117,6 +142,24 @@ def fdmt_forward(plan, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
 def fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, batch, ws_ptr, ws_bytes, stream):
     _check(load().fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, int(batch), ws_ptr, int(ws_bytes),
                                stream), "fdmt_adjoint")
+
+
+def fdmt_step_count(plan, adjoint=False):
+    return int(load().fdmt_step_count(plan, int(bool(adjoint))))
+
+
+def fdmt_step_info(plan, adjoint, step):
+    info = _StepInfo()
+    _check(load().fdmt_step_info(plan, int(bool(adjoint)), int(step), ctypes.byref(info)),
+           "fdmt_step_info")
+    d = {f: getattr(info, f) for f, _ in _StepInfo._fields_}
+    d["kind"] = STEP_KINDS[d["kind"]]
+    return d
+
+
+def fdmt_run_step(plan, adjoint, step, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_run_step(plan, int(bool(adjoint)), int(step), in_ptr, out_ptr, int(batch),
+                                ws_ptr, int(ws_bytes), stream), "fdmt_run_step")
 
 
 def fdmt_plan_tables(plan, level, sub):
@@ -157,7 +200,7 @@ class Plan:
     shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
-                 host_only=False, unfused=False):
+                 host_only=False, unfused=False, **schedule):
         self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
         self.f_min, self.f_max = float(f_min), float(f_max)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
@@ -165,7 +208,7 @@ class Plan:
         self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
         self.handle = None
         self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
-                                _TORCH_TO_CODE[acc_dtype], flags)
+                                _TORCH_TO_CODE[acc_dtype], flags, **schedule)
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
@@ -206,6 +249,20 @@ class Plan:
 
     def adjoint(self, g, out=None, ws=None):
         return self._run(fdmt_adjoint, g, out, self.nd, self.nf, self.acc_dtype, self.acc_dtype, ws)
+
+    def steps(self, adjoint=False):
+        """Per-kernel description of the forward (or adjoint) launch sequence."""
+        return [fdmt_step_info(self.handle, adjoint, i)
+                for i in range(fdmt_step_count(self.handle, adjoint))]
+
+    def run_step(self, adjoint, step, x, out, ws, batch=None):
+        """Enqueue one kernel of the sequence on the current stream (x, out, ws
+        preallocated, as for forward/adjoint)."""
+        if batch is None:
+            batch = 1 if x.dim() == 2 else x.shape[0]
+        fdmt_run_step(self.handle, adjoint, step, ctypes.c_void_p(x.data_ptr()),
+                      ctypes.c_void_p(out.data_ptr()), batch, ctypes.c_void_p(ws.data_ptr()),
+                      ws.numel(), _stream_handle(self.device))
 
     def tables(self, level, sub):
         return fdmt_plan_tables(self.handle, level, sub)

@@ -2,6 +2,7 @@
 // upload and error reporting. See include/fdmt.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -48,6 +49,13 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   const size_t off_leaf_off = reserve(T.leaf_off.size() * sizeof(int32_t));
   const size_t off_leaf_rows = reserve(T.leaf_rows.size() * sizeof(int32_t));
+  const size_t off_recs = reserve(p.fwd.recs.size() * sizeof(fdmt::Rec));
+  const size_t off_heads = reserve(p.fwd.heads.size() * sizeof(int32_t));
+  const size_t off_terms = reserve(p.fwd.terms.size() * sizeof(fdmt::Term));
+  const size_t off_stage = reserve(p.fwd.stage.size() * sizeof(fdmt::Rec));
+  const size_t off_psums = reserve(p.fwd.psums.size() * sizeof(fdmt::Rec));
+  const size_t off_sterms = reserve(p.fwd.sterms.size() * sizeof(fdmt::StagedTerm));
+  const size_t off_sheads = reserve(p.fwd.sheads.size() * sizeof(int32_t));
 
   std::vector<unsigned char> host(bytes, 0);
   for (int l = 1; l <= T.levels; ++l) {
@@ -56,6 +64,20 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   std::memcpy(host.data() + off_leaf_off, T.leaf_off.data(), T.leaf_off.size() * sizeof(int32_t));
   std::memcpy(host.data() + off_leaf_rows, T.leaf_rows.data(), T.leaf_rows.size() * sizeof(int32_t));
+  if (!p.fwd.recs.empty())
+    std::memcpy(host.data() + off_recs, p.fwd.recs.data(), p.fwd.recs.size() * sizeof(fdmt::Rec));
+  if (!p.fwd.heads.empty())
+    std::memcpy(host.data() + off_heads, p.fwd.heads.data(), p.fwd.heads.size() * sizeof(int32_t));
+  if (!p.fwd.terms.empty())
+    std::memcpy(host.data() + off_terms, p.fwd.terms.data(), p.fwd.terms.size() * sizeof(fdmt::Term));
+  if (!p.fwd.stage.empty())
+    std::memcpy(host.data() + off_stage, p.fwd.stage.data(), p.fwd.stage.size() * sizeof(fdmt::Rec));
+  if (!p.fwd.psums.empty())
+    std::memcpy(host.data() + off_psums, p.fwd.psums.data(), p.fwd.psums.size() * sizeof(fdmt::Rec));
+  if (!p.fwd.sterms.empty())
+    std::memcpy(host.data() + off_sterms, p.fwd.sterms.data(), p.fwd.sterms.size() * sizeof(fdmt::StagedTerm));
+  if (!p.fwd.sheads.empty())
+    std::memcpy(host.data() + off_sheads, p.fwd.sheads.data(), p.fwd.sheads.size() * sizeof(int32_t));
 
   hipError_t e = hipGetDevice(&p.device);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
@@ -73,6 +95,15 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   p.dev.leaf_off = reinterpret_cast<const int32_t *>(base + off_leaf_off);
   p.dev.leaf_rows = reinterpret_cast<const int32_t *>(base + off_leaf_rows);
+  p.dev_recs = reinterpret_cast<const fdmt::Rec *>(base + off_recs);
+  p.dev_heads = reinterpret_cast<const int32_t *>(base + off_heads);
+  p.dev_terms = reinterpret_cast<const int2 *>(base + off_terms);
+  p.dev_stage = reinterpret_cast<const fdmt::Rec *>(base + off_stage);
+  p.dev_psums = reinterpret_cast<const fdmt::Rec *>(base + off_psums);
+  p.dev_sterms = reinterpret_cast<const int2 *>(base + off_sterms);
+  p.dev_sheads = reinterpret_cast<const int32_t *>(base + off_sheads);
+  e = fdmt::prepare_kernels(p);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute (dynamic LDS)");
   return FDMT_OK;
 }
 
@@ -106,7 +137,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
                         double f_max, const fdmt_options_t *opt) {
   if (!out) return fail(FDMT_E_INVALID, "out is NULL");
   *out = nullptr;
-  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0};
+  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (opt) o = *opt;
   if (nf < 1 || nf > 65536) return fail(FDMT_E_INVALID, "Nf must be in [1, 65536]");
   if ((nf & (nf - 1)) != 0) return fail(FDMT_E_UNSUPPORTED, "Nf must be a power of two");
@@ -114,7 +145,20 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (nd < 1 || nd > 65536) return fail(FDMT_E_INVALID, "Nd must be in [1, 65536]");
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
     return fail(FDMT_E_INVALID, "need 0 < f_min < f_max (finite)");
-  if (o.reserved != 0) return fail(FDMT_E_INVALID, "options.reserved must be 0");
+  if (o.first_levels < 0 || o.first_levels > 8 || o.later_levels < 0 || o.later_levels > 8)
+    return fail(FDMT_E_INVALID, "fused iterations per pass must be in [1, 8]");
+  if (o.tile < 0 || (o.tile && (o.tile < 64 || o.tile > 8192 || o.tile % 64)))
+    return fail(FDMT_E_INVALID, "tile must be a multiple of 64 in [64, 8192]");
+  if (o.lds_kib < 0 || (o.lds_kib && (o.lds_kib < 16 || o.lds_kib > 160)))
+    return fail(FDMT_E_INVALID, "lds_kib must be in [16, 160]");
+  if (o.first_kernel < 0 || o.first_kernel > 2 || o.later_kernel < 0 || o.later_kernel > 3)
+    return fail(FDMT_E_INVALID, "unknown pass kernel");
+  if (o.stream_tiles < 0 || o.stream_tiles > 65535)
+    return fail(FDMT_E_INVALID, "stream_tiles must be in [1, 65535]");
+  if (o.gather_rows < 0 || o.gather_rows > 16 || (o.gather_rows & (o.gather_rows - 1)))
+    return fail(FDMT_E_INVALID, "gather_rows must be 1, 2, 4, 8 or 16");
+  if (o.max_block_rows < 0 || o.max_block_rows > 4096)
+    return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED))
     return fail(FDMT_E_INVALID, "unknown option flag");
   if (!pair_supported(o.in_dtype, o.acc_dtype))
@@ -138,7 +182,46 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   p.in_dtype = o.in_dtype;
   p.acc_dtype = o.acc_dtype;
   p.flags = o.flags;
+  if (o.stream_tiles) p.tiles_per_wg = o.stream_tiles;
+  if (o.gather_rows) p.gather_rows = o.gather_rows;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
+  if (!(o.flags & FDMT_PLAN_UNFUSED)) {
+    fdmt::ScheduleParams sp;
+    if (o.first_levels) {
+      sp.first_levels = o.first_levels;
+      sp.first_auto = false;
+    }
+    if (o.later_levels) {
+      sp.later_levels = o.later_levels;
+      sp.later_auto = false;
+    }
+    if (o.tile) sp.tile = o.tile;
+    if (o.lds_kib) sp.lds_bytes = o.lds_kib * 1024;
+    if (o.max_block_rows) sp.max_block_rows = o.max_block_rows;
+    static const fdmt::PassKind kinds[] = {fdmt::PassKind::Staged, fdmt::PassKind::Staged,
+                                           fdmt::PassKind::Recursive, fdmt::PassKind::Register};
+    if (o.first_kernel) sp.first_kind = kinds[o.first_kernel];
+    if (o.later_kernel) sp.later_kind = kinds[o.later_kernel];
+    try {
+      const std::string err = fdmt::build_schedule(p.fwd, p.tab, sp);
+      if (!err.empty()) {
+        delete h;
+        return fail(FDMT_E_UNSUPPORTED, "schedule: " + err);
+      }
+    } catch (const std::bad_alloc &) {
+      delete h;
+      return fail(FDMT_E_NOMEM, "host allocation of the schedule failed");
+    }
+  }
+  fdmt::plan_steps(p);
+  // Time tiles run along the grid's y dimension (at most 65535 workgroups).
+  int64_t min_tile = 1024;
+  for (const fdmt::Pass &ps : p.fwd.passes)
+    if (!ps.gather) min_tile = std::min<int64_t>(min_tile, ps.tile);
+  if ((nt + min_tile - 1) / min_tile > 65535) {
+    delete h;
+    return fail(FDMT_E_UNSUPPORTED, "Nt too long for the time tile (more than 65535 tiles)");
+  }
   if (!(o.flags & FDMT_PLAN_HOST_ONLY)) {
     const fdmt_status_t s = upload(p);
     if (s != FDMT_OK) {
@@ -171,6 +254,98 @@ fdmt_status_t fdmt_adjoint(fdmt_plan_t p, const void *grad_out, void *grad_in, i
   if (s != FDMT_OK) return s;
   hipError_t e = fdmt::launch_adjoint(p->plan, grad_out, grad_in, batch, ws, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(e, "fdmt_adjoint launch");
+  return FDMT_OK;
+}
+
+int32_t fdmt_step_count(fdmt_plan_t p, int32_t adjoint) {
+  if (!p) return -1;
+  return static_cast<int32_t>(adjoint ? p->plan.adj_steps.size() : p->plan.fwd_steps.size());
+}
+
+fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_step_info_t *info) {
+  if (!p || !info) return fail(FDMT_E_INVALID, "plan or info is NULL");
+  const fdmt::Plan &P = p->plan;
+  const auto &steps = adjoint ? P.adj_steps : P.fwd_steps;
+  if (step < 0 || step >= static_cast<int32_t>(steps.size()))
+    return fail(FDMT_E_INVALID, "step out of range");
+  const fdmt::Step &st = steps[step];
+  const fdmt::Tables &T = P.tab;
+  const int64_t nt = P.nt;
+  const int64_t in_b = P.in_dtype == FDMT_U8 ? 1 : (P.in_dtype == FDMT_F16 ? 2 : 4);
+  *info = fdmt_step_info_t{};
+  info->kind = static_cast<int32_t>(st.kind);
+  auto init_adds = [&]() {
+    int64_t a = 0;
+    for (int k = 0; k < T.nf; ++k) a += T.leaf_rows[k] - 1;
+    return a * nt;
+  };
+  switch (st.kind) {
+    case fdmt::Step::Init:
+      info->level_first = info->level_last = 0;
+      info->work_items = T.nf;
+      info->bytes_read = static_cast<int64_t>(T.nf) * nt * in_b;
+      info->bytes_written = T.total[0] * nt * 4;
+      info->staged_bytes = info->bytes_read;
+      info->adds = init_adds();
+      break;
+    case fdmt::Step::Merge:
+      info->level_first = info->level_last = st.index;
+      info->work_items = static_cast<int32_t>(T.total[st.index]);
+      info->bytes_read = T.total[st.index - 1] * nt * 4;
+      info->bytes_written = T.total[st.index] * nt * 4;
+      info->staged_bytes = 2 * T.total[st.index] * nt * 4;
+      info->adds = T.total[st.index] * nt;
+      break;
+    case fdmt::Step::Fused: {
+      const fdmt::Pass &ps = P.fwd.passes[st.index];
+      info->level_first = ps.from_input ? 0 : ps.l0 + 1;
+      info->level_last = ps.l1;
+      info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
+                                                          ((nt + 4096 / P.gather_rows - 1) / (4096 / P.gather_rows)))
+                                   : static_cast<int32_t>(ps.nblocks * ((nt + ps.tile - 1) / ps.tile));
+      info->lds_bytes = ps.gather ? 0
+                        : ps.kind == fdmt::PassKind::Staged
+                            ? static_cast<int64_t>(ps.lds_a + ps.lds_p + ps.lds_b + ps.max_recs) * 4
+                            : static_cast<int64_t>(ps.lds_a + ps.lds_b) * 4 + static_cast<int64_t>(ps.max_recs) * 32;
+      const int64_t eb = ps.from_input ? in_b : 4;
+      info->bytes_read = ps.rows_in * nt * eb;
+      info->bytes_written = ps.rows_out * nt * 4;
+      info->staged_bytes = ps.staged_rows * nt * eb;
+      for (int l = ps.l0 + 1; l <= ps.l1; ++l) info->adds += T.total[l] * nt;
+      if (ps.from_input) info->adds += init_adds();
+      break;
+    }
+    case fdmt::Step::MergeAdj:
+      info->level_first = info->level_last = st.index;
+      info->work_items = static_cast<int32_t>(T.total[st.index - 1]);
+      info->bytes_read = T.total[st.index] * nt * 4;
+      info->bytes_written = T.total[st.index - 1] * nt * 4;
+      info->staged_bytes = 2 * T.total[st.index] * nt * 4;
+      info->adds = (T.total[st.index] * 2 - T.total[st.index - 1]) * nt;
+      break;
+    case fdmt::Step::InitAdj:
+      info->level_first = info->level_last = 0;
+      info->work_items = T.nf;
+      info->bytes_read = T.total[0] * nt * 4;
+      info->bytes_written = static_cast<int64_t>(T.nf) * nt * 4;
+      info->staged_bytes = info->bytes_read;
+      for (int k = 0; k < T.nf; ++k)
+        info->adds += (static_cast<int64_t>(T.leaf_rows[k]) * (T.leaf_rows[k] + 1) / 2 - 1) * nt;
+      break;
+  }
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_run_step(fdmt_plan_t p, int32_t adjoint, int32_t step, const void *in, void *out,
+                            int32_t batch, void *ws, size_t ws_bytes, void *hip_stream) {
+  fdmt_status_t s = check_call(p, in, out, batch, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  const auto &steps = adjoint ? p->plan.adj_steps : p->plan.fwd_steps;
+  if (step < 0 || step >= static_cast<int32_t>(steps.size()))
+    return fail(FDMT_E_INVALID, "step out of range");
+  hipError_t e = fdmt::run_step(p->plan, adjoint != 0, step, in, out, batch, ws,
+                                static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "fdmt_run_step launch");
   return FDMT_OK;
 }
 

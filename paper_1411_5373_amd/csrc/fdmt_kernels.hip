@@ -8,7 +8,9 @@
 // every kernel streams rows with coalesced loads (lane i reads sample base+i).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "fdmt_plan.h"
 
@@ -128,100 +130,786 @@ __global__ __launch_bounds__(kThreads) void init_adjoint_kernel(
   }
 }
 
-template <typename Tin, typename Tacc>
-hipError_t forward_unfused(const Plan &p, const Tin *in, Tacc *out, int batch, void *ws,
-                           hipStream_t stream) {
-  const Tables &T = p.tab;
-  const int L = T.levels;
-  const int64_t nt = p.nt;
-  const unsigned tiles = static_cast<unsigned>((nt + kTile - 1) / kTile);
-  const int64_t plane_b = p.rmax * p.ntp;
-  Tacc *buf[2] = {static_cast<Tacc *>(ws), static_cast<Tacc *>(ws) + plane_b * batch};
+// ---------------------------------------------------------------------------
+// Fused pass: iterations l0+1 .. l1 of one block (a row range of one sub-band
+// of plane l1) over one time tile, every intermediate plane held in LDS.
+//
+// The host flattens the block's dependency tree into per-row records (Rec):
+// level 0 rows are staged from global memory into LDS buffer A, level i is
+// merged from the buffer of level i-1 into the other buffer, and the top
+// level goes straight to global memory. Each output element is the same
+// single addition lower[d_lo][t] + upper[d_hi][t - s] (or the copy rule) as
+// in the per-iteration kernels, so every schedule gives identical bits.
+//
+// Work split: rows are dealt round-robin to the waves. A lane handles columns
+// lane + 64*j, so each LDS access of a wave touches 64 consecutive words (no
+// bank conflicts) and each global access is a coalesced 256-byte run; whole
+// 256-column chunks run without bounds or copy-rule checks.
+constexpr int kFusedThreads = 512;
+constexpr int kWaves = kFusedThreads / 64;
 
-  // Initialisation writes plane 0, or the output directly when Nf = 1.
+struct FusedArgs {
+  const void *src;      // input [beam][Nf][Nt] (first pass) or plane l0
+  void *dst;            // plane l1 or the user output
+  const Rec *recs;      // this pass's records
+  const int32_t *heads; // this pass's block headers (kRecHeader each)
+  int64_t src_stride, src_bstride, dst_stride, dst_bstride;
+  int32_t nt, k, nblocks, tile, lds_a, lds_b;
+};
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so each XCD
+// runs a contiguous range of work items (neighbouring blocks share leaf rows
+// and time halos through that XCD's L2).
+__device__ __forceinline__ int xcd_local_order(int id, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = id & 7, slot = id >> 3;
+  return x * q + (x < r ? x : r) + slot;
+}
+
+// Option-1 partial sum of chain length n at column c: x[c] + x[c-1] + ... + x[c-n].
+template <typename Tacc>
+__device__ __forceinline__ Tacc chain(const Tacc *x, int c, int n) {
+  Tacc v = x[c];
+  for (int d = 1; d <= n; ++d) v += x[c - d];
+  return v;
+}
+
+template <typename Tin, typename Tacc, bool FROM_INPUT>
+__global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tacc *buf_a = reinterpret_cast<Tacc *>(smem);
+  Tacc *buf_b = buf_a + a.lds_a;
+  Rec *lrec = reinterpret_cast<Rec *>(buf_b + a.lds_b);
+
+  const int blk = xcd_local_order(blockIdx.x, a.nblocks);
+  const int T0 = blockIdx.y * a.tile;
+  const int64_t beam = blockIdx.z;
+  const int wave = uniform(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  const int32_t *head = a.heads + blk * kRecHeader;
+  const Rec *grec = a.recs + head[0];
+  const int nrec = head[1 + a.k];
+  const int nstage = head[1];
+
+  // All records of the block into LDS (two 16-byte words per record).
   {
-    Tacc *dst = L == 0 ? out : buf[0];
-    const int64_t stride = L == 0 ? nt : p.ntp;
-    const int64_t bstride = L == 0 ? static_cast<int64_t>(T.nd) * nt : plane_b;
-    dim3 grid(T.nf, tiles, batch);
-    hipLaunchKernelGGL((init_kernel<Tin, Tacc>), grid, dim3(kThreads), 0, stream, in, dst,
-                       p.dev.leaf_off, p.dev.leaf_rows, nt, static_cast<int64_t>(T.nf) * nt,
-                       stride, bstride);
+    const int4 *from = reinterpret_cast<const int4 *>(grec);
+    int4 *to = reinterpret_cast<int4 *>(lrec);
+    for (int x = threadIdx.x; x < 2 * nrec; x += kFusedThreads) to[x] = from[x];
   }
-  for (int l = 1; l <= L; ++l) {
-    const Tacc *src = buf[(l - 1) & 1];
-    const bool last = l == L;
-    Tacc *dst = last ? out : buf[l & 1];
-    const int64_t stride = last ? nt : p.ntp;
-    const int64_t bstride = last ? static_cast<int64_t>(T.nd) * nt : plane_b;
-    dim3 grid(static_cast<unsigned>(T.total[l]), tiles, batch);
-    hipLaunchKernelGGL((merge_kernel<Tacc>), grid, dim3(kThreads), 0, stream, src, dst,
-                       p.dev.merge[l], nt, p.ntp, plane_b, stride, bstride);
+  __syncthreads();
+
+  // Stage the leaves, zero outside [0, nt). A wave takes two rows at a time
+  // and issues every load of both (up to 8 columns per lane each) before
+  // writing any of them to LDS.
+  {
+    typedef typename std::conditional<FROM_INPUT, Tin, Tacc>::type Tsrc;
+    const Tsrc *in_base = static_cast<const Tsrc *>(a.src) + beam * a.src_bstride;
+    for (int q0 = wave; q0 < nstage; q0 += 2 * kWaves) {
+      Tacc v[2][8];
+      int wd[2], dst[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int q = q0 + m * kWaves;
+        wd[m] = 0;
+        dst[m] = 0;
+        if (q < nstage) {
+          const Rec e = lrec[q];
+          const int t0 = T0 - e.d;
+          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * a.nt
+                                                  : static_cast<int64_t>(e.a) * a.src_stride);
+          wd[m] = e.e;
+          dst[m] = e.c;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int c = 64 * j + lane;
+            const int t = t0 + c;
+            v[m][j] = (c < e.e && t >= 0 && t < a.nt) ? widen<Tacc>(row[t]) : Tacc(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = 64 * j + lane;
+          if (c < wd[m]) buf_a[dst[m] + c] = v[m][j];
+        }
+        if (wd[m] > 512) {  // rare: rows wider than 512 columns
+          const Rec e = lrec[q0 + m * kWaves];
+          const int t0 = T0 - e.d;
+          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * a.nt
+                                                  : static_cast<int64_t>(e.a) * a.src_stride);
+          for (int c = 512 + lane; c < e.e; c += 64) {
+            const int t = t0 + c;
+            buf_a[e.c + c] = (t >= 0 && t < a.nt) ? widen<Tacc>(row[t]) : Tacc(0);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int i = 1; i <= a.k; ++i) {
+    const Tacc *S = (i & 1) ? buf_a : buf_b;
+    Tacc *D = (i & 1) ? buf_b : buf_a;
+    const bool top = i == a.k;
+    const int qe = head[1 + i];
+    for (int q = head[i] + wave; q < qe; q += kWaves) {
+      const Rec e = lrec[q];
+      const Tacc *pl = S + e.a;
+      const Tacc *ph = S + e.b;
+      const int c_hi = e.d - T0;  // first column with t - s >= 0
+      int cmax = e.e;
+      Tacc *out;
+      if (top) {
+        out = static_cast<Tacc *>(a.dst) + beam * a.dst_bstride + e.c * a.dst_stride + T0;
+        const int left = a.nt - T0;
+        if (left < cmax) cmax = left;
+      } else {
+        out = D + e.c;
+      }
+      int c0 = 0;
+      if (FROM_INPUT && i == 1) {
+        const int gl = e.g, gh = e.h;
+        if (c_hi <= 0) {
+          for (; c0 + 256 <= cmax; c0 += 256) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int c = c0 + 64 * j + lane;
+              out[c] = chain(pl, c, gl) + chain(ph, c, gh);
+            }
+          }
+        }
+        for (int c = c0 + lane; c < cmax; c += 64) {
+          Tacc v = chain(pl, c, gl);
+          if (c >= c_hi) v += chain(ph, c, gh);
+          out[c] = v;
+        }
+      } else {
+        if (c_hi <= 0) {
+          for (; c0 + 256 <= cmax; c0 += 256) {
+            const Tacc v0 = pl[c0 + lane] + ph[c0 + lane];
+            const Tacc v1 = pl[c0 + 64 + lane] + ph[c0 + 64 + lane];
+            const Tacc v2 = pl[c0 + 128 + lane] + ph[c0 + 128 + lane];
+            const Tacc v3 = pl[c0 + 192 + lane] + ph[c0 + 192 + lane];
+            out[c0 + lane] = v0;
+            out[c0 + 64 + lane] = v1;
+            out[c0 + 128 + lane] = v2;
+            out[c0 + 192 + lane] = v3;
+          }
+        }
+        for (int c = c0 + lane; c < cmax; c += 64) {
+          Tacc v = pl[c];
+          if (c >= c_hi) v += ph[c];
+          out[c] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct View {
+  void *ptr;
+  int64_t stride, bstride;
+};
+
+// ---------------------------------------------------------------------------
+// Register gather over k fused iterations: walking the tables down from an
+// output row of plane l1 gives 2^k terms (row of plane l0, accumulated shift
+// sigma); the output is their sum, evaluated as the recursion evaluates it:
+// sibling pairs first, then pairs of pairs, lower half before upper half.
+// A term whose time t - sigma is negative is zero (the record starts at 0),
+// and an upper half made only of such terms adds +0, so each element equals
+// the per-iteration result exactly (the copy rule).
+//
+// Work split: a workgroup covers 1024 consecutive samples of one output row,
+// 4 per lane; every term is one unaligned 16-byte load per lane, all issued
+// before any add. Rows run fastest in the workgroup order so neighbouring
+// rows - which share most of their terms - meet in one XCD's L2.
+constexpr int kGatherThreads = 1024;
+
+// Four consecutive elements at 4-byte alignment: one 16-byte global access.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct Vec4<int32_t> {
+  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
+};
+
+template <typename Tacc, int K>
+__global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
+    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
+    int32_t nt, int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+    int32_t nrows, int32_t rows_per_wg) {
+  typedef typename Vec4<Tacc>::type V;
+  constexpr int N = 1 << K;
+  // A workgroup holds rows_per_wg consecutive output rows (one wave each, the
+  // rows share most terms, so repeats hit this CU's L1) over one tile of
+  // 256 * (kGatherThreads / 64 / rows_per_wg) samples.
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;  // waves per row
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  const int tw = (blockIdx.y * col_waves + wave % col_waves) * 256;  // first sample of the wave
+  const int t = tw + lane * 4;
+  if (t >= nt) return;
+  const Tacc *base = src + blockIdx.z * src_bstride;
+  const int2 *tm = terms + static_cast<int64_t>(r) * N;
+  int2 e[N];
+  int smax = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    e[j] = tm[j];
+    smax = e[j].y > smax ? e[j].y : smax;
+  }
+  V v[N];
+  if (tw >= smax) {  // every term inside the record for the whole wave
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      v[j] = *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t - e[j].y));
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tacc *row = base + e[j].x * src_stride;
+      const int ts = t - e[j].y;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[j][i] = ts + i >= 0 ? row[ts + i] : Tacc(0);
+    }
+  }
+#pragma unroll
+  for (int span = 1; span < N; span *= 2)
+#pragma unroll
+    for (int j = 0; j < N; j += 2 * span) v[j] = v[j] + v[j + span];
+  Tacc *o = dst + blockIdx.z * dst_bstride + r * dst_stride + t;
+  if (t + 4 <= nt) {
+    *reinterpret_cast<V *>(o) = v[0];
+  } else {
+    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = v[0][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Staged gather over k fused iterations. A block is a row range of one
+// sub-band of plane l1; a workgroup keeps the block's tables in LDS and
+// streams over a run of time tiles. Per tile it stages, once each, the rows
+// of plane l0 (or the input channels) its outputs read, zero outside
+// [0, nt); in the first pass it then builds each channel's Option-1 partial
+// sums from the staged input in LDS, in the chain order x[t] + x[t-1] + ...
+// Each output element is the sum of its 2^k terms (row of plane l0,
+// accumulated shift) read from LDS, added as the recursion adds them:
+// sibling pairs first, lower half before upper half. A term before the
+// record start reads a staged zero, so the copy rule needs no branch and
+// every result equals the per-iteration kernels' bit for bit.
+//
+// Latency: the next tile's staging loads are issued into registers before
+// the current tile's outputs are computed, so they are in flight meanwhile.
+// Staging is one flat copy of 4-sample quads (thread x moves quads x,
+// x + 512, ...); the compute loop gives each wave whole output rows and each
+// lane the columns lane + 64*j, so every LDS read of a wave is 64 consecutive
+// words (no bank conflicts).
+constexpr int kStagedThreads = 512;
+constexpr int kStagedWaves = kStagedThreads / 64;
+constexpr int kStageQuads = kMaxStagedQuads / kStagedThreads;  // quads per thread in registers
+
+struct StagedArgs {
+  const void *src;      // input [beam][Nf][Nt] (first pass) or plane l0
+  void *dst;            // plane l1 or the user output
+  const Rec *stage;     // this pass's staging records
+  const Rec *psums;     // this pass's partial-sum records (first pass)
+  const int2 *terms;    // this pass's terms {LDS offset at column 0, unused}
+  const int32_t *heads; // this pass's block headers
+  int64_t src_stride, src_bstride, dst_stride, dst_bstride;
+  int32_t nt, nblocks, tile, ntiles, tiles_per_wg, lds_rec, lds_prec, lds_term;
+};
+
+template <typename Tacc, int N>
+struct TreeSum {
+  static __device__ __forceinline__ void eval(const int2 *tm, const Tacc *lds, int col, Tacc out[4]) {
+    Tacc l[4], r[4];
+    TreeSum<Tacc, N / 2>::eval(tm, lds, col, l);
+    TreeSum<Tacc, N / 2>::eval(tm + N / 2, lds, col, r);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = l[j] + r[j];
+  }
+};
+template <typename Tacc>
+struct TreeSum<Tacc, 1> {
+  static __device__ __forceinline__ void eval(const int2 *tm, const Tacc *lds, int col, Tacc out[4]) {
+    const Tacc *p = lds + tm[0].x + col;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = p[64 * j];
+  }
+};
+
+template <typename Tsrc, typename Tacc>
+struct Stager {
+  Tacc v[kStageQuads][4];
+  int dst[kStageQuads];
+
+  // Loads this thread's quads of the tile starting at T0 into registers.
+  __device__ __forceinline__ void load(const Tsrc *base, const int4 *lrec, int total, int qpr,
+                                       uint32_t magic, int T0, int nt, int64_t row_stride) {
+#pragma unroll
+    for (int u = 0; u < kStageQuads; ++u) {
+      const int q = threadIdx.x + u * kStagedThreads;
+      dst[u] = -1;
+      if (q < total) {
+        const int row = static_cast<int>(__umulhi(static_cast<uint32_t>(q), magic));
+        const int col = 4 * (q - row * qpr);
+        const int4 e = lrec[row];  // {source row, LDS offset, win, padded width}
+        if (col < e.w) {
+          dst[u] = e.y + col;
+          const int t = T0 - e.z + col;
+          const Tsrc *src = base + static_cast<int64_t>(e.x) * row_stride;
+          if (t >= 0 && t + 4 <= nt) {
+            if constexpr (std::is_same<Tsrc, Tacc>::value) {
+              const typename Vec4<Tacc>::type w = *reinterpret_cast<const typename Vec4<Tacc>::type *>(src + t);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[u][i] = w[i];
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[u][i] = widen<Tacc>(src[t + i]);
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              v[u][i] = (t + i >= 0 && t + i < nt) ? widen<Tacc>(src[t + i]) : Tacc(0);
+          }
+        }
+      }
+    }
+  }
+
+  // Writes the quads to LDS (16-byte aligned: offsets and columns are multiples of 4).
+  __device__ __forceinline__ void store(Tacc *lds) const {
+    typedef Tacc V4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int u = 0; u < kStageQuads; ++u) {
+      if (dst[u] >= 0) {
+        V4 w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = v[u][i];
+        *reinterpret_cast<V4 *>(lds + dst[u]) = w;
+      }
+    }
+  }
+};
+
+template <typename Tin, typename Tacc, bool FROM_INPUT, int K>
+__global__ __launch_bounds__(kStagedThreads) void staged_pass_kernel(StagedArgs a) {
+  constexpr int N = 1 << K;
+  typedef typename std::conditional<FROM_INPUT, Tin, Tacc>::type Tsrc;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Tacc *lds = reinterpret_cast<Tacc *>(smem);
+  int4 *lrec = reinterpret_cast<int4 *>(reinterpret_cast<int32_t *>(smem) + a.lds_rec);
+  int4 *lprec = reinterpret_cast<int4 *>(reinterpret_cast<int32_t *>(smem) + a.lds_prec);
+  int2 *lterm = reinterpret_cast<int2 *>(reinterpret_cast<int32_t *>(smem) + a.lds_term);
+
+  const int nchunks = (a.ntiles + a.tiles_per_wg - 1) / a.tiles_per_wg;
+  const int w = xcd_local_order(blockIdx.x, a.nblocks * nchunks);
+  const int blk = w % a.nblocks;
+  const int tile_begin = (w / a.nblocks) * a.tiles_per_wg;
+  const int tile_end = tile_begin + a.tiles_per_wg < a.ntiles ? tile_begin + a.tiles_per_wg : a.ntiles;
+  const int64_t beam = blockIdx.z;
+  const int32_t *head = a.heads + blk * kStagedHeader;
+  const int nstage = head[1], nout = head[3], qpr = head[5], npsum = head[8];
+  const uint32_t magic = static_cast<uint32_t>(head[6]);
+  const int wave = uniform(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+
+  // Block tables into LDS.
+  {
+    const Rec *gs = a.stage + head[0];
+    for (int x = threadIdx.x; x < nstage; x += kStagedThreads) {
+      const Rec e = gs[x];
+      lrec[x] = make_int4(e.a, e.c, e.d, e.e);
+    }
+    if (FROM_INPUT) {
+      const Rec *gp = a.psums + head[7];
+      for (int x = threadIdx.x; x < npsum; x += kStagedThreads) {
+        const Rec e = gp[x];
+        lprec[2 * x] = make_int4(e.a, e.b, e.c, e.d);
+        lprec[2 * x + 1] = make_int4(e.e, e.f, 0, 0);
+      }
+    }
+    const int2 *gt = a.terms + head[2];
+    for (int x = threadIdx.x; x < nout * N; x += kStagedThreads) lterm[x] = gt[x];
+  }
+  __syncthreads();
+
+  const Tsrc *base = static_cast<const Tsrc *>(a.src) + beam * a.src_bstride;
+  const int64_t row_stride = FROM_INPUT ? static_cast<int64_t>(a.nt) : a.src_stride;
+  const int total = nstage * qpr;
+  Stager<Tsrc, Tacc> st;
+  st.load(base, lrec, total, qpr, magic, tile_begin * a.tile, a.nt, row_stride);
+
+  for (int tile = tile_begin; tile < tile_end; ++tile) {
+    const int T0 = tile * a.tile;
+    st.store(lds);
+    __syncthreads();
+    if (FROM_INPUT) {
+      // Option-1 partial sums of each channel, rows 0 .. d_last.
+      for (int j = wave; j < npsum; j += kStagedWaves) {
+        const int4 e = lprec[2 * j];       // {LDS row 0, LDS input row, d_last, row stride}
+        const int4 f = lprec[2 * j + 1];   // {width, input columns ahead}
+        const Tacc *x = lds + e.y + f.y;
+        for (int c = lane; c < f.x; c += 64) {
+          Tacc acc = x[c];
+          lds[e.x + c] = acc;
+          for (int d = 1; d <= e.z; ++d) {
+            acc += x[c - d];
+            lds[e.x + d * e.w + c] = acc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (tile + 1 < tile_end)
+      st.load(base, lrec, total, qpr, magic, T0 + a.tile, a.nt, row_stride);
+    const int cmax = a.nt - T0 < a.tile ? a.nt - T0 : a.tile;
+    for (int r = wave; r < nout; r += kStagedWaves) {
+      int2 tm[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) tm[j] = lterm[r * N + j];
+      Tacc *o = static_cast<Tacc *>(a.dst) + beam * a.dst_bstride +
+                (head[4] + r) * a.dst_stride + T0;
+      for (int c0 = 0; c0 < a.tile; c0 += 256) {
+        Tacc acc[4];
+        TreeSum<Tacc, N>::eval(tm, lds, c0 + lane, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + 64 * j + lane;
+          if (c < cmax) o[c] = acc[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t fused_lds_bytes(const Pass &ps) {
+  if (ps.kind == PassKind::Staged)  // staged rows, partial sums, records, terms (4-byte units)
+    return static_cast<size_t>(ps.lds_a + ps.lds_p + ps.lds_b + ps.max_recs) * 4;
+  return static_cast<size_t>(ps.lds_a + ps.lds_b) * 4 + static_cast<size_t>(ps.max_recs) * sizeof(Rec);
+}
+
+View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, bool adjoint) {
+  const int64_t nt = p.nt;
+  const int64_t plane_b = p.ws_rows * p.ntp;
+  const int64_t in_rows = adjoint ? p.tab.nd : p.tab.nf;
+  const int64_t out_rows = adjoint ? p.tab.nf : p.tab.nd;
+  switch (b) {
+    case Buf::In: return {const_cast<void *>(in), nt, in_rows * nt};
+    case Buf::Out: return {out, nt, out_rows * nt};
+    case Buf::Ws0: return {ws, p.ntp, plane_b};
+    case Buf::Ws1:
+      return {static_cast<unsigned char *>(ws) + static_cast<size_t>(plane_b) * batch * 4, p.ntp, plane_b};
+  }
+  return {nullptr, 0, 0};
+}
+
+template <typename Tin, typename Tacc>
+hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void *out, int batch,
+                            void *ws, hipStream_t stream) {
+  const Tables &T = p.tab;
+  const int64_t nt = p.nt;
+  const View src = view(p, st.src, in, out, ws, batch, false);
+  const View dst = view(p, st.dst, in, out, ws, batch, false);
+  const unsigned tiles = static_cast<unsigned>((nt + kTile - 1) / kTile);
+  switch (st.kind) {
+    case Step::Init: {
+      dim3 grid(T.nf, tiles, batch);
+      hipLaunchKernelGGL((init_kernel<Tin, Tacc>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                         p.dev.leaf_off, p.dev.leaf_rows, nt, src.bstride, dst.stride, dst.bstride);
+      break;
+    }
+    case Step::Merge: {
+      dim3 grid(static_cast<unsigned>(T.total[st.index]), tiles, batch);
+      hipLaunchKernelGGL((merge_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                         p.dev.merge[st.index], nt, src.stride, src.bstride, dst.stride, dst.bstride);
+      break;
+    }
+    case Step::Fused: {
+      const Pass &ps = p.fwd.passes[st.index];
+      if (ps.kind == PassKind::Staged) {
+        StagedArgs a{};
+        a.src = src.ptr;
+        a.dst = dst.ptr;
+        a.stage = p.dev_stage + ps.rec_offset;
+        a.psums = p.dev_psums + ps.psum_offset;
+        a.terms = p.dev_sterms + ps.term_offset;
+        a.heads = p.dev_sheads + ps.head_offset;
+        a.src_stride = src.stride;
+        a.src_bstride = src.bstride;
+        a.dst_stride = dst.stride;
+        a.dst_bstride = dst.bstride;
+        a.nt = static_cast<int32_t>(nt);
+        a.nblocks = ps.nblocks;
+        a.tile = ps.tile;
+        a.ntiles = static_cast<int32_t>((nt + ps.tile - 1) / ps.tile);
+        a.tiles_per_wg = std::max(1, std::min(a.ntiles, p.tiles_per_wg));
+        a.lds_rec = ps.lds_a + ps.lds_p;
+        a.lds_prec = a.lds_rec + ps.stage_ints;
+        a.lds_term = ps.lds_a + ps.lds_p + ps.lds_b;
+        const size_t lds = fused_lds_bytes(ps);
+        const int nchunks = (a.ntiles + a.tiles_per_wg - 1) / a.tiles_per_wg;
+        dim3 grid(static_cast<unsigned>(ps.nblocks * nchunks), 1, batch);
+        const int k = ps.l1 - ps.l0;
+#define FDMT_STAGED(FI, KK) hipLaunchKernelGGL((staged_pass_kernel<Tin, Tacc, FI, KK>), grid, dim3(kStagedThreads), lds, stream, a)
+        if (ps.from_input) {
+          switch (k) {
+            case 1: FDMT_STAGED(true, 1); break;
+            case 2: FDMT_STAGED(true, 2); break;
+            case 3: FDMT_STAGED(true, 3); break;
+            case 4: FDMT_STAGED(true, 4); break;
+            case 5: FDMT_STAGED(true, 5); break;
+            default: return hipErrorInvalidValue;
+          }
+        } else {
+          switch (k) {
+            case 1: FDMT_STAGED(false, 1); break;
+            case 2: FDMT_STAGED(false, 2); break;
+            case 3: FDMT_STAGED(false, 3); break;
+            case 4: FDMT_STAGED(false, 4); break;
+            case 5: FDMT_STAGED(false, 5); break;
+            default: return hipErrorInvalidValue;
+          }
+        }
+#undef FDMT_STAGED
+        break;
+      }
+      if (ps.gather) {
+        const int k = ps.l1 - ps.l0;
+        const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
+        const int tile = 256 * (kGatherThreads / 64 / rpw);
+        const unsigned ntl = static_cast<unsigned>((nt + tile - 1) / tile);
+        dim3 grid(static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw), ntl, batch);
+        const int32_t nt32 = static_cast<int32_t>(nt);
+        const int2 *tm = p.dev_terms + ps.term_offset;
+        const Tacc *sp = static_cast<const Tacc *>(src.ptr);
+        Tacc *dp = static_cast<Tacc *>(dst.ptr);
+        switch (k) {
+          case 1: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 1>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
+          case 2: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 2>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
+          case 3: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 3>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
+          case 4: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 4>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
+          default: return hipErrorInvalidValue;
+        }
+        break;
+      }
+      FusedArgs a{};
+      a.src = src.ptr;
+      a.dst = dst.ptr;
+      a.recs = p.dev_recs + ps.rec_offset;
+      a.heads = p.dev_heads + ps.head_offset;
+      const int k = ps.l1 - ps.l0;
+      a.nt = static_cast<int32_t>(nt);
+      a.src_stride = src.stride;
+      a.src_bstride = src.bstride;
+      a.dst_stride = dst.stride;
+      a.dst_bstride = dst.bstride;
+      a.k = k;
+      a.nblocks = ps.nblocks;
+      a.tile = ps.tile;
+      a.lds_a = ps.lds_a;
+      a.lds_b = ps.lds_b;
+      const size_t lds = fused_lds_bytes(ps);
+      dim3 grid(static_cast<unsigned>(a.nblocks), static_cast<unsigned>((nt + ps.tile - 1) / ps.tile), batch);
+      if (ps.from_input)
+        hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, true>), grid, dim3(kFusedThreads), lds,
+                           stream, a);
+      else
+        hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, false>), grid, dim3(kFusedThreads), lds,
+                           stream, a);
+      break;
+    }
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename Tacc>
-hipError_t adjoint_unfused(const Plan &p, const Tacc *gout, Tacc *gin, int batch, void *ws,
-                           hipStream_t stream) {
+hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void *out, int batch,
+                            void *ws, hipStream_t stream) {
   const Tables &T = p.tab;
-  const int L = T.levels;
   const int64_t nt = p.nt;
+  const View src = view(p, st.src, in, out, ws, batch, true);
+  const View dst = view(p, st.dst, in, out, ws, batch, true);
   const unsigned tiles = static_cast<unsigned>((nt + kTile - 1) / kTile);
-  const int64_t plane_b = p.rmax * p.ntp;
-  Tacc *buf[2] = {static_cast<Tacc *>(ws), static_cast<Tacc *>(ws) + plane_b * batch};
-
-  const Tacc *src = gout;
-  int64_t src_stride = nt, src_bstride = static_cast<int64_t>(T.nd) * nt;
-  for (int l = L; l >= 1; --l) {
-    Tacc *dst = buf[l & 1];
-    dim3 grid(static_cast<unsigned>(T.total[l - 1]), tiles, batch);
-    hipLaunchKernelGGL((merge_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream, src, dst,
-                       p.dev.adj[l], p.dev.merge[l], nt, src_stride, src_bstride, p.ntp, plane_b);
-    src = dst;
-    src_stride = p.ntp;
-    src_bstride = plane_b;
+  switch (st.kind) {
+    case Step::MergeAdj: {
+      const int l = st.index;
+      dim3 grid(static_cast<unsigned>(T.total[l - 1]), tiles, batch);
+      hipLaunchKernelGGL((merge_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                         p.dev.adj[l], p.dev.merge[l], nt, src.stride, src.bstride, dst.stride,
+                         dst.bstride);
+      break;
+    }
+    case Step::InitAdj: {
+      dim3 grid(T.nf, tiles, batch);
+      hipLaunchKernelGGL((init_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                         p.dev.leaf_off, p.dev.leaf_rows, nt, src.stride, src.bstride, dst.bstride);
+      break;
+    }
+    default: return hipErrorInvalidValue;
   }
-  dim3 grid(T.nf, tiles, batch);
-  hipLaunchKernelGGL((init_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream, src, gin,
-                     p.dev.leaf_off, p.dev.leaf_rows, nt, src_stride, src_bstride,
-                     static_cast<int64_t>(T.nf) * nt);
   return hipGetLastError();
 }
 
 } // namespace
 
-size_t workspace_bytes(const Plan &p, int batch) {
-  if (p.tab.levels == 0) return 0;
-  return static_cast<size_t>(2) * batch * p.rmax * p.ntp * 4;
+void plan_steps(Plan &p) {
+  const Tables &T = p.tab;
+  const int L = T.levels;
+  p.fwd_steps.clear();
+  p.adj_steps.clear();
+  p.ws_rows = 0;
+  auto ws = [](int i) { return (i & 1) ? Buf::Ws1 : Buf::Ws0; };
+  if (L == 0) {
+    p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Out});
+  } else if (p.fwd.passes.empty()) {
+    p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Ws0});
+    for (int l = 1; l <= L; ++l)
+      p.fwd_steps.push_back({Step::Merge, l, ws(l - 1), l == L ? Buf::Out : ws(l)});
+    for (int l = 0; l < L; ++l) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[l]);
+  } else {
+    const int n = static_cast<int>(p.fwd.passes.size());
+    // With a separate initialisation, plane 0 occupies workspace 0 and pass i
+    // reads ws(i) and writes ws(i + 1).
+    const int sh = p.fwd.init_separate ? 1 : 0;
+    if (sh) {
+      p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Ws0});
+      p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[0]);
+    }
+    for (int i = 0; i < n; ++i) {
+      const Pass &ps = p.fwd.passes[i];
+      const Buf src = (i == 0 && !sh) ? Buf::In : ws(i - 1 + sh);
+      p.fwd_steps.push_back({Step::Fused, i, src, i == n - 1 ? Buf::Out : ws(i + sh)});
+      if (i < n - 1) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[ps.l1]);
+    }
+  }
+  // Adjoint: one gather per iteration from the output back to plane 0, then
+  // the transpose of the initialisation.
+  if (L == 0) {
+    p.adj_steps.push_back({Step::InitAdj, 0, Buf::In, Buf::Out});
+  } else {
+    for (int l = L; l >= 1; --l)
+      p.adj_steps.push_back({Step::MergeAdj, l, l == L ? Buf::In : ws(l), ws(l - 1)});
+    p.adj_steps.push_back({Step::InitAdj, 0, ws(0), Buf::Out});
+    for (int l = 0; l < L; ++l) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[l]);
+  }
 }
 
-hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
-                          hipStream_t stream) {
+size_t workspace_bytes(const Plan &p, int batch) {
+  if (p.ws_rows == 0) return 0;
+  return static_cast<size_t>(2) * batch * p.ws_rows * p.ntp * 4;
+}
+
+template <typename Tin, typename Tacc, bool FI>
+hipError_t set_staged_lds_k(int lds) {
+  const void *fns[] = {reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 1>),
+                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 2>),
+                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 3>),
+                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 4>),
+                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 5>)};
+  for (const void *f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t set_staged_lds(int lds) {
+  hipError_t e;
+  if ((e = set_staged_lds_k<float, float, true>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<_Float16, float, true>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<uint8_t, float, true>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<uint8_t, int32_t, true>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<int32_t, int32_t, true>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<float, float, false>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<_Float16, float, false>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<uint8_t, float, false>(lds)) != hipSuccess) return e;
+  if ((e = set_staged_lds_k<uint8_t, int32_t, false>(lds)) != hipSuccess) return e;
+  return set_staged_lds_k<int32_t, int32_t, false>(lds);
+}
+
+hipError_t prepare_kernels(const Plan &p) {
+  size_t lds = 0;
+  for (const Pass &ps : p.fwd.passes)
+    if (!ps.gather) lds = std::max(lds, fused_lds_bytes(ps));
+  if (lds <= 64 * 1024) return hipSuccess;
+  const void *fns[] = {
+      reinterpret_cast<const void *>(&fused_pass_kernel<float, float, true>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, true>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, true>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, true>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, true>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<float, float, false>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, false>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, false>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, false>),
+      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, false>)};
+  for (const void *f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  return set_staged_lds(static_cast<int>(lds));
+}
+
+hipError_t run_step(const Plan &p, bool adjoint, int i, const void *in, void *out, int batch,
+                    void *ws, hipStream_t stream) {
+  if (adjoint) {
+    const Step &st = p.adj_steps[i];
+    if (p.acc_dtype == FDMT_F32) return run_adjoint_step<float>(p, st, in, out, batch, ws, stream);
+    return run_adjoint_step<int32_t>(p, st, in, out, batch, ws, stream);
+  }
+  const Step &st = p.fwd_steps[i];
   if (p.acc_dtype == FDMT_F32) {
-    float *o = static_cast<float *>(out);
     switch (p.in_dtype) {
-      case FDMT_F32: return forward_unfused(p, static_cast<const float *>(in), o, batch, ws, stream);
-      case FDMT_F16: return forward_unfused(p, static_cast<const _Float16 *>(in), o, batch, ws, stream);
-      case FDMT_U8: return forward_unfused(p, static_cast<const uint8_t *>(in), o, batch, ws, stream);
+      case FDMT_F32: return run_forward_step<float, float>(p, st, in, out, batch, ws, stream);
+      case FDMT_F16: return run_forward_step<_Float16, float>(p, st, in, out, batch, ws, stream);
+      case FDMT_U8: return run_forward_step<uint8_t, float>(p, st, in, out, batch, ws, stream);
       default: return hipErrorInvalidValue;
     }
   }
-  int32_t *o = static_cast<int32_t *>(out);
   switch (p.in_dtype) {
-    case FDMT_U8: return forward_unfused(p, static_cast<const uint8_t *>(in), o, batch, ws, stream);
-    case FDMT_I32: return forward_unfused(p, static_cast<const int32_t *>(in), o, batch, ws, stream);
+    case FDMT_U8: return run_forward_step<uint8_t, int32_t>(p, st, in, out, batch, ws, stream);
+    case FDMT_I32: return run_forward_step<int32_t, int32_t>(p, st, in, out, batch, ws, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
+hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
+                          hipStream_t stream) {
+  for (size_t i = 0; i < p.fwd_steps.size(); ++i) {
+    hipError_t e = run_step(p, false, static_cast<int>(i), in, out, batch, ws, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch, void *ws,
                           hipStream_t stream) {
-  if (p.acc_dtype == FDMT_F32)
-    return adjoint_unfused(p, static_cast<const float *>(gout), static_cast<float *>(gin), batch,
-                           ws, stream);
-  return adjoint_unfused(p, static_cast<const int32_t *>(gout), static_cast<int32_t *>(gin), batch,
-                         ws, stream);
+  for (size_t i = 0; i < p.adj_steps.size(); ++i) {
+    hipError_t e = run_step(p, true, static_cast<int>(i), gout, gin, batch, ws, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 } // namespace fdmt

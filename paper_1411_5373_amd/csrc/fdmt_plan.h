@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fdmt.h"
+#include "fdmt_schedule.h"
 #include "fdmt_tables.h"
 
 namespace fdmt {
@@ -23,6 +24,17 @@ struct DeviceTables {
   const int32_t *leaf_rows = nullptr;
 };
 
+// Where a step reads or writes: the caller's input/output or one of the two
+// workspace planes.
+enum class Buf { In, Out, Ws0, Ws1 };
+
+// One kernel launch of a transform.
+struct Step {
+  enum Kind { Init, Merge, Fused, MergeAdj, InitAdj } kind;
+  int index;  // Merge/MergeAdj: iteration l; Fused: pass index in the schedule
+  Buf src, dst;
+};
+
 struct Plan {
   Tables tab;
   int64_t nt = 0;        // samples per beam
@@ -33,13 +45,32 @@ struct Plan {
   int64_t rmax = 0;      // tallest plane (rows)
   void *dbuf = nullptr;  // device copy of every table
   DeviceTables dev;
+  Schedule fwd;                // fused forward schedule (empty when unfused)
+  const Rec *dev_recs = nullptr;
+  const int32_t *dev_heads = nullptr;
+  const int2 *dev_terms = nullptr;
+  const Rec *dev_stage = nullptr;
+  const Rec *dev_psums = nullptr;
+  int tiles_per_wg = 1;        // time tiles one staged workgroup streams over
+  int gather_rows = 8;         // output rows per register-gather workgroup
+  const int2 *dev_sterms = nullptr;
+  const int32_t *dev_sheads = nullptr;
+  std::vector<Step> fwd_steps, adj_steps;
+  int64_t ws_rows = 0;         // rows of each workspace plane
 };
 
+// Builds fwd_steps/adj_steps and ws_rows from the tables and the schedule.
+void plan_steps(Plan &p);
+
 // Kernel sequences (fdmt_kernels.hip). Both assume validated arguments.
+hipError_t run_step(const Plan &p, bool adjoint, int step, const void *in, void *out, int batch,
+                    void *ws, hipStream_t stream);
 hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
                           hipStream_t stream);
 hipError_t launch_adjoint(const Plan &p, const void *grad_out, void *grad_in, int batch, void *ws,
                           hipStream_t stream);
 size_t workspace_bytes(const Plan &p, int batch);
+// Sets the dynamic-LDS limit of the fused kernels the plan uses.
+hipError_t prepare_kernels(const Plan &p);
 
 } // namespace fdmt

@@ -1,0 +1,120 @@
+// Pass schedule of the fused FDMT: which iterations each kernel launch runs
+// and, per work block, the tree of (row range, time window) nodes it needs.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fdmt_tables.h"
+
+namespace fdmt {
+
+// One node of a block's dependency tree. Its rows are row0 .. row0+nrows-1 of
+// its iteration's plane (for input-channel leaves: one staged input row and
+// row0 = the channel's first partial-sum row); it holds times
+// [T0 - win, T0 - win + width) of a tile that starts at T0.
+struct Node {
+  int32_t row0, nrows, win, width;
+  int32_t lds;    // element offset inside its LDS buffer
+  int32_t sub;    // sub-band (leaf of the first pass: channel) index
+  int32_t rowcum; // rows of the nodes before it at the same level
+  int32_t pad;
+};
+
+// One row of one level of a block, ready for the kernel (all offsets in
+// elements). Level 0 ("staging") rows copy global data into LDS:
+//   a = source row (plane row, or channel for the first pass), c = LDS row,
+//   d = win (column 0 holds time T0 - win), e = width.
+// Merge rows compute, for columns col < e,
+//   LDS[c + col] (or global row c at the top level)
+//     = LDS[a + col] (+ chain) + (col >= d - T0 ? LDS[b + col] (+ chain) : 0)
+// where a/b already include the child row, window alignment and shift s,
+// d = s + win (so col >= d - T0 exactly when t - s >= 0), f = win,
+// g/h = Option-1 chain lengths of the two halves (first pass, first level).
+struct Rec {
+  int32_t a, b, c, d, e, f, g, h;
+};
+
+constexpr int kRecHeader = 12;  // per block: first record, then level ends (k+1 values)
+
+// How a pass evaluates its iterations.
+enum class PassKind {
+  Staged,     // leaves staged in LDS once, each output the tree sum of its 2^k terms
+  Recursive,  // leaves staged in LDS, iterations merged level by level in LDS
+  Register    // each output the tree sum of its 2^k terms loaded through the caches
+};
+
+// A term of a staged pass: LDS offset of the term's sample at the block's
+// first output time, and the Option-1 chain length (first pass; else 0).
+struct StagedTerm {
+  int32_t lds, chain;
+};
+
+// Per staged block: [0] first staging record, [1] staged rows, [2] first term,
+// [3] output rows, [4] first output row (plane l1), [5] quads per staged row,
+// [6] ceil(2^32 / quads per row), [7] first partial-sum record, [8] channels
+// with partial sums (first pass).
+constexpr int kStagedHeader = 12;
+constexpr int kMaxStagedQuads = 8192;  // staged 4-sample quads per block (held in registers)
+
+struct Pass {
+  bool from_input = false;  // leaves are input channels (first pass)
+  PassKind kind = PassKind::Staged;
+  bool gather = false;      // kind == Register
+  int64_t term_offset = 0;  // Register: index of this pass's first Term in Schedule::terms;
+                            // Staged: first StagedTerm in Schedule::sterms
+  int l0 = 0, l1 = 0;       // consumes plane l0 (or the input), produces plane l1
+  int tile = 0;             // W: output samples per block
+  int nblocks = 0;
+  int nodes_per_block = 0;  // 2^(l1-l0+1) - 1, level by level, leaves first
+  int lds_a = 0, lds_b = 0; // elements of the two LDS buffers
+  int64_t node_offset = 0;  // index of this pass's first node in Schedule::nodes
+  int64_t rec_offset = 0;   // index of this pass's first record in Schedule::recs
+  int64_t head_offset = 0;  // index of this pass's first block header in Schedule::heads
+  int max_recs = 0;         // most records of any block (LDS is reserved for them)
+  int64_t rows_in = 0;      // unique rows of the consumed plane (input: channels)
+  int64_t rows_out = 0;     // rows of the produced plane
+  int64_t staged_rows = 0;  // leaf rows staged, summed over blocks (overlap included)
+  int64_t psum_offset = 0;  // staged first pass: index of the first Schedule::psums record
+  int lds_p = 0;            // staged first pass: LDS elements of the partial-sum rows
+  int stage_ints = 0;       // staged: LDS ints of the staging-record area
+};
+
+struct ScheduleParams {
+  int first_levels = 4;      // iterations fused with the initialisation
+  int later_levels = 3;      // iterations per later pass
+  bool first_auto = true;    // fewer first-pass iterations if they do not fit the budget
+  bool later_auto = true;    // likewise for later passes
+  int tile = 256;            // W (a multiple of 256 for staged passes)
+  int lds_bytes = 64 * 1024; // per-block LDS budget
+  int max_block_rows = 64;   // cap on rows of the top node
+  int acc_bytes = 4;
+  PassKind first_kind = PassKind::Recursive;
+  PassKind later_kind = PassKind::Register;
+};
+
+// A term of a gather pass: plane-l0 row and accumulated shift.
+struct Term {
+  int32_t row, shift;
+};
+
+struct Schedule {
+  bool init_separate = false;   // the initialisation runs as its own step (writes plane 0)
+  std::vector<Pass> passes;
+  std::vector<Node> nodes;
+  std::vector<Rec> recs;        // per block, level by level
+  std::vector<int32_t> heads;   // kRecHeader per block: record base (pass-relative), level ends
+  std::vector<Term> terms;      // register passes: 2^k terms per output row, recursion order
+  std::vector<StagedTerm> sterms;  // staged passes: 2^k terms per block row, recursion order
+  std::vector<Rec> stage;       // staged passes: leaf rows (a = source row, c = LDS, d = win, e = width)
+  std::vector<Rec> psums;       // staged first pass, per channel: a = LDS of partial-sum row 0,
+                                // b = LDS of the staged input row, c = last partial-sum row,
+                                // d = partial-sum row stride, e = width, f = input columns ahead
+  std::vector<int32_t> sheads;  // staged passes: kStagedHeader per block
+};
+
+// Builds the pass list and every block's node tree. Returns "" on success.
+std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p);
+
+} // namespace fdmt

@@ -34,6 +34,8 @@ SHAPES = [  # nf, nt, nd, band
     (64, 1030, 100, (1.2, 1.6)),     # ragged time tail, Nd > Nf
     (256, 3001, 300, (1.2, 1.6)),
     (512, 2048, 96, (0.4, 0.8)),     # Nd << Nf
+    (2, 500, 1999, (0.4, 0.8)),      # Nd >> Nf: ~1000 partial sums per channel
+    (8, 3000, 2500, (1.0, 3.0)),
 ]
 
 
@@ -249,3 +251,44 @@ def test_side_stream():
         y = p.forward(x)
     s.synchronize()
     assert torch.equal(y, ref)
+
+
+SCHEDULES = [
+    # level-by-level merges in LDS
+    dict(first_levels=1, later_levels=1, tile=64, lds_kib=16, max_block_rows=1, first_kernel=2, later_kernel=2),
+    dict(first_levels=3, later_levels=2, tile=64, lds_kib=16, max_block_rows=4, first_kernel=2, later_kernel=2),
+    dict(first_levels=6, later_levels=3, tile=128, lds_kib=120, max_block_rows=64, first_kernel=2, later_kernel=2),
+    # gathers through the caches
+    dict(first_levels=2, later_levels=1, first_kernel=2, later_kernel=3),
+    dict(first_levels=4, later_levels=4, first_kernel=2, later_kernel=3),
+    # staged gathers
+    dict(first_levels=1, later_levels=1, tile=256, lds_kib=16, max_block_rows=1),
+    dict(first_levels=3, later_levels=2, tile=256, lds_kib=24, max_block_rows=5),
+    dict(first_levels=4, later_levels=4, tile=256, lds_kib=64),
+    dict(first_levels=5, later_levels=5, tile=512, lds_kib=150, max_block_rows=128),
+    dict(first_levels=2, later_levels=3, tile=1024, lds_kib=96),
+    dict(first_levels=4, later_levels=3, stream_tiles=1),
+    dict(first_levels=4, later_levels=4, stream_tiles=5),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("nf,nt,nd,band", [(256, 3001, 300, (1.2, 1.6)), (1024, 2000, 1024, (0.4, 0.8)),
+                                           (64, 50, 100, (1.2, 1.6)), (4096, 3000, 2048, (1.2, 1.6))])
+def test_schedules_bit_identical(sched, nf, nt, nd, band):
+    """Any fusion schedule (block splits, tiles, LDS budgets) gives the same bits
+    as the per-iteration kernels, which match the oracle."""
+    print(f"schedule {sched} nf={nf} nt={nt} nd={nd}", flush=True)
+    x = torch.randn(nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(nf + nt))
+    ref = F.Plan(nf, nt, nd, *band, unfused=True).forward(x)
+    try:
+        p = F.Plan(nf, nt, nd, *band, **sched)
+    except F.FDMTError as e:
+        assert e.status == 2  # FDMT_E_UNSUPPORTED: this explicit schedule does not fit the shape
+        pytest.skip(str(e))
+    assert torch.equal(p.forward(x), ref)
+    xi = torch.randint(0, 256, (nf, nt), device=DEV, dtype=torch.uint8,
+                       generator=torch.Generator(DEV).manual_seed(nd))
+    refi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, unfused=True).forward(xi)
+    pi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, **sched)
+    assert torch.equal(pi.forward(xi), refi)
