@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""FDMT benchmark on one MI355X.
+
+One step = the whole hot path over one beam of the Nf=4096 workload
+(Nf=4096 channels over 1.2-1.6 GHz, Nt=65536 samples, Nd=2048 delay trials):
+the forward transform of a uint8 intensity matrix with FP32 accumulation,
+followed by the hand-written adjoint of an FP32 gradient of the same shape.
+Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line. `value` is DM-trial x samples per second of the whole
+step (Nd * Nt / step time); forward-only and adjoint-only rates, achieved HBM
+bandwidth, the adjoint/forward time ratio and the other precision forms are
+reported beside it. `roofline` describes the step's longest kernel: its
+algorithmic bytes (every element it must read and write, once) over its
+average duration measured with HIP events on the launch stream.
+`cpu_baseline` times the CPU oracle (NumPy, one core) on a bounded slice of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
+KERNEL_SOURCES = ("paper_1411_5373_amd/csrc/fdmt_kernels.hip",
+                  "paper_1411_5373_amd/csrc/fdmt_schedule.cpp")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash() or vals.get("kernel") != kernel_key:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(plan, tensors, steps, warmup, torch):
+    """Runs warmup + timed steps; returns (wall ms per step, per-kernel mean ms)."""
+    x, y, g, xb, ws = tensors
+    fwd = plan.steps(False)
+    adj = plan.steps(True)
+    kernels = [(False, i) for i in range(len(fwd))] + [(True, i) for i in range(len(adj))]
+
+    def run(events=None):
+        for j, (is_adj, i) in enumerate(kernels):
+            if is_adj:
+                plan.run_step(True, i, g, xb, ws)
+            else:
+                plan.run_step(False, i, x, y, ws)
+            if events is not None:
+                events[j + 1].record()
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(kernels) + 1)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        run(ev[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps
+           for j in range(len(kernels))]
+    infos = [("adjoint" if a else "forward", (adj if a else fwd)[i]) for a, i in kernels]
+    return (t1 - t0) * 1000.0 / steps, per, infos
+
+
+def cpu_baseline(nt_sample, min_seconds=10.0, max_reps=4):
+    """Oracle forward (int64) + adjoint (float64) on the first nt_sample samples,
+    repeated until at least min_seconds of CPU work (at most max_reps times)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import build_tables, fdmt, fdmt_adjoint
+    w = W.WORKLOADS["c3"]
+    u8, _, _ = W.make_c3(nt=nt_sample)
+    g = np.random.default_rng(7).standard_normal((w.nd, nt_sample))
+    reps = 0
+    t0 = time.perf_counter()
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+        tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+        fdmt(u8, w.f_min, w.f_max, w.nd, tab)
+        fdmt_adjoint(g, w.f_min, w.f_max, w.nf, tab)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": w.nd * nt_sample / dt, "unit": "DM-trial*samples/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one step (forward uint8 -> int64, adjoint float64) of Nf=4096, Nd=2048 on the "
+                      f"first {nt_sample} of 65536 samples, {reps} repetition(s), {dt:.2f} s each; "
+                      f"NumPy, single thread"}
+
+
+def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    if in_dtype == torch.uint8:
+        x = torch.randint(0, 256, (w.nf, w.nt), device="cuda", dtype=torch.uint8, generator=gen)
+    elif in_dtype == torch.int32:
+        x = torch.randint(0, 256, (w.nf, w.nt), device="cuda", dtype=torch.int32, generator=gen)
+    else:
+        x = torch.randn(w.nf, w.nt, device="cuda", generator=gen).to(in_dtype)
+    y = torch.empty(w.nd, w.nt, device="cuda", dtype=acc_dtype)
+    ws = plan.workspace(1)
+    plan.forward(x, out=y, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.forward(x, out=y, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=32768,
+                    help="samples of the workload the CPU oracle baseline processes (0: skip)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(beams and time ranges shard across GPUs without exchange, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1411_5373_amd as F
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = W.WORKLOADS["c3"]
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=torch.float32)
+    x = W.torch_noise((w.nf, w.nt), W.SEED_BASE + 2, "cuda", kind="u8")
+    g = W.torch_noise((w.nd, w.nt), W.SEED_BASE + 102, "cuda")
+    y = torch.empty(w.nd, w.nt, device="cuda", dtype=torch.float32)
+    xb = torch.empty(w.nf, w.nt, device="cuda", dtype=torch.float32)
+    ws = plan.workspace(1)
+    torch.cuda.synchronize()
+
+    ms_step, per, infos = time_steps(plan, (x, y, g, xb, ws), args.steps, args.warmup, torch)
+    fwd_ms = sum(m for m, (d, _) in zip(per, infos) if d == "forward")
+    adj_ms = sum(m for m, (d, _) in zip(per, infos) if d == "adjoint")
+    fwd_bytes = sum(i["bytes_read"] + i["bytes_written"] for d, i in infos if d == "forward")
+    adj_bytes = sum(i["bytes_read"] + i["bytes_written"] for d, i in infos if d == "adjoint")
+    j = max(range(len(per)), key=lambda q: per[q])
+    dom_dir, dom = infos[j]
+    key = f"{dom_dir}:{dom['kind']}:{dom['level_first']}-{dom['level_last']}"
+    alg = dom["bytes_read"] + dom["bytes_written"]
+    achieved = alg / (per[j] / 1000.0) / 1e9
+    traffic = read_traffic(key)
+    kernels = [{"direction": d, "kind": i["kind"], "levels": [i["level_first"], i["level_last"]],
+                "ms": round(m, 4), "alg_gb_s": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6, 1)}
+               for m, (d, i) in zip(per, infos)]
+
+    out = {
+        "metric": "DM-trial*samples/sec (forward + adjoint step), Nf=4096",
+        "value": w.nd * w.nt / (ms_step / 1000.0),
+        "unit": "DM-trial*samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Nf=4096 channels 1.2-1.6 GHz, Nt=65536, Nd=2048; uint8 input "
+                               "clip(rint(64 + 8 N(0,1))), FP32 accumulation; step = forward + adjoint",
+                   "nf": w.nf, "nt": w.nt, "nd": w.nd, "batch": 1, "parallelism": "single GPU"},
+        "forward": {"ms": round(fwd_ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (fwd_ms / 1000.0),
+                    "alg_hbm_gb_s": round(fwd_bytes / fwd_ms / 1e6, 1)},
+        "adjoint": {"ms": round(adj_ms, 4), "alg_hbm_gb_s": round(adj_bytes / adj_ms / 1e6, 1)},
+        "adjoint_forward_ratio": round(adj_ms / fwd_ms, 3),
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": key, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+    if not args.no_forms:
+        out["precision_forms"] = {
+            "u8_in_f32_acc": forward_only(F, torch, w, torch.uint8, torch.float32),
+            "f16_in_f32_acc": forward_only(F, torch, w, torch.float16, torch.float32),
+            "f32_in_f32_acc": forward_only(F, torch, w, torch.float32, torch.float32),
+            "u8_in_i32_acc": forward_only(F, torch, w, torch.uint8, torch.int32),
+            "i32_in_i32_acc": forward_only(F, torch, w, torch.int32, torch.int32),
+        }
+    del x, g, y, xb, ws, plan
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,9 @@ typedef struct {
                              merges in LDS, 3 gather through the caches (0 = default: 3) */
   int32_t stream_tiles;   /* time tiles one staged-gather workgroup streams over, 1..65535 */
   int32_t gather_rows;    /* output rows per cache-gather workgroup: 1, 2, 4, 8 or 16 */
+  int32_t adjoint_levels; /* iterations per adjoint pass, 1..5 (0 = default 2) */
+  int32_t adjoint_last_levels; /* iterations folded into the last adjoint pass with the
+                                  transposed initialisation, 1..4 (0 = default 2) */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 3: "this decision

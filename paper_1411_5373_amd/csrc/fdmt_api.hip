@@ -54,6 +54,9 @@ fdmt_status_t upload(fdmt::Plan &p) {
   const size_t off_terms = reserve(p.fwd.terms.size() * sizeof(fdmt::Term));
   const size_t off_stage = reserve(p.fwd.stage.size() * sizeof(fdmt::Rec));
   const size_t off_psums = reserve(p.fwd.psums.size() * sizeof(fdmt::Rec));
+  const size_t off_adj_leaves = reserve(p.adj.leaves.size() * sizeof(fdmt::AdjLeaf));
+  const size_t off_adj_starts = reserve(p.adj.starts.size() * sizeof(int32_t));
+  const size_t off_adj_order = reserve(p.adj.order.size() * sizeof(int32_t));
   const size_t off_sterms = reserve(p.fwd.sterms.size() * sizeof(fdmt::StagedTerm));
   const size_t off_sheads = reserve(p.fwd.sheads.size() * sizeof(int32_t));
 
@@ -74,6 +77,12 @@ fdmt_status_t upload(fdmt::Plan &p) {
     std::memcpy(host.data() + off_stage, p.fwd.stage.data(), p.fwd.stage.size() * sizeof(fdmt::Rec));
   if (!p.fwd.psums.empty())
     std::memcpy(host.data() + off_psums, p.fwd.psums.data(), p.fwd.psums.size() * sizeof(fdmt::Rec));
+  if (!p.adj.leaves.empty())
+    std::memcpy(host.data() + off_adj_leaves, p.adj.leaves.data(), p.adj.leaves.size() * sizeof(fdmt::AdjLeaf));
+  if (!p.adj.starts.empty())
+    std::memcpy(host.data() + off_adj_starts, p.adj.starts.data(), p.adj.starts.size() * sizeof(int32_t));
+  if (!p.adj.order.empty())
+    std::memcpy(host.data() + off_adj_order, p.adj.order.data(), p.adj.order.size() * sizeof(int32_t));
   if (!p.fwd.sterms.empty())
     std::memcpy(host.data() + off_sterms, p.fwd.sterms.data(), p.fwd.sterms.size() * sizeof(fdmt::StagedTerm));
   if (!p.fwd.sheads.empty())
@@ -100,6 +109,9 @@ fdmt_status_t upload(fdmt::Plan &p) {
   p.dev_terms = reinterpret_cast<const int2 *>(base + off_terms);
   p.dev_stage = reinterpret_cast<const fdmt::Rec *>(base + off_stage);
   p.dev_psums = reinterpret_cast<const fdmt::Rec *>(base + off_psums);
+  p.dev_adj_leaves = reinterpret_cast<const int4 *>(base + off_adj_leaves);
+  p.dev_adj_starts = reinterpret_cast<const int32_t *>(base + off_adj_starts);
+  p.dev_adj_order = reinterpret_cast<const int32_t *>(base + off_adj_order);
   p.dev_sterms = reinterpret_cast<const int2 *>(base + off_sterms);
   p.dev_sheads = reinterpret_cast<const int32_t *>(base + off_sheads);
   e = fdmt::prepare_kernels(p);
@@ -137,7 +149,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
                         double f_max, const fdmt_options_t *opt) {
   if (!out) return fail(FDMT_E_INVALID, "out is NULL");
   *out = nullptr;
-  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (opt) o = *opt;
   if (nf < 1 || nf > 65536) return fail(FDMT_E_INVALID, "Nf must be in [1, 65536]");
   if ((nf & (nf - 1)) != 0) return fail(FDMT_E_UNSUPPORTED, "Nf must be a power of two");
@@ -157,6 +169,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "stream_tiles must be in [1, 65535]");
   if (o.gather_rows < 0 || o.gather_rows > 16 || (o.gather_rows & (o.gather_rows - 1)))
     return fail(FDMT_E_INVALID, "gather_rows must be 1, 2, 4, 8 or 16");
+  if (o.adjoint_levels < 0 || o.adjoint_levels > 5 || o.adjoint_last_levels < 0 || o.adjoint_last_levels > 4)
+    return fail(FDMT_E_INVALID, "adjoint_levels must be in [1, 5], adjoint_last_levels in [1, 4]");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED))
@@ -211,6 +225,20 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     } catch (const std::bad_alloc &) {
       delete h;
       return fail(FDMT_E_NOMEM, "host allocation of the schedule failed");
+    }
+  }
+  if (!(o.flags & FDMT_PLAN_UNFUSED)) {
+    try {
+      const int per = o.adjoint_levels ? o.adjoint_levels : 2;
+      const int last = o.adjoint_last_levels ? o.adjoint_last_levels : 2;
+      const std::string err = fdmt::build_adjoint_schedule(p.adj, p.tab, per, last);
+      if (!err.empty()) {
+        delete h;
+        return fail(FDMT_E_UNSUPPORTED, "adjoint schedule: " + err);
+      }
+    } catch (const std::bad_alloc &) {
+      delete h;
+      return fail(FDMT_E_NOMEM, "host allocation of the adjoint schedule failed");
     }
   }
   fdmt::plan_steps(p);
@@ -323,6 +351,19 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->staged_bytes = 2 * T.total[st.index] * nt * 4;
       info->adds = (T.total[st.index] * 2 - T.total[st.index - 1]) * nt;
       break;
+    case fdmt::Step::AdjGather: {
+      const fdmt::AdjPass &ps = P.adj.passes[st.index];
+      info->kind = 3;
+      info->level_first = ps.to_input ? 0 : ps.l_lo + 1;
+      info->level_last = ps.l_hi;
+      info->work_items = static_cast<int32_t>(((ps.nrows + P.gather_rows - 1) / P.gather_rows) *
+                                              ((nt + 4096 / P.gather_rows - 1) / (4096 / P.gather_rows)));
+      info->bytes_read = T.total[ps.l_hi] * nt * 4;
+      info->bytes_written = static_cast<int64_t>(ps.nrows) * nt * 4;
+      info->staged_bytes = ps.leaves * nt * 4;
+      info->adds = ps.leaves * nt;
+      break;
+    }
     case fdmt::Step::InitAdj:
       info->level_first = info->level_last = 0;
       info->work_items = T.nf;

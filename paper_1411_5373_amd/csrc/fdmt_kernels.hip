@@ -400,6 +400,85 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint over several iterations as a register gather. An output row (of
+// plane l_lo, or an input channel in the last pass) is a nested sum whose
+// leaves are rows of plane l_hi at accumulated shifts (AdjLeaf, host-built in
+// depth-first order). One accumulator per tree depth reproduces the order of
+// the level-by-level transpose exactly: before a leaf whose path leaves the
+// previous one below depth b, the finished nodes deeper than b are added to
+// their parents (deepest first) and restarted from zero; each leaf is added
+// to its parent at depth K-1. A leaf sample at or past nt is zero, which is
+// the transpose's "t + s < nt" rule. Leaves are loaded eight at a time, all
+// eight loads in flight before any is used.
+constexpr int kAdjChunk = 8;
+
+template <typename Tacc, int K>
+__global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
+    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
+    const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt,
+    int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+    int32_t nrows, int32_t rows_per_wg) {
+  typedef typename Vec4<Tacc>::type V;
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  const int t = (blockIdx.y * col_waves + wave % col_waves) * 256 + lane * 4;
+  if (t >= nt) return;
+  const Tacc *base = src + blockIdx.z * src_bstride;
+  const int x_begin = starts[r], x_end = starts[r + 1];
+  const int out_row = order[r];
+  V acc[K];
+#pragma unroll
+  for (int d = 0; d < K; ++d) acc[d] = V(0);
+  for (int x0 = x_begin; x0 < x_end; x0 += kAdjChunk) {
+    const int n = x_end - x0 < kAdjChunk ? x_end - x0 : kAdjChunk;
+    int4 e[kAdjChunk];
+    V v[kAdjChunk];
+#pragma unroll
+    for (int j = 0; j < kAdjChunk; ++j) {
+      if (j < n) {
+        e[j] = leaves[x0 + j];
+        const Tacc *row = base + e[j].x * src_stride;
+        const int ts = t + e[j].y;
+        if (ts + 4 <= nt) {
+          v[j] = *reinterpret_cast<const V *>(row + ts);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[j][i] = ts + i < nt ? row[ts + i] : Tacc(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kAdjChunk; ++j) {
+      if (j < n) {
+        if (x0 + j != x_begin) {
+          const int b = e[j].z;
+#pragma unroll
+          for (int d = K - 1; d >= 1; --d)
+            if (d > b) acc[d - 1] = acc[d - 1] + acc[d];
+#pragma unroll
+          for (int d = 1; d < K; ++d)
+            if (d > b) acc[d] = V(0);
+        }
+        acc[K - 1] = acc[K - 1] + v[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int d = K - 1; d >= 1; --d) acc[d - 1] = acc[d - 1] + acc[d];
+  Tacc *o = dst + blockIdx.z * dst_bstride + out_row * dst_stride + t;
+  if (t + 4 <= nt) {
+    *reinterpret_cast<V *>(o) = acc[0];
+  } else {
+    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = acc[0][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Staged gather over k fused iterations. A block is a row range of one
 // sub-band of plane l1; a workgroup keeps the block's tables in LDS and
 // streams over a run of time tiles. Per tile it stages, once each, the rows
@@ -759,6 +838,30 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
                          dst.bstride);
       break;
     }
+    case Step::AdjGather: {
+      const AdjPass &ps = p.adj.passes[st.index];
+      const int rpw = p.gather_rows;
+      const int tile = 256 * (kGatherThreads / 64 / rpw);
+      dim3 grid(static_cast<unsigned>((ps.nrows + rpw - 1) / rpw),
+                static_cast<unsigned>((nt + tile - 1) / tile), batch);
+      const int4 *lv = p.dev_adj_leaves + ps.leaf_offset;
+      const int32_t *sr = p.dev_adj_starts + ps.start_offset;
+      const int32_t *od = p.dev_adj_order + ps.order_offset;
+      const Tacc *sp = static_cast<const Tacc *>(src.ptr);
+      Tacc *dp = static_cast<Tacc *>(dst.ptr);
+      const int32_t nt32 = static_cast<int32_t>(nt);
+#define FDMT_ADJ(KK) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw)
+      switch (ps.depth) {
+        case 1: FDMT_ADJ(1); break;
+        case 2: FDMT_ADJ(2); break;
+        case 3: FDMT_ADJ(3); break;
+        case 4: FDMT_ADJ(4); break;
+        case 5: FDMT_ADJ(5); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef FDMT_ADJ
+      break;
+    }
     case Step::InitAdj: {
       dim3 grid(T.nf, tiles, batch);
       hipLaunchKernelGGL((init_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
@@ -803,10 +906,20 @@ void plan_steps(Plan &p) {
       if (i < n - 1) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[ps.l1]);
     }
   }
-  // Adjoint: one gather per iteration from the output back to plane 0, then
-  // the transpose of the initialisation.
+  // Adjoint: fused gathers (or, unfused, one gather per iteration from the
+  // output back to plane 0, then the transpose of the initialisation).
   if (L == 0) {
     p.adj_steps.push_back({Step::InitAdj, 0, Buf::In, Buf::Out});
+  } else if (!p.adj.passes.empty()) {
+    const int n = static_cast<int>(p.adj.passes.size());
+    const bool sep = p.adj.init_separate;
+    for (int i = 0; i < n; ++i) {
+      const AdjPass &ps = p.adj.passes[i];
+      const bool last = i == n - 1 && !sep;
+      p.adj_steps.push_back({Step::AdjGather, i, i == 0 ? Buf::In : ws(i - 1), last ? Buf::Out : ws(i)});
+      if (!last) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[ps.l_lo]);
+    }
+    if (sep) p.adj_steps.push_back({Step::InitAdj, 0, ws(n - 1), Buf::Out});
   } else {
     for (int l = L; l >= 1; --l)
       p.adj_steps.push_back({Step::MergeAdj, l, l == L ? Buf::In : ws(l), ws(l - 1)});

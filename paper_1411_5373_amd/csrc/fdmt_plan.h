@@ -30,7 +30,7 @@ enum class Buf { In, Out, Ws0, Ws1 };
 
 // One kernel launch of a transform.
 struct Step {
-  enum Kind { Init, Merge, Fused, MergeAdj, InitAdj } kind;
+  enum Kind { Init, Merge, Fused, MergeAdj, InitAdj, AdjGather } kind;
   int index;  // Merge/MergeAdj: iteration l; Fused: pass index in the schedule
   Buf src, dst;
 };
@@ -46,6 +46,10 @@ struct Plan {
   void *dbuf = nullptr;  // device copy of every table
   DeviceTables dev;
   Schedule fwd;                // fused forward schedule (empty when unfused)
+  AdjSchedule adj;             // fused adjoint schedule (empty when unfused)
+  const int4 *dev_adj_leaves = nullptr;
+  const int32_t *dev_adj_starts = nullptr;
+  const int32_t *dev_adj_order = nullptr;
   const Rec *dev_recs = nullptr;
   const int32_t *dev_heads = nullptr;
   const int2 *dev_terms = nullptr;

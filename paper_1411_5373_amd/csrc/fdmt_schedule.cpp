@@ -529,4 +529,100 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
   return "";
 }
 
+namespace {
+
+// Depth-first walk of one adjoint output row (see AdjLeaf).
+struct AdjWalker {
+  const Tables &t;
+  int l_hi;
+  std::vector<AdjLeaf> &out;
+
+  // Row r of plane l at accumulated shift sigma, tree depth d; `branch` is
+  // the branch depth handed to the first leaf below this node.
+  void visit(int l, int r, int sigma, int d, int branch) {
+    if (l == l_hi) {
+      out.push_back(AdjLeaf{r, sigma, branch, 0});
+      return;
+    }
+    const AdjRow &a = t.adj[l + 1][r];
+    for (int q = 0; q < a.count; ++q) {
+      const int p = a.first + q;
+      const int s = a.upper ? t.merge[l + 1][p].s : 0;
+      visit(l + 1, p, sigma + s, d + 1, q == 0 ? branch : d);
+    }
+  }
+};
+
+} // namespace
+
+std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels) {
+  s = AdjSchedule();
+  const int L = t.levels;
+  if (L == 0) return "";
+  if (levels_per_pass < 1 || last_levels < 1) return "bad adjoint schedule parameters";
+  // Fold the init transpose into the last pass only while its fan-out (the
+  // (d, i) pairs of a channel, quadratic in its partial-sum rows) is small;
+  // otherwise the passes stop at plane 0 and the transpose runs on its own.
+  int fan = 0;
+  for (int k = 0; k < t.nf; ++k) fan = std::max(fan, t.leaf_rows[k] * (t.leaf_rows[k] + 1) / 2);
+  s.init_separate = fan > 16;
+  int l_hi = L;
+  while (l_hi > 0) {
+    AdjPass ps;
+    ps.l_hi = l_hi;
+    // The last pass (down to the channels) takes the init transpose too.
+    if (l_hi <= last_levels && !s.init_separate) {
+      ps.l_lo = 0;
+      ps.to_input = true;
+      ps.depth = l_hi + 1;
+      ps.nrows = t.nf;
+    } else {
+      ps.l_lo = std::max(l_hi - levels_per_pass, s.init_separate ? 0 : last_levels);
+      ps.depth = l_hi - ps.l_lo;
+      ps.nrows = static_cast<int>(t.total[ps.l_lo]);
+    }
+    if (ps.depth > 5) return "adjoint pass deeper than 5";
+    ps.leaf_offset = static_cast<int64_t>(s.leaves.size());
+    ps.start_offset = static_cast<int64_t>(s.starts.size());
+    ps.order_offset = static_cast<int64_t>(s.order.size());
+    // Leaves of every output row, then the rows ordered by the first plane-l_hi
+    // row they read.
+    std::vector<std::vector<AdjLeaf>> per_row(ps.nrows);
+    for (int r = 0; r < ps.nrows; ++r) {
+      AdjWalker w{t, l_hi, per_row[r]};
+      if (ps.to_input) {
+        // channel r: partial-sum rows d at lags i, in (d, i) order; each starts
+        // a new child of the root (branch depth 0)
+        for (int d = 0; d < t.leaf_rows[r]; ++d)
+          for (int i = 0; i <= d; ++i) w.visit(0, t.leaf_off[r] + d, i, 1, 0);
+      } else {
+        w.visit(ps.l_lo, r, 0, 0, 0);
+      }
+    }
+    std::vector<int32_t> ord(ps.nrows);
+    for (int r = 0; r < ps.nrows; ++r) ord[r] = r;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+      return per_row[a].front().row < per_row[b].front().row;
+    });
+    for (int i = 0; i < ps.nrows; ++i) {
+      s.starts.push_back(static_cast<int32_t>(s.leaves.size() - ps.leaf_offset));
+      s.order.push_back(ord[i]);
+      const std::vector<AdjLeaf> &lv = per_row[ord[i]];
+      s.leaves.insert(s.leaves.end(), lv.begin(), lv.end());
+    }
+    s.starts.push_back(static_cast<int32_t>(s.leaves.size() - ps.leaf_offset));
+    ps.leaves = static_cast<int64_t>(s.leaves.size()) - ps.leaf_offset;
+    if (s.leaves.size() > static_cast<size_t>(INT32_MAX)) return "adjoint schedule too large";
+    // Audit: rows inside plane l_hi, shifts non-negative, branch depths valid.
+    for (int64_t x = ps.leaf_offset; x < static_cast<int64_t>(s.leaves.size()); ++x) {
+      const AdjLeaf &e = s.leaves[x];
+      if (e.row < 0 || e.row >= t.total[l_hi] || e.shift < 0 || e.branch < 0 || e.branch >= ps.depth)
+        return "adjoint leaf out of range";
+    }
+    s.passes.push_back(ps);
+    l_hi = ps.l_lo;
+  }
+  return "";
+}
+
 } // namespace fdmt

@@ -117,4 +117,41 @@ struct Schedule {
 // Builds the pass list and every block's node tree. Returns "" on success.
 std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p);
 
+// ---------------------------------------------------------------------------
+// Adjoint schedule. Each pass maps plane l_hi (the gradient of the output when
+// l_hi = levels) to plane l_lo, or to the input channels when `to_input`, in
+// which case it also applies the transpose of the Option-1 sums. Every output
+// row is a nested sum: a row of plane l adds, in ascending dt, the rows of
+// plane l+1 that read it (shifted by s when it is their upper half); a channel
+// adds its partial-sum rows d at lags i = 0..d, in (d, i) order. A leaf is a
+// row of plane l_hi with its accumulated shift and the depth of the deepest
+// tree node it shares with the previous leaf.
+struct AdjLeaf {
+  int32_t row, shift, branch, pad;
+};
+
+struct AdjPass {
+  int l_hi = 0, l_lo = 0;
+  bool to_input = false;
+  int depth = 0;              // tree depth: l_hi - l_lo, plus 1 with the init transpose
+  int nrows = 0;              // output rows (plane l_lo rows, or channels)
+  int64_t leaf_offset = 0;    // first leaf in AdjSchedule::leaves
+  int64_t start_offset = 0;   // first entry in AdjSchedule::starts (nrows + 1 per pass)
+  int64_t order_offset = 0;   // first entry in AdjSchedule::order (nrows per pass)
+  int64_t leaves = 0;         // leaves of this pass
+};
+
+struct AdjSchedule {
+  bool init_separate = false;   // passes end at plane 0; the init transpose runs on its own
+  std::vector<AdjPass> passes;
+  std::vector<AdjLeaf> leaves;
+  std::vector<int32_t> starts;  // per pass: leaf index (pass-relative) of each row, then the end
+  std::vector<int32_t> order;   // per pass: output row of each position (rows that share
+                                // leaves are neighbours, so they meet in one XCD's L2)
+};
+
+// Passes of at most `levels_per_pass` iterations from the output down to the
+// channels; the last pass includes the init transpose.
+std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels);
+
 } // namespace fdmt

@@ -107,10 +107,13 @@ def test_unknown_flag_rejected():
 def test_call_argument_errors_before_launch():
     """Fake (never dereferenced) pointers: every check fails before any launch."""
     lib = F.load()
+    unfused = _host_plan(64, 64, 1.2, 1.6, nt=1000, unfused=True)
+    # per-iteration schedule: two planes of the tallest (127-row) plane, padded Nt, per beam
+    assert unfused.workspace_bytes(2) == 2 * 2 * 127 * 1024 * 4
     p = _host_plan(64, 64, 1.2, 1.6, nt=1000)
     h = p.handle
     need = F.fdmt_workspace_bytes(h, 2)
-    assert need == 2 * 2 * 127 * 1024 * 4  # two planes of the tallest (127-row) plane, padded Nt
+    assert need == 2 * F.fdmt_workspace_bytes(h, 1) > 0
     assert F.fdmt_workspace_bytes(h, 0) == 0 and F.fdmt_workspace_bytes(None, 1) == 0
     x, y, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000)
     for fn in (lib.fdmt_forward, lib.fdmt_adjoint):
