@@ -142,6 +142,57 @@ def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0)}
 
 
+def ragged_c4(F, torch, W, reps=5):
+    """The ragged workload: 256 beams, Nf=1024, Nd=512, Nt log-uniform in
+    [2048, 32768], FP32 in and out. Times the ragged forward and adjoint (one
+    launch per step for all beams), the forward replayed from a captured HIP
+    graph, and, for comparison, a loop of per-beam calls."""
+    w = W.WORKLOADS["c4"]
+    lengths = [int(n) for n in W.c4_lengths()]
+    tot = sum(lengths)
+    plan = F.Plan(w.nf, max(lengths), w.nd, w.f_min, w.f_max)
+    r = F.RaggedPlan(plan, lengths)
+    x = W.torch_noise((w.nf * tot,), W.SEED_BASE + 40, "cuda")
+    g = W.torch_noise((w.nd * tot,), W.SEED_BASE + 41, "cuda")
+    y = torch.empty(w.nd * tot, device="cuda")
+    xb = torch.empty(w.nf * tot, device="cuda")
+    ws = r.workspace()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    fwd_ms = timed(lambda: r.forward(x, out=y, ws=ws))
+    adj_ms = timed(lambda: r.adjoint(g, out=xb, ws=ws))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        r.forward(x, out=y, ws=ws)
+    graph_ms = timed(graph.replay)
+    plans = [F.Plan(w.nf, n, w.nd, w.f_min, w.f_max) for n in lengths]
+    xs, ys = r.unpack(x, w.nf), r.unpack(y, w.nd)
+
+    def loop():
+        for p, xi, yi in zip(plans, xs, ys):
+            p.forward(xi, out=yi, ws=ws)
+    loop_ms = timed(loop)
+    rate = w.nd * tot / (fwd_ms / 1000.0)
+    return {"workload": f"{len(lengths)} beams, Nf={w.nf} 1.2-1.6 GHz, Nd={w.nd}, Nt log-uniform "
+                        f"2048-32768 (total {tot} samples), FP32",
+            "launches_forward_plus_adjoint": r.info()[2],
+            "forward_ms": round(fwd_ms, 4), "forward_graph_ms": round(graph_ms, 4),
+            "adjoint_ms": round(adj_ms, 4), "per_beam_loop_forward_ms": round(loop_ms, 4),
+            "forward_dm_trial_samples_per_s": rate}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +201,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="samples of the workload the CPU oracle baseline processes (0: skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -234,6 +286,10 @@ def main():
             "i32_in_i32_acc": forward_only(F, torch, w, torch.int32, torch.int32),
         }
     del x, g, y, xb, ws, plan
+    if not args.no_ragged:
+        torch.cuda.empty_cache()
+        out["ragged"] = ragged_c4(F, torch, W)
+        torch.cuda.empty_cache()
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)

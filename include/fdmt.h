@@ -1,14 +1,14 @@
 /*
  * fdmt.h - C ABI of the MI355X (gfx950) Fast Dispersion Measure Transform.
  *
- * The transform is the one of Zackay & Ofek, arXiv:1411.5373, Sec. 3 and
+ * The transform is the one of Zackay & Ofek, arXiv:1411.5373, Sec. 4 and
  * Algorithm 1: the input is an intensity matrix I[f][t] (channel 0 = lowest
- * frequency f_min, time contiguous, Sec. 3.2 "Memory access"), the output is
+ * frequency f_min, time contiguous, Sec. 4.2 "Memory access"), the output is
  * A[dt][t0] = the sum of I along the dispersion curve of Eq. (DtD) that
  * reaches f_min at sample t0 and spans dt samples across the band
  * (Eq. parametrization), for dt = 0 .. Nd-1 and t0 = 0 .. Nt-1.
  *
- * Discretisation (the paper leaves it to the implementation, Sec. 3.2
+ * Discretisation (the paper leaves it to the implementation, Sec. 4.2
  * "Rounding and binning"):
  *   - channel k covers [f_min + k*df, f_min + (k+1)*df), df = (f_max-f_min)/Nf;
  *   - the addition rule merges sub-bands [f0,f1) and [f1,f2) with f1 their
@@ -52,6 +52,7 @@ extern "C" {
 #endif
 
 typedef struct fdmt_plan_s *fdmt_plan_t;
+typedef struct fdmt_ragged_s *fdmt_ragged_t;
 
 typedef enum {
   FDMT_OK = 0,
@@ -102,8 +103,8 @@ typedef struct {
                                   transposed initialisation, 1..4 (0 = default 2) */
 } fdmt_options_t;
 
-/* Build a plan: the delay tables of every iteration (Sec. 3: "this decision
- * can be made prior to the computation") and the kernel schedule, then upload
+/* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
+ * sub-band needs are fixed before any data is seen) and the kernel schedule, then upload
  * the tables to the current HIP device.
  *   nf     channels, a power of two, 1 <= nf <= 65536
  *   nt     samples per beam, 1 <= nt <= 2^31 - 1
@@ -178,6 +179,56 @@ fdmt_status_t fdmt_plan_info(fdmt_plan_t p, int32_t *levels, int64_t *rows_per_l
 
 /* Release the plan and its device tables (must not be in use by queued work). NULL is a no-op. */
 fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p);
+
+/* Ragged batches. Beams of different lengths (a survey's beams, or records
+ * cut at different places) run through one plan's kernels together: every
+ * step of a transform is one launch over all beams (a further launch per
+ * 65535 time tiles of that step), so the beam count does not multiply the
+ * launch count. Beam b has nt[b] samples (0 allowed); the delay tables and
+ * schedule are the plan's, whose own Nt is not used. Results per beam are
+ * bit-identical to fdmt_forward()/fdmt_adjoint() of a plan with Nt = nt[b].
+ *
+ * Packed layout (dense, time fastest): beam b's [rows][nt[b]] block starts at
+ * element rows * (nt[0] + ... + nt[b-1]) of the buffer, rows = Nf for the
+ * forward input and the adjoint output, Nd for the forward output and the
+ * adjoint input. The plan must outlive the ragged plan, which owns one small
+ * device buffer (beam table and tile maps) and nothing else; the forward and
+ * adjoint calls allocate nothing and may be captured into a HIP graph.
+ * Many beams per device are the workload of Sec. 8 (an interferometer's
+ * synthesized beams, each dedispersed on its own).
+ *
+ * fdmt_ragged_plan errors: FDMT_E_INVALID (NULL pointer, nbeams < 1, an nt[b]
+ * outside [0, 2^31 - 1], device mismatch), FDMT_E_UNSUPPORTED (host-only plan,
+ * a plan whose passes use the staged-gather kernel, more than 2^31 - 1 padded
+ * samples in total), FDMT_E_NOMEM. */
+fdmt_status_t fdmt_ragged_plan(fdmt_ragged_t *out, fdmt_plan_t p, int32_t nbeams, const int64_t *nt);
+
+/* Workspace (bytes, 256-byte aligned) of a ragged forward or adjoint; 0 if r is NULL. */
+size_t fdmt_ragged_workspace_bytes(fdmt_ragged_t r);
+
+/* Forward transform of every beam of the batch.
+ * in  : device, packed [Nf][nt[b]] blocks, the plan's input dtype, read only
+ * out : device, packed [Nd][nt[b]] blocks, the accumulation dtype, fully overwritten
+ * A batch with no samples at all enqueues nothing and accepts NULL buffers. */
+fdmt_status_t fdmt_ragged_forward(fdmt_ragged_t r, const void *in, void *out, void *ws, size_t ws_bytes,
+                                  void *hip_stream);
+
+/* Adjoint of every beam: grad_out packed [Nd][nt[b]], grad_in packed [Nf][nt[b]],
+ * both in the accumulation dtype. */
+fdmt_status_t fdmt_ragged_adjoint(fdmt_ragged_t r, const void *grad_out, void *grad_in, void *ws,
+                                  size_t ws_bytes, void *hip_stream);
+
+/* Enqueues one step of a ragged forward (adjoint = 0) or adjoint (adjoint = 1);
+ * steps and their order are the plan's (fdmt_step_count). */
+fdmt_status_t fdmt_ragged_run_step(fdmt_ragged_t r, int32_t adjoint, int32_t step, const void *in, void *out,
+                                   void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Shape of a ragged plan: beams, total samples, and the kernel launches of one
+ * forward plus one adjoint (any pointer may be NULL). */
+fdmt_status_t fdmt_ragged_info(fdmt_ragged_t r, int32_t *nbeams, int64_t *total_nt, int32_t *launches);
+
+/* Release the ragged plan's device buffer (must not be in use by queued work). NULL is a no-op. */
+fdmt_status_t fdmt_ragged_destroy(fdmt_ragged_t r);
 
 /* Static description of a status code. */
 const char *fdmt_status_string(fdmt_status_t s);

@@ -7,7 +7,7 @@ with the HIP library.
 
 It follows Zackay & Ofek, "An accurate and efficient algorithm for detection
 of radio bursts with an unknown dispersion measure" (arXiv:1411.5373),
-Sec. 3 ("The FDMT Algorithm") and Algorithm 1, step by step, in plain NumPy:
+Sec. 4 ("The FDMT Algorithm") and Algorithm 1, step by step, in plain NumPy:
 one vector add per (iteration, sub-band, delay) row, as in the paper's
 vectorised form (caption of Fig. 2). Integer inputs are summed in int64,
 floating inputs in float64 after an exact upcast. An explicit `acc=np.float32`
@@ -24,7 +24,7 @@ earlier (Eq. parametrization). All planes are indexed [dt][t0].
 Readings where the paper is silent, garbled or inconsistent (each one is
 listed with its justification in the design notes):
   R-f1   f1 in the addition rule is the border frequency between the two
-         sub-bands, i.e. the midpoint of [f0, f2] (Sec. 3.2, "Dealing with the
+         sub-bands, i.e. the midpoint of [f0, f2] (Sec. 4.2, "Dealing with the
          case Nf != 2^k", names it the border frequency; "(f2-f0)/2" is a typo).
   R-t2   the upper half is A_{f1}^{f2}(t1, t1 - t2) (the second statement of the
          rule repeats it as t1 - t0, a typo).
@@ -51,11 +51,11 @@ import numpy as np
 
 
 # ----------------------------------------------------------------------------
-# Frequency grid and merge coefficient (Sec. 1 Eq. DtD, Sec. 3 Eq. Cf2f0)
+# Frequency grid and merge coefficient (Sec. 1 Eq. DtD, Sec. 4 Eq. Cf2f0)
 # ----------------------------------------------------------------------------
 
 def channel_edges(nf, f_min, f_max):
-    """Edges e_k = f_min + k*delta_f, delta_f = (f_max - f_min)/N_f (Sec. 3,
+    """Edges e_k = f_min + k*delta_f, delta_f = (f_max - f_min)/N_f (Sec. 4,
     definition of delta_f under the simple initialization), k = 0..N_f."""
     delta_f = (f_max - f_min) / nf
     return [f_min + k * delta_f for k in range(nf + 1)]
@@ -77,7 +77,7 @@ def round_half_up(x):
 
 
 # ----------------------------------------------------------------------------
-# Delay tables (Sec. 3: t1 = t0 - C*dt; dt_max decided before the computation)
+# Delay tables (Sec. 4: t1 = t0 - C*dt; dt_max decided before the computation)
 # ----------------------------------------------------------------------------
 
 @dataclass
@@ -147,7 +147,7 @@ def _acc_dtype(x, acc=None):
 
 
 def initialize(img, tables, acc=None):
-    """Option 1 (Sec. 3): A_f^{f+df}(t, dt) = sum_{i=0}^{dt} I(f, t - i) for
+    """Option 1 (Sec. 4): A_f^{f+df}(t, dt) = sum_{i=0}^{dt} I(f, t - i) for
     dt = 0..rows[0][k]-1, with I = 0 before the record starts (readings R-init,
     R-copy). Built as the chain A(t, dt) = A(t, dt-1) + I(f, t - dt)."""
     img = np.asarray(img)
@@ -288,7 +288,7 @@ def brute_row(img, tables, dt):
 
 
 def brute_ideal(img, f_min, f_max, nd):
-    """Brute-force dedispersion along the exact law (prior-art comparator, Sec. 2):
+    """Brute-force dedispersion along the exact law (prior-art comparator, Sec. 3):
     each channel contributes I[k][t0 - round(dt * phi(centre_k))]."""
     img = np.asarray(img)
     nf, nt = img.shape

@@ -24,7 +24,9 @@ FDMT_PLAN_UNFUSED = 0x2
 EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_step_count", "fdmt_step_info", "fdmt_run_step",
             "fdmt_plan_tables", "fdmt_plan_info", "fdmt_plan_destroy",
-            "fdmt_status_string", "fdmt_last_error")
+            "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
+            "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
+            "fdmt_ragged_destroy", "fdmt_status_string", "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "fused", "iteration_adjoint", "init_adjoint")
 
@@ -93,6 +95,20 @@ def load():
     lib.fdmt_plan_info.restype = ctypes.c_int
     lib.fdmt_plan_destroy.argtypes = [vp]
     lib.fdmt_plan_destroy.restype = ctypes.c_int
+    lib.fdmt_ragged_plan.argtypes = [ctypes.POINTER(vp), vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.fdmt_ragged_plan.restype = ctypes.c_int
+    lib.fdmt_ragged_workspace_bytes.argtypes = [vp]
+    lib.fdmt_ragged_workspace_bytes.restype = sz
+    for name in ("fdmt_ragged_forward", "fdmt_ragged_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp, sz, vp]
+        f.restype = ctypes.c_int
+    lib.fdmt_ragged_run_step.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
+    lib.fdmt_ragged_run_step.restype = ctypes.c_int
+    lib.fdmt_ragged_info.argtypes = [vp, p_i32, ctypes.POINTER(ctypes.c_int64), p_i32]
+    lib.fdmt_ragged_info.restype = ctypes.c_int
+    lib.fdmt_ragged_destroy.argtypes = [vp]
+    lib.fdmt_ragged_destroy.restype = ctypes.c_int
     lib.fdmt_status_string.argtypes = [ctypes.c_int]
     lib.fdmt_status_string.restype = ctypes.c_char_p
     lib.fdmt_last_error.argtypes = []
@@ -192,6 +208,46 @@ def fdmt_plan_destroy(plan):
         _check(load().fdmt_plan_destroy(plan), "fdmt_plan_destroy")
 
 
+def fdmt_ragged_plan(plan, nts):
+    """Ragged batch over `plan`'s kernels: beams of nts[b] samples. Returns a handle."""
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * max(1, len(nts)))(*[int(n) for n in nts])
+    _check(load().fdmt_ragged_plan(ctypes.byref(h), plan, len(nts), arr), "fdmt_ragged_plan")
+    return h.value
+
+
+def fdmt_ragged_workspace_bytes(ragged):
+    return int(load().fdmt_ragged_workspace_bytes(ragged))
+
+
+def fdmt_ragged_forward(ragged, in_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_ragged_forward(ragged, in_ptr, out_ptr, ws_ptr, int(ws_bytes), stream),
+           "fdmt_ragged_forward")
+
+
+def fdmt_ragged_adjoint(ragged, grad_out_ptr, grad_in_ptr, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_ragged_adjoint(ragged, grad_out_ptr, grad_in_ptr, ws_ptr, int(ws_bytes), stream),
+           "fdmt_ragged_adjoint")
+
+
+def fdmt_ragged_run_step(ragged, adjoint, step, in_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_ragged_run_step(ragged, int(bool(adjoint)), int(step), in_ptr, out_ptr, ws_ptr,
+                                       int(ws_bytes), stream), "fdmt_ragged_run_step")
+
+
+def fdmt_ragged_info(ragged):
+    """Returns (beams, total samples, launches of one forward plus one adjoint)."""
+    nb, tot, nl = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+    _check(load().fdmt_ragged_info(ragged, ctypes.byref(nb), ctypes.byref(tot), ctypes.byref(nl)),
+           "fdmt_ragged_info")
+    return nb.value, tot.value, nl.value
+
+
+def fdmt_ragged_destroy(ragged):
+    if ragged:
+        _check(load().fdmt_ragged_destroy(ragged), "fdmt_ragged_destroy")
+
+
 # ----------------------------------------------------------------- tensor layer
 
 def _stream_handle(device):
@@ -272,6 +328,82 @@ class Plan:
 
     def info(self):
         return fdmt_plan_info(self.handle)
+
+
+class RaggedPlan:
+    """Beams of different lengths through one plan's kernels, one launch per
+    step for the whole batch. Buffers are packed: beam b's [rows][nt[b]] block
+    starts at element rows * (nt[0] + ... + nt[b-1]) of a 1-D tensor."""
+
+    def __init__(self, plan, lengths):
+        self.plan = plan  # keeps the plan alive while this handle exists
+        self.lengths = [int(n) for n in lengths]
+        self.total = sum(self.lengths)
+        self.offsets = [0]
+        for n in self.lengths:
+            self.offsets.append(self.offsets[-1] + n)
+        self.device = plan.device
+        self.handle = None
+        self.handle = fdmt_ragged_plan(plan.handle, self.lengths)
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.fdmt_ragged_destroy(h)
+
+    def workspace_bytes(self):
+        return fdmt_ragged_workspace_bytes(self.handle)
+
+    def workspace(self):
+        return torch.empty(max(self.workspace_bytes(), 1), dtype=torch.uint8, device=self.device)
+
+    def pack(self, beams):
+        """Concatenate [rows][nt[b]] tensors into one packed 1-D tensor."""
+        if len(beams) != len(self.lengths):
+            raise ValueError(f"expected {len(self.lengths)} beams, got {len(beams)}")
+        for b, (x, n) in enumerate(zip(beams, self.lengths)):
+            if x.dim() != 2 or x.shape[1] != n:
+                raise ValueError(f"beam {b}: expected [rows, {n}], got {tuple(x.shape)}")
+        return torch.cat([x.reshape(-1) for x in beams])
+
+    def unpack(self, packed, rows):
+        """Views [rows][nt[b]] of a packed tensor, one per beam."""
+        return [packed[rows * a:rows * b].view(rows, b - a)
+                for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def _run(self, fn, x, out, rows_in, rows_out, dtype_in, dtype_out, ws):
+        if x.device != self.device:
+            raise ValueError(f"tensor on {x.device}, plan on {self.device}")
+        if x.dtype != dtype_in:
+            raise TypeError(f"expected {dtype_in}, got {x.dtype}")
+        if x.dim() != 1 or x.numel() != rows_in * self.total or not x.is_contiguous():
+            raise ValueError(f"expected a contiguous 1-D tensor of {rows_in * self.total} elements")
+        if out is None:
+            out = torch.empty(rows_out * self.total, dtype=dtype_out, device=self.device)
+        elif (out.dim() != 1 or out.numel() != rows_out * self.total or out.dtype != dtype_out
+              or not out.is_contiguous()):
+            raise ValueError("out has the wrong size, dtype or layout")
+        if ws is None:
+            ws = self.workspace()
+        fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(self.device))
+        return out
+
+    def forward(self, x, out=None, ws=None):
+        p = self.plan
+        return self._run(fdmt_ragged_forward, x, out, p.nf, p.nd, p.in_dtype, p.acc_dtype, ws)
+
+    def adjoint(self, g, out=None, ws=None):
+        p = self.plan
+        return self._run(fdmt_ragged_adjoint, g, out, p.nd, p.nf, p.acc_dtype, p.acc_dtype, ws)
+
+    def run_step(self, adjoint, step, x, out, ws):
+        fdmt_ragged_run_step(self.handle, adjoint, step, ctypes.c_void_p(x.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream_handle(self.device))
+
+    def info(self):
+        return fdmt_ragged_info(self.handle)
 
 
 class FDMTFunction(torch.autograd.Function):

@@ -14,6 +14,13 @@ struct fdmt_plan_s {
   fdmt::Plan plan;
 };
 
+struct fdmt_ragged_s {
+  fdmt_plan_t plan = nullptr;  // borrowed; must outlive the ragged plan
+  fdmt::RaggedBatch rb;
+  void *dbuf = nullptr;        // beam table and tile maps
+  int device = -1;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -138,6 +145,24 @@ fdmt_status_t check_call(fdmt_plan_t p, const void *a, const void *b, int32_t ba
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
   if (dev != p->plan.device)
     return fail(FDMT_E_INVALID, "current device differs from the plan's device");
+  return FDMT_OK;
+}
+
+fdmt_status_t check_ragged(fdmt_ragged_t r, const void *a, const void *b, void *ws, size_t ws_bytes) {
+  if (!r) return fail(FDMT_E_INVALID, "ragged plan is NULL");
+  if (r->rb.sum_nt == 0) return FDMT_OK;  // nothing to read or write
+  if (!a || !b) return fail(FDMT_E_INVALID, "input or output pointer is NULL");
+  if (a == b) return fail(FDMT_E_INVALID, "input and output alias");
+  const size_t need = static_cast<size_t>(2) * r->plan->plan.ws_rows * r->rb.sum_ntp * 4;
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(FDMT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
+                                      std::to_string(ws ? ws_bytes : 0));
+  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+    return fail(FDMT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev != r->device) return fail(FDMT_E_INVALID, "current device differs from the plan's device");
   return FDMT_OK;
 }
 
@@ -427,6 +452,162 @@ fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p) {
     if (e != hipSuccess) s = device_fail(e, "hipFree of delay tables");
   }
   delete p;
+  return s;
+}
+
+fdmt_status_t fdmt_ragged_plan(fdmt_ragged_t *out, fdmt_plan_t p, int32_t nbeams, const int64_t *nt) {
+  if (!out) return fail(FDMT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(FDMT_E_INVALID, "plan is NULL");
+  if (!nt) return fail(FDMT_E_INVALID, "nt is NULL");
+  if (nbeams < 1) return fail(FDMT_E_INVALID, "nbeams must be at least 1");
+  const fdmt::Plan &P = p->plan;
+  int64_t sum = 0, sump = 0;
+  for (int32_t b = 0; b < nbeams; ++b) {
+    if (nt[b] < 0 || nt[b] > INT32_MAX)
+      return fail(FDMT_E_INVALID, "beam " + std::to_string(b) + ": Nt must be in [0, 2^31 - 1]");
+    sum += nt[b];
+    sump += fdmt::round_up(nt[b], fdmt::kRowAlign);
+    if (sump > INT32_MAX) return fail(FDMT_E_UNSUPPORTED, "total samples of the batch exceed 2^31 - 1");
+  }
+  // Tile widths of every step of both transforms.
+  std::vector<int> widths;
+  for (int adj = 0; adj < 2; ++adj) {
+    const int n = static_cast<int>(adj ? P.adj_steps.size() : P.fwd_steps.size());
+    for (int i = 0; i < n; ++i) {
+      const int w = fdmt::step_tile(P, adj != 0, i);
+      if (w <= 0) return fail(FDMT_E_UNSUPPORTED, "the plan's staged-gather passes have no ragged form");
+      if (std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+    }
+  }
+  if (P.flags & FDMT_PLAN_HOST_ONLY)
+    return fail(FDMT_E_UNSUPPORTED, "plan was built with FDMT_PLAN_HOST_ONLY");
+  auto *h = new (std::nothrow) fdmt_ragged_s;
+  if (!h) return fail(FDMT_E_NOMEM, "host allocation of the ragged plan failed");
+  std::vector<int4> beams(nbeams);
+  std::vector<std::vector<int2>> maps(widths.size());
+  try {
+    int64_t off = 0, poff = 0;
+    for (int32_t b = 0; b < nbeams; ++b) {
+      const int64_t ntp = fdmt::round_up(nt[b], fdmt::kRowAlign);
+      beams[b] = make_int4(static_cast<int>(nt[b]), static_cast<int>(ntp), static_cast<int>(off),
+                           static_cast<int>(poff));
+      off += nt[b];
+      poff += ntp;
+      for (size_t m = 0; m < widths.size(); ++m)
+        for (int64_t j = 0; j * widths[m] < nt[b]; ++j) maps[m].push_back(make_int2(b, static_cast<int>(j)));
+    }
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(FDMT_E_NOMEM, "host allocation of the tile maps failed");
+  }
+  size_t bytes = fdmt::round_up(static_cast<int64_t>(beams.size() * sizeof(int4)), 256);
+  std::vector<size_t> map_off(widths.size());
+  for (size_t m = 0; m < widths.size(); ++m) {
+    map_off[m] = bytes;
+    bytes += fdmt::round_up(static_cast<int64_t>(std::max<size_t>(1, maps[m].size()) * sizeof(int2)), 256);
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  std::memcpy(host.data(), beams.data(), beams.size() * sizeof(int4));
+  for (size_t m = 0; m < widths.size(); ++m)
+    if (!maps[m].empty()) std::memcpy(host.data() + map_off[m], maps[m].data(), maps[m].size() * sizeof(int2));
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return device_fail(e, "hipGetDevice");
+  }
+  if (h->device != P.device) {
+    delete h;
+    return fail(FDMT_E_INVALID, "current device differs from the plan's device");
+  }
+  e = hipMalloc(&h->dbuf, bytes);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(FDMT_E_NOMEM, std::string("hipMalloc of the tile maps: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(h->dbuf, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(h->dbuf);
+    delete h;
+    return device_fail(e, "hipMemcpy of the tile maps");
+  }
+  auto *base = static_cast<unsigned char *>(h->dbuf);
+  h->plan = p;
+  h->rb.nbeams = nbeams;
+  h->rb.sum_nt = sum;
+  h->rb.sum_ntp = sump;
+  h->rb.beam = reinterpret_cast<const int4 *>(base);
+  for (size_t m = 0; m < widths.size(); ++m)
+    h->rb.maps.push_back({widths[m], static_cast<int64_t>(maps[m].size()),
+                          reinterpret_cast<const int2 *>(base + map_off[m])});
+  *out = h;
+  return FDMT_OK;
+}
+
+size_t fdmt_ragged_workspace_bytes(fdmt_ragged_t r) {
+  if (!r) return 0;
+  return static_cast<size_t>(2) * r->plan->plan.ws_rows * r->rb.sum_ntp * 4;
+}
+
+fdmt_status_t fdmt_ragged_forward(fdmt_ragged_t r, const void *in, void *out, void *ws, size_t ws_bytes,
+                                  void *hip_stream) {
+  fdmt_status_t s = check_ragged(r, in, out, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  hipError_t e = fdmt::launch_forward(r->plan->plan, in, out, 1, ws, static_cast<hipStream_t>(hip_stream), &r->rb);
+  if (e != hipSuccess) return device_fail(e, "fdmt_ragged_forward launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_ragged_adjoint(fdmt_ragged_t r, const void *grad_out, void *grad_in, void *ws,
+                                  size_t ws_bytes, void *hip_stream) {
+  fdmt_status_t s = check_ragged(r, grad_out, grad_in, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  hipError_t e = fdmt::launch_adjoint(r->plan->plan, grad_out, grad_in, 1, ws, static_cast<hipStream_t>(hip_stream), &r->rb);
+  if (e != hipSuccess) return device_fail(e, "fdmt_ragged_adjoint launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_ragged_run_step(fdmt_ragged_t r, int32_t adjoint, int32_t step, const void *in, void *out,
+                                   void *ws, size_t ws_bytes, void *hip_stream) {
+  fdmt_status_t s = check_ragged(r, in, out, ws, ws_bytes);
+  if (s != FDMT_OK) return s;
+  const fdmt::Plan &P = r->plan->plan;
+  const auto &steps = adjoint ? P.adj_steps : P.fwd_steps;
+  if (step < 0 || step >= static_cast<int32_t>(steps.size()))
+    return fail(FDMT_E_INVALID, "step out of range");
+  hipError_t e = fdmt::run_step(P, adjoint != 0, step, in, out, 1, ws, static_cast<hipStream_t>(hip_stream), &r->rb);
+  if (e != hipSuccess) return device_fail(e, "fdmt_ragged_run_step launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_ragged_info(fdmt_ragged_t r, int32_t *nbeams, int64_t *total_nt, int32_t *launches) {
+  if (!r) return fail(FDMT_E_INVALID, "ragged plan is NULL");
+  if (nbeams) *nbeams = r->rb.nbeams;
+  if (total_nt) *total_nt = r->rb.sum_nt;
+  if (launches) {
+    const fdmt::Plan &P = r->plan->plan;
+    int32_t n = 0;
+    for (int adj = 0; adj < 2; ++adj) {
+      const int k = static_cast<int>(adj ? P.adj_steps.size() : P.fwd_steps.size());
+      for (int i = 0; i < k; ++i) {
+        const int w = fdmt::step_tile(P, adj != 0, i);
+        for (const fdmt::RaggedBatch::Map &m : r->rb.maps)
+          if (m.tile == w) n += static_cast<int32_t>((m.count + 65534) / 65535);
+      }
+    }
+    *launches = n;
+  }
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_ragged_destroy(fdmt_ragged_t r) {
+  if (!r) return FDMT_OK;
+  fdmt_status_t s = FDMT_OK;
+  if (r->dbuf) {
+    hipError_t e = hipFree(r->dbuf);
+    if (e != hipSuccess) s = device_fail(e, "hipFree of the tile maps");
+  }
+  delete r;
   return s;
 }
 

@@ -31,22 +31,66 @@ __device__ __forceinline__ float widen<float, _Float16>(_Float16 x) {
   return static_cast<float>(x);
 }
 
+// Where a workgroup's beam lives. Uniform batches take the beam from
+// blockIdx.z and share one Nt; ragged batches look the tile (blockIdx.y) up in
+// host-built maps: beam b has its own Nt, its input/output start at
+// rows * (samples of the beams before it) and its workspace planes at
+// rows * (padded samples before it).
+struct RaggedMap {
+  const int4 *beam;   // per beam: {nt, padded nt, first sample, first padded sample}
+  const int2 *tiles;  // per tile of the launch: {beam, tile within the beam}
+  int32_t src_rows, dst_rows;      // rows per beam of the source / destination buffer
+  int32_t src_padded, dst_padded;  // 1: workspace plane (row stride = padded nt)
+};
+
+struct BeamSpan {
+  int nt, tile;                    // samples of the beam; tile index within the beam
+  int64_t src_off, dst_off;        // element offsets of the beam in src / dst
+  int64_t src_stride, dst_stride;  // row strides (elements)
+};
+
+template <bool RAGGED>
+__device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64_t src_stride,
+                                              int64_t src_bstride, int64_t dst_stride,
+                                              int64_t dst_bstride) {
+  BeamSpan b;
+  if constexpr (RAGGED) {
+    const int2 tb = rg.tiles[blockIdx.y];
+    const int4 bm = rg.beam[tb.x];
+    b.nt = bm.x;
+    b.tile = tb.y;
+    b.src_off = static_cast<int64_t>(rg.src_rows) * (rg.src_padded ? bm.w : bm.z);
+    b.dst_off = static_cast<int64_t>(rg.dst_rows) * (rg.dst_padded ? bm.w : bm.z);
+    b.src_stride = rg.src_padded ? bm.y : bm.x;
+    b.dst_stride = rg.dst_padded ? bm.y : bm.x;
+  } else {
+    b.nt = nt;
+    b.tile = blockIdx.y;
+    b.src_off = blockIdx.z * src_bstride;
+    b.dst_off = blockIdx.z * dst_bstride;
+    b.src_stride = src_stride;
+    b.dst_stride = dst_stride;
+  }
+  return b;
+}
+
 // ---------------------------------------------------------------------------
-// Option-1 initialisation (Sec. 3): row d of channel k holds
+// Option-1 initialisation (Sec. 4): row d of channel k holds
 // sum_{i=0}^{d} I[k][t - i], zero before t = 0. Grid: (channel, time tile, beam).
-template <typename Tin, typename Tacc>
+template <typename Tin, typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void init_kernel(
     const Tin *__restrict__ in, Tacc *__restrict__ out, const int32_t *__restrict__ leaf_off,
-    const int32_t *__restrict__ leaf_rows, int64_t nt, int64_t in_bstride, int64_t out_stride,
-    int64_t out_bstride) {
+    const int32_t *__restrict__ leaf_rows, int64_t nt_u, int64_t in_bstride, int64_t out_stride_u,
+    int64_t out_bstride, RaggedMap rg) {
   const int k = blockIdx.x;
-  const int64_t b = blockIdx.z;
-  const Tin *x = in + b * in_bstride + static_cast<int64_t>(k) * nt;
-  Tacc *o = out + b * out_bstride + static_cast<int64_t>(leaf_off[k]) * out_stride;
+  const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), nt_u, in_bstride, out_stride_u, out_bstride);
+  const int64_t nt = bs.nt, out_stride = bs.dst_stride;
+  const Tin *x = in + bs.src_off + static_cast<int64_t>(k) * nt;
+  Tacc *o = out + bs.dst_off + static_cast<int64_t>(leaf_off[k]) * out_stride;
   const int n = leaf_rows[k];
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
-    const int64_t t = static_cast<int64_t>(blockIdx.y) * kTile + i * kThreads + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(bs.tile) * kTile + i * kThreads + threadIdx.x;
     if (t >= nt) break;
     Tacc acc = 0;
     for (int d = 0; d < n; ++d) {
@@ -58,21 +102,22 @@ __global__ __launch_bounds__(kThreads) void init_kernel(
 
 // One iteration: out[r][t] = prev[lo][t] + (t >= s ? prev[hi][t - s] : 0).
 // Grid: (plane row, time tile, beam).
-template <typename Tacc>
+template <typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void merge_kernel(
     const Tacc *__restrict__ prev, Tacc *__restrict__ next, const int4 *__restrict__ rows,
-    int64_t nt, int64_t prev_stride, int64_t prev_bstride, int64_t next_stride,
-    int64_t next_bstride) {
+    int64_t nt_u, int64_t prev_stride_u, int64_t prev_bstride, int64_t next_stride_u,
+    int64_t next_bstride, RaggedMap rg) {
   const int r = blockIdx.x;
-  const int64_t b = blockIdx.z;
+  const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), prev_stride_u, prev_bstride, next_stride_u, next_bstride);
+  const int64_t nt = bs.nt;
   const int4 e = rows[r];
-  const Tacc *lo = prev + b * prev_bstride + static_cast<int64_t>(e.x) * prev_stride;
-  const Tacc *hi = prev + b * prev_bstride + static_cast<int64_t>(e.y) * prev_stride;
-  Tacc *o = next + b * next_bstride + static_cast<int64_t>(r) * next_stride;
+  const Tacc *lo = prev + bs.src_off + static_cast<int64_t>(e.x) * bs.src_stride;
+  const Tacc *hi = prev + bs.src_off + static_cast<int64_t>(e.y) * bs.src_stride;
+  Tacc *o = next + bs.dst_off + static_cast<int64_t>(r) * bs.dst_stride;
   const int64_t s = e.z;
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
-    const int64_t t = static_cast<int64_t>(blockIdx.y) * kTile + i * kThreads + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(bs.tile) * kTile + i * kThreads + threadIdx.x;
     if (t >= nt) break;
     Tacc v = lo[t];
     if (t >= s) v += hi[t - s];
@@ -83,19 +128,20 @@ __global__ __launch_bounds__(kThreads) void merge_kernel(
 // Transpose of one iteration: child row r of plane l-1 gathers the `count`
 // consecutive parent rows that read it, in ascending dt, shifted back by the
 // parent's s if it is their upper half. Grid: (child row, time tile, beam).
-template <typename Tacc>
+template <typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void merge_adjoint_kernel(
     const Tacc *__restrict__ parent, Tacc *__restrict__ child, const int4 *__restrict__ adj,
-    const int4 *__restrict__ fwd, int64_t nt, int64_t parent_stride, int64_t parent_bstride,
-    int64_t child_stride, int64_t child_bstride) {
+    const int4 *__restrict__ fwd, int64_t nt_u, int64_t parent_stride_u, int64_t parent_bstride,
+    int64_t child_stride_u, int64_t child_bstride, RaggedMap rg) {
   const int r = blockIdx.x;
-  const int64_t b = blockIdx.z;
+  const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), parent_stride_u, parent_bstride, child_stride_u, child_bstride);
+  const int64_t nt = bs.nt, parent_stride = bs.src_stride;
   const int4 a = adj[r];
-  const Tacc *g = parent + b * parent_bstride;
-  Tacc *o = child + b * child_bstride + static_cast<int64_t>(r) * child_stride;
+  const Tacc *g = parent + bs.src_off;
+  Tacc *o = child + bs.dst_off + static_cast<int64_t>(r) * bs.dst_stride;
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
-    const int64_t t = static_cast<int64_t>(blockIdx.y) * kTile + i * kThreads + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(bs.tile) * kTile + i * kThreads + threadIdx.x;
     if (t >= nt) break;
     Tacc acc = 0;
     for (int p = a.x; p < a.x + a.y; ++p) {
@@ -108,19 +154,20 @@ __global__ __launch_bounds__(kThreads) void merge_adjoint_kernel(
 
 // Transpose of the initialisation: grad_I[k][t] = sum_d sum_{i<=d} P_bar[d][t + i].
 // Grid: (channel, time tile, beam).
-template <typename Tacc>
+template <typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void init_adjoint_kernel(
     const Tacc *__restrict__ plane, Tacc *__restrict__ out, const int32_t *__restrict__ leaf_off,
-    const int32_t *__restrict__ leaf_rows, int64_t nt, int64_t plane_stride,
-    int64_t plane_bstride, int64_t out_bstride) {
+    const int32_t *__restrict__ leaf_rows, int64_t nt_u, int64_t plane_stride_u,
+    int64_t plane_bstride, int64_t out_bstride, RaggedMap rg) {
   const int k = blockIdx.x;
-  const int64_t b = blockIdx.z;
-  const Tacc *g = plane + b * plane_bstride + static_cast<int64_t>(leaf_off[k]) * plane_stride;
-  Tacc *o = out + b * out_bstride + static_cast<int64_t>(k) * nt;
+  const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), plane_stride_u, plane_bstride, nt_u, out_bstride);
+  const int64_t nt = bs.nt, plane_stride = bs.src_stride;
+  const Tacc *g = plane + bs.src_off + static_cast<int64_t>(leaf_off[k]) * plane_stride;
+  Tacc *o = out + bs.dst_off + static_cast<int64_t>(k) * nt;
   const int n = leaf_rows[k];
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
-    const int64_t t = static_cast<int64_t>(blockIdx.y) * kTile + i * kThreads + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(bs.tile) * kTile + i * kThreads + threadIdx.x;
     if (t >= nt) break;
     Tacc acc = 0;
     for (int d = 0; d < n; ++d)
@@ -176,16 +223,17 @@ __device__ __forceinline__ Tacc chain(const Tacc *x, int c, int n) {
   return v;
 }
 
-template <typename Tin, typename Tacc, bool FROM_INPUT>
-__global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) {
+template <typename Tin, typename Tacc, bool FROM_INPUT, bool RAGGED>
+__global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a, RaggedMap rg) {
   extern __shared__ __align__(16) unsigned char smem[];
   Tacc *buf_a = reinterpret_cast<Tacc *>(smem);
   Tacc *buf_b = buf_a + a.lds_a;
   Rec *lrec = reinterpret_cast<Rec *>(buf_b + a.lds_b);
 
   const int blk = xcd_local_order(blockIdx.x, a.nblocks);
-  const int T0 = blockIdx.y * a.tile;
-  const int64_t beam = blockIdx.z;
+  const BeamSpan bs = beam_span<RAGGED>(rg, a.nt, a.src_stride, a.src_bstride, a.dst_stride, a.dst_bstride);
+  const int nt = bs.nt;
+  const int T0 = bs.tile * a.tile;
   const int wave = uniform(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
   const int32_t *head = a.heads + blk * kRecHeader;
@@ -206,7 +254,7 @@ __global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) 
   // writing any of them to LDS.
   {
     typedef typename std::conditional<FROM_INPUT, Tin, Tacc>::type Tsrc;
-    const Tsrc *in_base = static_cast<const Tsrc *>(a.src) + beam * a.src_bstride;
+    const Tsrc *in_base = static_cast<const Tsrc *>(a.src) + bs.src_off;
     for (int q0 = wave; q0 < nstage; q0 += 2 * kWaves) {
       Tacc v[2][8];
       int wd[2], dst[2];
@@ -218,15 +266,15 @@ __global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) 
         if (q < nstage) {
           const Rec e = lrec[q];
           const int t0 = T0 - e.d;
-          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * a.nt
-                                                  : static_cast<int64_t>(e.a) * a.src_stride);
+          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * nt
+                                                  : static_cast<int64_t>(e.a) * bs.src_stride);
           wd[m] = e.e;
           dst[m] = e.c;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int c = 64 * j + lane;
             const int t = t0 + c;
-            v[m][j] = (c < e.e && t >= 0 && t < a.nt) ? widen<Tacc>(row[t]) : Tacc(0);
+            v[m][j] = (c < e.e && t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
           }
         }
       }
@@ -240,11 +288,11 @@ __global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) 
         if (wd[m] > 512) {  // rare: rows wider than 512 columns
           const Rec e = lrec[q0 + m * kWaves];
           const int t0 = T0 - e.d;
-          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * a.nt
-                                                  : static_cast<int64_t>(e.a) * a.src_stride);
+          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * nt
+                                                  : static_cast<int64_t>(e.a) * bs.src_stride);
           for (int c = 512 + lane; c < e.e; c += 64) {
             const int t = t0 + c;
-            buf_a[e.c + c] = (t >= 0 && t < a.nt) ? widen<Tacc>(row[t]) : Tacc(0);
+            buf_a[e.c + c] = (t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
           }
         }
       }
@@ -265,8 +313,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a) 
       int cmax = e.e;
       Tacc *out;
       if (top) {
-        out = static_cast<Tacc *>(a.dst) + beam * a.dst_bstride + e.c * a.dst_stride + T0;
-        const int left = a.nt - T0;
+        out = static_cast<Tacc *>(a.dst) + bs.dst_off + e.c * bs.dst_stride + T0;
+        const int left = nt - T0;
         if (left < cmax) cmax = left;
       } else {
         out = D + e.c;
@@ -344,11 +392,11 @@ struct Vec4<int32_t> {
   typedef int type __attribute__((ext_vector_type(4), aligned(4)));
 };
 
-template <typename Tacc, int K>
+template <typename Tacc, int K, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
-    int32_t nt, int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
-    int32_t nrows, int32_t rows_per_wg) {
+    int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
+    int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   constexpr int N = 1 << K;
   // A workgroup holds rows_per_wg consecutive output rows (one wave each, the
@@ -361,10 +409,13 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   const int g = xcd_local_order(blockIdx.x, groups);
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
-  const int tw = (blockIdx.y * col_waves + wave % col_waves) * 256;  // first sample of the wave
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
+  const int nt = bs.nt;
+  const int64_t src_stride = bs.src_stride;
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256;  // first sample of the wave
   const int t = tw + lane * 4;
   if (t >= nt) return;
-  const Tacc *base = src + blockIdx.z * src_bstride;
+  const Tacc *base = src + bs.src_off;
   const int2 *tm = terms + static_cast<int64_t>(r) * N;
   int2 e[N];
   int smax = 0;
@@ -391,7 +442,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   for (int span = 1; span < N; span *= 2)
 #pragma unroll
     for (int j = 0; j < N; j += 2 * span) v[j] = v[j] + v[j + span];
-  Tacc *o = dst + blockIdx.z * dst_bstride + r * dst_stride + t;
+  Tacc *o = dst + bs.dst_off + r * bs.dst_stride + t;
   if (t + 4 <= nt) {
     *reinterpret_cast<V *>(o) = v[0];
   } else {
@@ -412,12 +463,12 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
 // eight loads in flight before any is used.
 constexpr int kAdjChunk = 8;
 
-template <typename Tacc, int K>
+template <typename Tacc, int K, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
-    const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt,
-    int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
-    int32_t nrows, int32_t rows_per_wg) {
+    const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u,
+    int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride,
+    int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   const int waves = kGatherThreads / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
@@ -426,9 +477,12 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
   const int g = xcd_local_order(blockIdx.x, groups);
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
-  const int t = (blockIdx.y * col_waves + wave % col_waves) * 256 + lane * 4;
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
+  const int nt = bs.nt;
+  const int64_t src_stride = bs.src_stride;
+  const int t = (bs.tile * col_waves + wave % col_waves) * 256 + lane * 4;
   if (t >= nt) return;
-  const Tacc *base = src + blockIdx.z * src_bstride;
+  const Tacc *base = src + bs.src_off;
   const int x_begin = starts[r], x_end = starts[r + 1];
   const int out_row = order[r];
   V acc[K];
@@ -470,7 +524,7 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
   }
 #pragma unroll
   for (int d = K - 1; d >= 1; --d) acc[d - 1] = acc[d - 1] + acc[d];
-  Tacc *o = dst + blockIdx.z * dst_bstride + out_row * dst_stride + t;
+  Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + t;
   if (t + 4 <= nt) {
     *reinterpret_cast<V *>(o) = acc[0];
   } else {
@@ -683,9 +737,11 @@ size_t fused_lds_bytes(const Pass &ps) {
   return static_cast<size_t>(ps.lds_a + ps.lds_b) * 4 + static_cast<size_t>(ps.max_recs) * sizeof(Rec);
 }
 
-View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, bool adjoint) {
+View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, bool adjoint,
+          const RaggedBatch *rb) {
   const int64_t nt = p.nt;
-  const int64_t plane_b = p.ws_rows * p.ntp;
+  const int64_t plane_b = p.ws_rows * (rb ? rb->sum_ntp : p.ntp);
+  const int64_t nb = rb ? 1 : batch;
   const int64_t in_rows = adjoint ? p.tab.nd : p.tab.nf;
   const int64_t out_rows = adjoint ? p.tab.nf : p.tab.nd;
   switch (b) {
@@ -693,37 +749,77 @@ View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, 
     case Buf::Out: return {out, nt, out_rows * nt};
     case Buf::Ws0: return {ws, p.ntp, plane_b};
     case Buf::Ws1:
-      return {static_cast<unsigned char *>(ws) + static_cast<size_t>(plane_b) * batch * 4, p.ntp, plane_b};
+      return {static_cast<unsigned char *>(ws) + static_cast<size_t>(plane_b) * nb * 4, p.ntp, plane_b};
   }
   return {nullptr, 0, 0};
 }
 
+int64_t buf_rows(const Plan &p, Buf b, bool adjoint) {
+  switch (b) {
+    case Buf::In: return adjoint ? p.tab.nd : p.tab.nf;
+    case Buf::Out: return adjoint ? p.tab.nf : p.tab.nd;
+    default: return p.ws_rows;
+  }
+}
+
+constexpr int64_t kMaxGridY = 65535;
+
+// Issues the launches of one step over time tiles of width `tile`. A uniform
+// batch is one launch: ceil(nt / tile) tiles in grid y, beams in grid z. A
+// ragged batch walks the flattened tile map of that width, at most 65535
+// tiles per launch. `launch(ragged, grid_y, grid_z, map)` issues one launch.
+template <typename F>
+hipError_t for_each_launch(const Plan &p, const RaggedBatch *rb, const Step &st, bool adjoint,
+                           int tile, int batch, F &&launch) {
+  if (rb == nullptr) {
+    launch(std::false_type{}, static_cast<unsigned>((p.nt + tile - 1) / tile),
+           static_cast<unsigned>(batch), RaggedMap{});
+    return hipGetLastError();
+  }
+  const RaggedBatch::Map *m = nullptr;
+  for (const RaggedBatch::Map &x : rb->maps)
+    if (x.tile == tile) m = &x;
+  if (m == nullptr) return hipErrorInvalidValue;
+  RaggedMap rg{};
+  rg.beam = rb->beam;
+  rg.src_rows = static_cast<int32_t>(buf_rows(p, st.src, adjoint));
+  rg.dst_rows = static_cast<int32_t>(buf_rows(p, st.dst, adjoint));
+  rg.src_padded = st.src == Buf::Ws0 || st.src == Buf::Ws1;
+  rg.dst_padded = st.dst == Buf::Ws0 || st.dst == Buf::Ws1;
+  for (int64_t off = 0; off < m->count; off += kMaxGridY) {
+    rg.tiles = m->tiles + off;
+    launch(std::true_type{}, static_cast<unsigned>(std::min(kMaxGridY, m->count - off)), 1u, rg);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <typename Tin, typename Tacc>
 hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void *out, int batch,
-                            void *ws, hipStream_t stream) {
+                            void *ws, hipStream_t stream, const RaggedBatch *rb) {
   const Tables &T = p.tab;
   const int64_t nt = p.nt;
-  const View src = view(p, st.src, in, out, ws, batch, false);
-  const View dst = view(p, st.dst, in, out, ws, batch, false);
-  const unsigned tiles = static_cast<unsigned>((nt + kTile - 1) / kTile);
+  const View src = view(p, st.src, in, out, ws, batch, false, rb);
+  const View dst = view(p, st.dst, in, out, ws, batch, false, rb);
   switch (st.kind) {
-    case Step::Init: {
-      dim3 grid(T.nf, tiles, batch);
-      hipLaunchKernelGGL((init_kernel<Tin, Tacc>), grid, dim3(kThreads), 0, stream,
-                         static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                         p.dev.leaf_off, p.dev.leaf_rows, nt, src.bstride, dst.stride, dst.bstride);
-      break;
-    }
-    case Step::Merge: {
-      dim3 grid(static_cast<unsigned>(T.total[st.index]), tiles, batch);
-      hipLaunchKernelGGL((merge_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
-                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                         p.dev.merge[st.index], nt, src.stride, src.bstride, dst.stride, dst.bstride);
-      break;
-    }
+    case Step::Init:
+      return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0, stream,
+                           static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                           p.dev.leaf_off, p.dev.leaf_rows, nt, src.bstride, dst.stride, dst.bstride, rg);
+      });
+    case Step::Merge:
+      return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        hipLaunchKernelGGL((merge_kernel<Tacc, decltype(r)::value>),
+                           dim3(static_cast<unsigned>(T.total[st.index]), gy, gz), dim3(kThreads), 0, stream,
+                           static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                           p.dev.merge[st.index], nt, src.stride, src.bstride, dst.stride, dst.bstride, rg);
+      });
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) {
+        if (rb != nullptr) return hipErrorInvalidValue;
         StagedArgs a{};
         a.src = src.ptr;
         a.dst = dst.ptr;
@@ -768,110 +864,112 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
           }
         }
 #undef FDMT_STAGED
-        break;
+        return hipGetLastError();
       }
       if (ps.gather) {
         const int k = ps.l1 - ps.l0;
+        if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
         const int tile = 256 * (kGatherThreads / 64 / rpw);
-        const unsigned ntl = static_cast<unsigned>((nt + tile - 1) / tile);
-        dim3 grid(static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw), ntl, batch);
+        const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int2 *tm = p.dev_terms + ps.term_offset;
         const Tacc *sp = static_cast<const Tacc *>(src.ptr);
         Tacc *dp = static_cast<Tacc *>(dst.ptr);
-        switch (k) {
-          case 1: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 1>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
-          case 2: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 2>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
-          case 3: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 3>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
-          case 4: hipLaunchKernelGGL((gather_pass_kernel<Tacc, 4>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw); break;
-          default: return hipErrorInvalidValue;
-        }
-        break;
+        return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+          constexpr bool R = decltype(r)::value;
+          const dim3 grid(gx, gy, gz);
+#define FDMT_GATHER(KK) hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
+          switch (k) {
+            case 1: FDMT_GATHER(1); break;
+            case 2: FDMT_GATHER(2); break;
+            case 3: FDMT_GATHER(3); break;
+            default: FDMT_GATHER(4); break;
+          }
+#undef FDMT_GATHER
+        });
       }
       FusedArgs a{};
       a.src = src.ptr;
       a.dst = dst.ptr;
       a.recs = p.dev_recs + ps.rec_offset;
       a.heads = p.dev_heads + ps.head_offset;
-      const int k = ps.l1 - ps.l0;
       a.nt = static_cast<int32_t>(nt);
       a.src_stride = src.stride;
       a.src_bstride = src.bstride;
       a.dst_stride = dst.stride;
       a.dst_bstride = dst.bstride;
-      a.k = k;
+      a.k = ps.l1 - ps.l0;
       a.nblocks = ps.nblocks;
       a.tile = ps.tile;
       a.lds_a = ps.lds_a;
       a.lds_b = ps.lds_b;
       const size_t lds = fused_lds_bytes(ps);
-      dim3 grid(static_cast<unsigned>(a.nblocks), static_cast<unsigned>((nt + ps.tile - 1) / ps.tile), batch);
-      if (ps.from_input)
-        hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, true>), grid, dim3(kFusedThreads), lds,
-                           stream, a);
-      else
-        hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, false>), grid, dim3(kFusedThreads), lds,
-                           stream, a);
-      break;
+      return for_each_launch(p, rb, st, false, ps.tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        constexpr bool R = decltype(r)::value;
+        const dim3 grid(static_cast<unsigned>(a.nblocks), gy, gz);
+        if (ps.from_input)
+          hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, true, R>), grid, dim3(kFusedThreads), lds, stream, a, rg);
+        else
+          hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, false, R>), grid, dim3(kFusedThreads), lds, stream, a, rg);
+      });
     }
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename Tacc>
 hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void *out, int batch,
-                            void *ws, hipStream_t stream) {
+                            void *ws, hipStream_t stream, const RaggedBatch *rb) {
   const Tables &T = p.tab;
   const int64_t nt = p.nt;
-  const View src = view(p, st.src, in, out, ws, batch, true);
-  const View dst = view(p, st.dst, in, out, ws, batch, true);
-  const unsigned tiles = static_cast<unsigned>((nt + kTile - 1) / kTile);
+  const View src = view(p, st.src, in, out, ws, batch, true, rb);
+  const View dst = view(p, st.dst, in, out, ws, batch, true, rb);
   switch (st.kind) {
     case Step::MergeAdj: {
       const int l = st.index;
-      dim3 grid(static_cast<unsigned>(T.total[l - 1]), tiles, batch);
-      hipLaunchKernelGGL((merge_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
-                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                         p.dev.adj[l], p.dev.merge[l], nt, src.stride, src.bstride, dst.stride,
-                         dst.bstride);
-      break;
+      return for_each_launch(p, rb, st, true, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        hipLaunchKernelGGL((merge_adjoint_kernel<Tacc, decltype(r)::value>),
+                           dim3(static_cast<unsigned>(T.total[l - 1]), gy, gz), dim3(kThreads), 0, stream,
+                           static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                           p.dev.adj[l], p.dev.merge[l], nt, src.stride, src.bstride, dst.stride,
+                           dst.bstride, rg);
+      });
     }
     case Step::AdjGather: {
       const AdjPass &ps = p.adj.passes[st.index];
+      if (ps.depth < 1 || ps.depth > 5) return hipErrorInvalidValue;
       const int rpw = p.gather_rows;
       const int tile = 256 * (kGatherThreads / 64 / rpw);
-      dim3 grid(static_cast<unsigned>((ps.nrows + rpw - 1) / rpw),
-                static_cast<unsigned>((nt + tile - 1) / tile), batch);
+      const unsigned gx = static_cast<unsigned>((ps.nrows + rpw - 1) / rpw);
       const int4 *lv = p.dev_adj_leaves + ps.leaf_offset;
       const int32_t *sr = p.dev_adj_starts + ps.start_offset;
       const int32_t *od = p.dev_adj_order + ps.order_offset;
       const Tacc *sp = static_cast<const Tacc *>(src.ptr);
       Tacc *dp = static_cast<Tacc *>(dst.ptr);
       const int32_t nt32 = static_cast<int32_t>(nt);
-#define FDMT_ADJ(KK) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw)
-      switch (ps.depth) {
-        case 1: FDMT_ADJ(1); break;
-        case 2: FDMT_ADJ(2); break;
-        case 3: FDMT_ADJ(3); break;
-        case 4: FDMT_ADJ(4); break;
-        case 5: FDMT_ADJ(5); break;
-        default: return hipErrorInvalidValue;
-      }
+      return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        constexpr bool R = decltype(r)::value;
+        const dim3 grid(gx, gy, gz);
+#define FDMT_ADJ(KK) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw, rg)
+        switch (ps.depth) {
+          case 1: FDMT_ADJ(1); break;
+          case 2: FDMT_ADJ(2); break;
+          case 3: FDMT_ADJ(3); break;
+          case 4: FDMT_ADJ(4); break;
+          default: FDMT_ADJ(5); break;
+        }
 #undef FDMT_ADJ
-      break;
+      });
     }
-    case Step::InitAdj: {
-      dim3 grid(T.nf, tiles, batch);
-      hipLaunchKernelGGL((init_adjoint_kernel<Tacc>), grid, dim3(kThreads), 0, stream,
-                         static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                         p.dev.leaf_off, p.dev.leaf_rows, nt, src.stride, src.bstride, dst.bstride);
-      break;
-    }
+    case Step::InitAdj:
+      return for_each_launch(p, rb, st, true, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        hipLaunchKernelGGL((init_adjoint_kernel<Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0,
+                           stream, static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                           p.dev.leaf_off, p.dev.leaf_rows, nt, src.stride, src.bstride, dst.bstride, rg);
+      });
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 } // namespace
@@ -967,16 +1065,19 @@ hipError_t prepare_kernels(const Plan &p) {
     if (!ps.gather) lds = std::max(lds, fused_lds_bytes(ps));
   if (lds <= 64 * 1024) return hipSuccess;
   const void *fns[] = {
-      reinterpret_cast<const void *>(&fused_pass_kernel<float, float, true>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, true>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, true>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, true>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, true>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<float, float, false>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, false>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, false>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, false>),
-      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, false>)};
+#define FDMT_FUSED_ALL(R)                                                                   \
+  reinterpret_cast<const void *>(&fused_pass_kernel<float, float, true, R>),                \
+      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, true, R>),         \
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, true, R>),          \
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, true, R>),        \
+      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, true, R>),        \
+      reinterpret_cast<const void *>(&fused_pass_kernel<float, float, false, R>),           \
+      reinterpret_cast<const void *>(&fused_pass_kernel<_Float16, float, false, R>),        \
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, float, false, R>),         \
+      reinterpret_cast<const void *>(&fused_pass_kernel<uint8_t, int32_t, false, R>),       \
+      reinterpret_cast<const void *>(&fused_pass_kernel<int32_t, int32_t, false, R>)
+      FDMT_FUSED_ALL(false), FDMT_FUSED_ALL(true)};
+#undef FDMT_FUSED_ALL
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -985,44 +1086,62 @@ hipError_t prepare_kernels(const Plan &p) {
 }
 
 hipError_t run_step(const Plan &p, bool adjoint, int i, const void *in, void *out, int batch,
-                    void *ws, hipStream_t stream) {
+                    void *ws, hipStream_t stream, const RaggedBatch *rb) {
   if (adjoint) {
     const Step &st = p.adj_steps[i];
-    if (p.acc_dtype == FDMT_F32) return run_adjoint_step<float>(p, st, in, out, batch, ws, stream);
-    return run_adjoint_step<int32_t>(p, st, in, out, batch, ws, stream);
+    if (p.acc_dtype == FDMT_F32) return run_adjoint_step<float>(p, st, in, out, batch, ws, stream, rb);
+    return run_adjoint_step<int32_t>(p, st, in, out, batch, ws, stream, rb);
   }
   const Step &st = p.fwd_steps[i];
   if (p.acc_dtype == FDMT_F32) {
     switch (p.in_dtype) {
-      case FDMT_F32: return run_forward_step<float, float>(p, st, in, out, batch, ws, stream);
-      case FDMT_F16: return run_forward_step<_Float16, float>(p, st, in, out, batch, ws, stream);
-      case FDMT_U8: return run_forward_step<uint8_t, float>(p, st, in, out, batch, ws, stream);
+      case FDMT_F32: return run_forward_step<float, float>(p, st, in, out, batch, ws, stream, rb);
+      case FDMT_F16: return run_forward_step<_Float16, float>(p, st, in, out, batch, ws, stream, rb);
+      case FDMT_U8: return run_forward_step<uint8_t, float>(p, st, in, out, batch, ws, stream, rb);
       default: return hipErrorInvalidValue;
     }
   }
   switch (p.in_dtype) {
-    case FDMT_U8: return run_forward_step<uint8_t, int32_t>(p, st, in, out, batch, ws, stream);
-    case FDMT_I32: return run_forward_step<int32_t, int32_t>(p, st, in, out, batch, ws, stream);
+    case FDMT_U8: return run_forward_step<uint8_t, int32_t>(p, st, in, out, batch, ws, stream, rb);
+    case FDMT_I32: return run_forward_step<int32_t, int32_t>(p, st, in, out, batch, ws, stream, rb);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
-                          hipStream_t stream) {
+                          hipStream_t stream, const RaggedBatch *rb) {
   for (size_t i = 0; i < p.fwd_steps.size(); ++i) {
-    hipError_t e = run_step(p, false, static_cast<int>(i), in, out, batch, ws, stream);
+    hipError_t e = run_step(p, false, static_cast<int>(i), in, out, batch, ws, stream, rb);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch, void *ws,
-                          hipStream_t stream) {
+                          hipStream_t stream, const RaggedBatch *rb) {
   for (size_t i = 0; i < p.adj_steps.size(); ++i) {
-    hipError_t e = run_step(p, true, static_cast<int>(i), gout, gin, batch, ws, stream);
+    hipError_t e = run_step(p, true, static_cast<int>(i), gout, gin, batch, ws, stream, rb);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+int step_tile(const Plan &p, bool adjoint, int i) {
+  const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
+  const int gather_tile = 256 * (kGatherThreads / 64 / p.gather_rows);
+  switch (st.kind) {
+    case Step::Init:
+    case Step::Merge:
+    case Step::MergeAdj:
+    case Step::InitAdj: return kTile;
+    case Step::AdjGather: return gather_tile;
+    case Step::Fused: {
+      const Pass &ps = p.fwd.passes[st.index];
+      if (ps.kind == PassKind::Staged) return 0;
+      return ps.gather ? gather_tile : ps.tile;
+    }
+  }
+  return 0;
 }
 
 } // namespace fdmt

@@ -63,16 +63,35 @@ struct Plan {
   int64_t ws_rows = 0;         // rows of each workspace plane
 };
 
+// Beams of different lengths packed back to back: beam b's [rows][Nt_b]
+// block starts at rows * (samples of beams 0..b-1) in caller buffers and at
+// rows * (padded samples of beams 0..b-1) in workspace planes. Device tables
+// are owned by the ragged plan of the C ABI.
+struct RaggedBatch {
+  int nbeams = 0;
+  int64_t sum_nt = 0, sum_ntp = 0;  // samples; padded samples
+  const int4 *beam = nullptr;       // per beam {nt, padded nt, first sample, first padded sample}
+  struct Map {
+    int tile;            // time-tile width
+    int64_t count;       // tiles over all beams
+    const int2 *tiles;   // per tile {beam, tile index within the beam}
+  };
+  std::vector<Map> maps;            // one per tile width the plan's steps use
+};
+
 // Builds fwd_steps/adj_steps and ws_rows from the tables and the schedule.
 void plan_steps(Plan &p);
 
-// Kernel sequences (fdmt_kernels.hip). Both assume validated arguments.
+// Kernel sequences (fdmt_kernels.hip). All assume validated arguments; `rb`
+// (null: `batch` beams of p.nt samples) switches every launch to a ragged batch.
 hipError_t run_step(const Plan &p, bool adjoint, int step, const void *in, void *out, int batch,
-                    void *ws, hipStream_t stream);
+                    void *ws, hipStream_t stream, const RaggedBatch *rb = nullptr);
 hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
-                          hipStream_t stream);
+                          hipStream_t stream, const RaggedBatch *rb = nullptr);
 hipError_t launch_adjoint(const Plan &p, const void *grad_out, void *grad_in, int batch, void *ws,
-                          hipStream_t stream);
+                          hipStream_t stream, const RaggedBatch *rb = nullptr);
+// Time-tile width of a step's launches; 0 when the step has no ragged form.
+int step_tile(const Plan &p, bool adjoint, int step);
 size_t workspace_bytes(const Plan &p, int batch);
 // Sets the dynamic-LDS limit of the fused kernels the plan uses.
 hipError_t prepare_kernels(const Plan &p);

@@ -1,8 +1,8 @@
 // Delay-table builder (host, IEEE float64, compiled without FP contraction).
 //
 // Per iteration l = 1..log2(Nf) and sub-band j, the merged band [f0, f2) is
-// split at its border frequency f1 (Sec. 3, addition rule; the border reading
-// is the one Sec. 3.2 gives for unequal sub-bands). Its row dt reads
+// split at its border frequency f1 (Sec. 4, addition rule; the border reading
+// is the one Sec. 4.2 gives for unequal sub-bands). Its row dt reads
 //   the lower half [f0, f1) at row d_lo = t0 - t1 = round(dt * C_{f2,f0}) and
 //   the upper half [f1, f2) at row d_hi = t1 - t2 = dt - d_lo, shifted by d_lo,
 // with C_{f2,f0} from Eq. (Cf2f0). Rows are counted top-down from the Nd

@@ -1,4 +1,4 @@
-// Host-side delay tables of the FDMT (Zackay & Ofek, Sec. 3, Eq. Cf2f0 and
+// Host-side delay tables of the FDMT (Zackay & Ofek, Sec. 4, Eq. Cf2f0 and
 // Algorithm 1) in the flat, device-friendly form the kernels consume.
 #pragma once
 

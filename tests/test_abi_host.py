@@ -143,3 +143,39 @@ def test_table_query_errors():
         p.tables(-1, 0)
     assert F.fdmt_status_string(B.FDMT_E_WORKSPACE).startswith("workspace")
     assert B.fdmt_plan_destroy(None) is None
+
+
+def test_ragged_plan_errors_before_any_device_work():
+    """Ragged plans validate beams and the plan's kernels first; a host-only
+    plan is refused last (it has no device tables to run)."""
+    lib = F.load()
+    p = _host_plan(64, 64, 1.2, 1.6, nt=1000)
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(p.handle, [])
+    assert e.value.status == B.FDMT_E_INVALID
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(p.handle, [100, -1])
+    assert e.value.status == B.FDMT_E_INVALID and "beam 1" in F.fdmt_last_error()
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(p.handle, [2 ** 31])
+    assert e.value.status == B.FDMT_E_INVALID
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(p.handle, [2 ** 30, 2 ** 30])  # padded total above 2^31 - 1
+    assert e.value.status == B.FDMT_E_UNSUPPORTED
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(p.handle, [100, 0, 5000])
+    assert e.value.status == B.FDMT_E_UNSUPPORTED and "HOST_ONLY" in F.fdmt_last_error()
+    staged = _host_plan(64, 64, 1.2, 1.6, nt=1000, first_kernel=1)
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(staged.handle, [100])
+    assert e.value.status == B.FDMT_E_UNSUPPORTED and "staged" in F.fdmt_last_error()
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_ragged_plan(None, [100])
+    assert e.value.status == B.FDMT_E_INVALID
+    x, y, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000)
+    for fn in (lib.fdmt_ragged_forward, lib.fdmt_ragged_adjoint):
+        assert fn(None, x, y, ws, 1 << 20, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_ragged_run_step(None, 0, 0, x, y, ws, 1 << 20, None) == B.FDMT_E_INVALID
+    assert F.fdmt_ragged_workspace_bytes(None) == 0
+    assert lib.fdmt_ragged_info(None, None, None, None) == B.FDMT_E_INVALID
+    assert B.fdmt_ragged_destroy(None) is None

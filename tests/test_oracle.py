@@ -78,7 +78,7 @@ def test_path_follows_dispersion_law(nf, nd, band):
 
 
 def test_work_below_paper_bound():
-    """Sec. 3.1: additions <= 2*Nf*Nt + Nt*Nd*log2(Nf) (per unit Nt)."""
+    """Sec. 4.1: additions <= 2*Nf*Nt + Nt*Nd*log2(Nf) (per unit Nt)."""
     for nf, nd in [(64, 64), (1024, 1024), (4096, 2048), (1024, 512)]:
         t = build_tables(nf, nd, 1.2, 1.6)
         adds = sum(sum(r) for r in t.rows[1:]) + sum(n - 1 for n in t.rows[0])
@@ -164,7 +164,7 @@ def test_causal_window():
 
 
 def test_commutes_with_causal_time_filter():
-    """Sec. 3.2 (pulse profile): convolving every channel's time series with the
+    """Sec. 4.2 (pulse profile): convolving every channel's time series with the
     same profile commutes with the transform (exact in integers)."""
     x = _rng(6).integers(-20, 20, size=(32, 120))
     h = np.array([3, -1, 2, 5])
@@ -216,7 +216,7 @@ def test_noiseless_pulses_recovered(nf, nd, band):
     """Noiseless width-1 pulses at several delays: the transform's peak sits within
     2 samples of the truth in both axes (2*Nd/Nf in delay when Nd > Nf, where each
     channel spans several delay samples and neighbouring delays tie) and captures
-    >= 60% of the pulse; the brute-force law integration (Sec. 2) captures all of
+    >= 60% of the pulse; the brute-force law integration (Sec. 3) captures all of
     it at the truth."""
     rng = _rng(nf + nd)
     nt = nd + 200

@@ -5,7 +5,7 @@ callers. It only draws random numbers and places dispersed pulses on the
 time-frequency plane; it contains none of the transform's arithmetic (no
 merge coefficients, no delay tables, no sums along curves).
 
-Conventions (Zackay & Ofek, Sec. 1 and Sec. 3):
+Conventions (Zackay & Ofek, Sec. 1 and Sec. 4):
   * the input is I[f][t] with the time axis contiguous;
   * channel k covers [e_k, e_k + df), e_k = f_min + k*df, df = (f_max-f_min)/Nf,
     channel 0 is the lowest frequency;
