@@ -120,7 +120,7 @@ def cpu_baseline(nt_sample, min_seconds=10.0, max_reps=4):
 
 
 def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
-    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype)
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, tuned=True)
     gen = torch.Generator(device="cuda").manual_seed(11)
     if in_dtype == torch.uint8:
         x = torch.randint(0, 256, (w.nf, w.nt), device="cuda", dtype=torch.uint8, generator=gen)
@@ -150,7 +150,7 @@ def ragged_c4(F, torch, W, reps=5):
     w = W.WORKLOADS["c4"]
     lengths = [int(n) for n in W.c4_lengths()]
     tot = sum(lengths)
-    plan = F.Plan(w.nf, max(lengths), w.nd, w.f_min, w.f_max)
+    plan = F.Plan(w.nf, max(lengths), w.nd, w.f_min, w.f_max, tuned=True)
     r = F.RaggedPlan(plan, lengths)
     x = W.torch_noise((w.nf * tot,), W.SEED_BASE + 40, "cuda")
     g = W.torch_noise((w.nd * tot,), W.SEED_BASE + 41, "cuda")
@@ -177,7 +177,7 @@ def ragged_c4(F, torch, W, reps=5):
     with torch.cuda.graph(graph, stream=s):
         r.forward(x, out=y, ws=ws)
     graph_ms = timed(graph.replay)
-    plans = [F.Plan(w.nf, n, w.nd, w.f_min, w.f_max) for n in lengths]
+    plans = [F.Plan(w.nf, n, w.nd, w.f_min, w.f_max, **plan.options) for n in lengths]
     xs, ys = r.unpack(x, w.nf), r.unpack(y, w.nd)
 
     def loop():
@@ -190,7 +190,7 @@ def ragged_c4(F, torch, W, reps=5):
             "launches_forward_plus_adjoint": r.info()[2],
             "forward_ms": round(fwd_ms, 4), "forward_graph_ms": round(graph_ms, 4),
             "adjoint_ms": round(adj_ms, 4), "per_beam_loop_forward_ms": round(loop_ms, 4),
-            "forward_dm_trial_samples_per_s": rate}
+            "forward_dm_trial_samples_per_s": rate, "schedule": plan.options}
 
 
 def main():
@@ -229,7 +229,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = W.WORKLOADS["c3"]
-    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=torch.float32)
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=torch.float32,
+                  tuned=True)
     x = W.torch_noise((w.nf, w.nt), W.SEED_BASE + 2, "cuda", kind="u8")
     g = W.torch_noise((w.nd, w.nt), W.SEED_BASE + 102, "cuda")
     y = torch.empty(w.nd, w.nt, device="cuda", dtype=torch.float32)
@@ -267,7 +268,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Nf=4096 channels 1.2-1.6 GHz, Nt=65536, Nd=2048; uint8 input "
                                "clip(rint(64 + 8 N(0,1))), FP32 accumulation; step = forward + adjoint",
-                   "nf": w.nf, "nt": w.nt, "nd": w.nd, "batch": 1, "parallelism": "single GPU"},
+                   "nf": w.nf, "nt": w.nt, "nd": w.nd, "batch": 1, "parallelism": "single GPU",
+                   "schedule": plan.options},
         "forward": {"ms": round(fwd_ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (fwd_ms / 1000.0),
                     "alg_hbm_gb_s": round(fwd_bytes / fwd_ms / 1e6, 1)},
         "adjoint": {"ms": round(adj_ms, 4), "alg_hbm_gb_s": round(adj_bytes / adj_ms / 1e6, 1)},

@@ -93,10 +93,12 @@ typedef struct {
   int32_t lds_kib;        /* LDS budget per work block, 16..160 KiB */
   int32_t max_block_rows; /* cap on the output rows of one work block, 1..4096 */
   int32_t first_kernel;   /* kernel form of the first pass: 1 staged gather,
-                             2 level-by-level merges in LDS (0 = default: 2) */
+                             2 level-by-level merges in LDS, 3 gather through the
+                             caches straight from the input (0 = default: 2) */
   int32_t later_kernel;   /* kernel form of later passes: 1 staged gather, 2 level-by-level
                              merges in LDS, 3 gather through the caches (0 = default: 3) */
-  int32_t stream_tiles;   /* time tiles one staged-gather workgroup streams over, 1..65535 */
+  int32_t stream_tiles;   /* consecutive time tiles one LDS workgroup runs, 1..65535
+                             (0 = default: 1 for staged gathers, 8 for level-by-level merges) */
   int32_t gather_rows;    /* output rows per cache-gather workgroup: 1, 2, 4, 8 or 16 */
   int32_t adjoint_levels; /* iterations per adjoint pass, 1..5 (0 = default 2) */
   int32_t adjoint_last_levels; /* iterations folded into the last adjoint pass with the

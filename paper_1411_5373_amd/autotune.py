@@ -1,0 +1,207 @@
+"""Schedule autotuner: times candidate plan options on the GPU and keeps the
+fastest per workload in a JSON cache that `Plan(..., tuned=True)` consults.
+
+Every candidate is a set of `fdmt_options_t` schedule fields (kernel form and
+iterations of each pass, tile width, LDS budget, rows per gather workgroup,
+adjoint pass depths). Schedule fields never change results, only speed, so
+the tuner compares times alone. Forward and adjoint are tuned separately;
+the one field they share (rows per gather workgroup) is chosen to minimise
+their sum.
+
+Cache key: GPU architecture, Nf, Nd, band, input and accumulation dtypes and
+Nt rounded up to a power of two. The cache shipped with the package
+(tuning/<arch>.json) holds the entries its benchmark workloads use;
+FDMT_TUNE_CACHE names another file to read and update instead.
+
+Command line (on a GPU):
+  python -m paper_1411_5373_amd.autotune --nf 4096 --nt 65536 --nd 2048 \
+      --band 1.2 1.6 --in-dtype u8 --acc-dtype f32 [--write]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import torch
+
+from . import binding as B
+
+DTYPES = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8, "i32": torch.int32}
+_NAMES = {v: k for k, v in DTYPES.items()}
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+
+# Fields that shape only the forward or only the adjoint schedule.
+FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
+                  "max_block_rows", "stream_tiles")
+ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels")
+SHARED_FIELDS = ("gather_rows",)
+
+
+def forward_candidates():
+    """Forward schedules worth timing: level-by-level LDS first pass, or a
+    gather straight from the input, followed by cache gathers."""
+    out = []
+    for later in (2, 3):
+        out.append(dict(first_kernel=2, first_levels=4, later_levels=later))
+        out.append(dict(first_kernel=2, first_levels=4, later_levels=later, stream_tiles=1))
+        for first in (2, 3, 4):
+            out.append(dict(first_kernel=3, first_levels=first, later_levels=later))
+    return out
+
+
+def adjoint_candidates():
+    return [dict(adjoint_levels=a, adjoint_last_levels=b) for a in (1, 2, 3) for b in (1, 2, 3)]
+
+
+GATHER_ROWS = (4, 8)
+
+
+def arch():
+    name = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+    return name.split(":")[0]
+
+
+def nt_bucket(nt):
+    b = 1
+    while b < nt:
+        b *= 2
+    return b
+
+
+def cache_key(arch_name, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype):
+    return (f"{arch_name}/nf{nf}/nd{nd}/band{float(f_min):.6g}-{float(f_max):.6g}/"
+            f"{_NAMES[in_dtype]}->{_NAMES[acc_dtype]}/nt{nt_bucket(nt)}")
+
+
+def cache_path(arch_name):
+    return os.environ.get("FDMT_TUNE_CACHE") or os.path.join(PKG_DIR, "tuning", f"{arch_name}.json")
+
+
+def load_cache(arch_name):
+    path = cache_path(arch_name)
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, arch_name=None):
+    """Tuned schedule options for this workload, or None."""
+    a = arch_name or arch()
+    entry = load_cache(a).get(cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype))
+    return None if entry is None else dict(entry["options"])
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32, reps=5,
+         verbose=False):
+    """Times every candidate; returns {"options", "forward_ms", "adjoint_ms", "tried"}."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    gen = torch.Generator(device=dev).manual_seed(1)
+    if in_dtype in (torch.uint8, torch.int32):
+        x = torch.randint(0, 256, (nf, nt), device=dev, dtype=torch.int32, generator=gen).to(in_dtype)
+    else:
+        x = torch.randn(nf, nt, device=dev, generator=gen).to(in_dtype)
+    if acc_dtype == torch.int32:
+        g = torch.randint(-8, 8, (nd, nt), device=dev, dtype=torch.int32, generator=gen)
+    else:
+        g = torch.randn(nd, nt, device=dev, generator=gen)
+    y = torch.empty(nd, nt, device=dev, dtype=acc_dtype)
+    xb = torch.empty(nf, nt, device=dev, dtype=acc_dtype)
+    tried = []
+    best = {}
+    for rows in GATHER_ROWS:
+        fwd_best, adj_best = None, None
+        for cand in forward_candidates():
+            opts = dict(cand, gather_rows=rows)
+            try:
+                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, **opts)
+            except B.FDMTError:
+                continue  # this schedule does not fit the shape
+            ws = p.workspace(1)
+            ms = _time(lambda: p.forward(x, out=y, ws=ws), reps)
+            tried.append({"direction": "forward", "options": opts, "ms": round(ms, 4)})
+            if verbose:
+                print(f"forward {opts}: {ms:.4f} ms", flush=True)
+            if fwd_best is None or ms < fwd_best[0]:
+                fwd_best = (ms, cand)
+            del p, ws
+        for cand in adjoint_candidates():
+            opts = dict(cand, gather_rows=rows)
+            try:
+                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, **opts)
+            except B.FDMTError:
+                continue
+            ws = p.workspace(1)
+            ms = _time(lambda: p.adjoint(g, out=xb, ws=ws), reps)
+            tried.append({"direction": "adjoint", "options": opts, "ms": round(ms, 4)})
+            if verbose:
+                print(f"adjoint {opts}: {ms:.4f} ms", flush=True)
+            if adj_best is None or ms < adj_best[0]:
+                adj_best = (ms, cand)
+            del p, ws
+        if fwd_best is None or adj_best is None:
+            continue
+        total = fwd_best[0] + adj_best[0]
+        if not best or total < best["forward_ms"] + best["adjoint_ms"]:
+            best = {"options": dict(fwd_best[1], **adj_best[1], gather_rows=rows),
+                    "forward_ms": round(fwd_best[0], 4), "adjoint_ms": round(adj_best[0], 4)}
+    if not best:
+        raise RuntimeError("no candidate schedule fits this workload")
+    best["tried"] = tried
+    return best
+
+
+def store(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, result, arch_name=None):
+    a = arch_name or arch()
+    path = cache_path(a)
+    cache = load_cache(a)
+    cache[cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype)] = {
+        "options": result["options"], "forward_ms": result["forward_ms"],
+        "adjoint_ms": result["adjoint_ms"], "tuned_at_nt": int(nt),
+        "date": time.strftime("%Y-%m-%d")}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return path
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--nf", type=int, required=True)
+    ap.add_argument("--nt", type=int, required=True)
+    ap.add_argument("--nd", type=int, required=True)
+    ap.add_argument("--band", type=float, nargs=2, required=True)
+    ap.add_argument("--in-dtype", choices=sorted(DTYPES), default="f32")
+    ap.add_argument("--acc-dtype", choices=sorted(DTYPES), default="f32")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--write", action="store_true", help="store the result in the cache")
+    ap.add_argument("--out", help="also write the full result (every candidate's time) to this JSON file")
+    args = ap.parse_args()
+    ind, acc = DTYPES[args.in_dtype], DTYPES[args.acc_dtype]
+    res = tune(args.nf, args.nt, args.nd, *args.band, ind, acc, reps=args.reps, verbose=True)
+    print(json.dumps({k: v for k, v in res.items() if k != "tried"}), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(dict(res, workload=vars(args)), f, indent=1)
+    if args.write:
+        print("stored in", store(args.nf, args.nt, args.nd, *args.band, ind, acc, res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -259,12 +259,22 @@ class Plan:
     shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
-                 host_only=False, unfused=False, **schedule):
+                 host_only=False, unfused=False, tuned=False, **schedule):
+        """`schedule`: fdmt_options_t schedule fields (first_kernel, first_levels,
+        ...). tuned=True first takes the autotuner's stored options for this
+        workload, if any; explicit schedule fields override them."""
         self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
         self.f_min, self.f_max = float(f_min), float(f_max)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
         flags = (FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0)
         self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
+        self.tuned = None
+        if tuned and not host_only and not unfused:
+            from . import autotune
+            self.tuned = autotune.lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype)
+            if self.tuned:
+                schedule = dict(self.tuned, **schedule)
+        self.options = dict(schedule)
         self.handle = None
         self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
                                 _TORCH_TO_CODE[acc_dtype], flags, **schedule)

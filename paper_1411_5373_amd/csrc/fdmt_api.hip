@@ -59,6 +59,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   const size_t off_recs = reserve(p.fwd.recs.size() * sizeof(fdmt::Rec));
   const size_t off_heads = reserve(p.fwd.heads.size() * sizeof(int32_t));
   const size_t off_terms = reserve(p.fwd.terms.size() * sizeof(fdmt::Term));
+  const size_t off_iterms = reserve(p.fwd.iterms.size() * sizeof(fdmt::InTerm));
   const size_t off_stage = reserve(p.fwd.stage.size() * sizeof(fdmt::Rec));
   const size_t off_psums = reserve(p.fwd.psums.size() * sizeof(fdmt::Rec));
   const size_t off_adj_leaves = reserve(p.adj.leaves.size() * sizeof(fdmt::AdjLeaf));
@@ -80,6 +81,8 @@ fdmt_status_t upload(fdmt::Plan &p) {
     std::memcpy(host.data() + off_heads, p.fwd.heads.data(), p.fwd.heads.size() * sizeof(int32_t));
   if (!p.fwd.terms.empty())
     std::memcpy(host.data() + off_terms, p.fwd.terms.data(), p.fwd.terms.size() * sizeof(fdmt::Term));
+  if (!p.fwd.iterms.empty())
+    std::memcpy(host.data() + off_iterms, p.fwd.iterms.data(), p.fwd.iterms.size() * sizeof(fdmt::InTerm));
   if (!p.fwd.stage.empty())
     std::memcpy(host.data() + off_stage, p.fwd.stage.data(), p.fwd.stage.size() * sizeof(fdmt::Rec));
   if (!p.fwd.psums.empty())
@@ -114,6 +117,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   p.dev_recs = reinterpret_cast<const fdmt::Rec *>(base + off_recs);
   p.dev_heads = reinterpret_cast<const int32_t *>(base + off_heads);
   p.dev_terms = reinterpret_cast<const int2 *>(base + off_terms);
+  p.dev_iterms = reinterpret_cast<const int4 *>(base + off_iterms);
   p.dev_stage = reinterpret_cast<const fdmt::Rec *>(base + off_stage);
   p.dev_psums = reinterpret_cast<const fdmt::Rec *>(base + off_psums);
   p.dev_adj_leaves = reinterpret_cast<const int4 *>(base + off_adj_leaves);
@@ -188,7 +192,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "tile must be a multiple of 64 in [64, 8192]");
   if (o.lds_kib < 0 || (o.lds_kib && (o.lds_kib < 16 || o.lds_kib > 160)))
     return fail(FDMT_E_INVALID, "lds_kib must be in [16, 160]");
-  if (o.first_kernel < 0 || o.first_kernel > 2 || o.later_kernel < 0 || o.later_kernel > 3)
+  if (o.first_kernel < 0 || o.first_kernel > 3 || o.later_kernel < 0 || o.later_kernel > 3)
     return fail(FDMT_E_INVALID, "unknown pass kernel");
   if (o.stream_tiles < 0 || o.stream_tiles > 65535)
     return fail(FDMT_E_INVALID, "stream_tiles must be in [1, 65535]");
@@ -221,7 +225,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   p.in_dtype = o.in_dtype;
   p.acc_dtype = o.acc_dtype;
   p.flags = o.flags;
-  if (o.stream_tiles) p.tiles_per_wg = o.stream_tiles;
+  if (o.stream_tiles) p.tiles_per_wg = p.rec_tiles = o.stream_tiles;
   if (o.gather_rows) p.gather_rows = o.gather_rows;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
   if (!(o.flags & FDMT_PLAN_UNFUSED)) {
@@ -355,11 +359,15 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->level_last = ps.l1;
       info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
                                                           ((nt + 4096 / P.gather_rows - 1) / (4096 / P.gather_rows)))
-                                   : static_cast<int32_t>(ps.nblocks * ((nt + ps.tile - 1) / ps.tile));
+                                   : static_cast<int32_t>(
+                                         ps.nblocks *
+                                         ((nt + ps.tile - 1) / ps.tile +
+                                          (ps.kind == fdmt::PassKind::Staged ? P.tiles_per_wg : P.rec_tiles) - 1) /
+                                         (ps.kind == fdmt::PassKind::Staged ? P.tiles_per_wg : P.rec_tiles));
       info->lds_bytes = ps.gather ? 0
                         : ps.kind == fdmt::PassKind::Staged
                             ? static_cast<int64_t>(ps.lds_a + ps.lds_p + ps.lds_b + ps.max_recs) * 4
-                            : static_cast<int64_t>(ps.lds_a + ps.lds_b) * 4 + static_cast<int64_t>(ps.max_recs) * 32;
+                            : static_cast<int64_t>(ps.lds_a + ps.lds_b + 2 * fdmt::kLdsSlack) * 4;
       const int64_t eb = ps.from_input ? in_b : 4;
       info->bytes_read = ps.rows_in * nt * eb;
       info->bytes_written = ps.rows_out * nt * 4;

@@ -202,6 +202,7 @@ struct FusedArgs {
   const int32_t *heads; // this pass's block headers (kRecHeader each)
   int64_t src_stride, src_bstride, dst_stride, dst_bstride;
   int32_t nt, k, nblocks, tile, lds_a, lds_b;
+  int32_t tiles_per_wg; // consecutive time tiles one workgroup runs
 };
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -223,140 +224,173 @@ __device__ __forceinline__ Tacc chain(const Tacc *x, int c, int n) {
   return v;
 }
 
+// Leaf rows a wave keeps in flight in registers: two rows of up to 512
+// columns (8 per lane). Rows beyond the first two of a wave, and columns past
+// 512, are staged synchronously.
+template <typename Tacc>
+struct StageRegs {
+  Tacc v[2][8];
+  int wd[2], dst[2];
+};
+
+// Block records and headers are read-only for the whole launch and the same
+// for every lane of a wave: reading them through the constant address space
+// makes them scalar loads.
+typedef const __attribute__((address_space(4))) int32_t *ConstInts;
+
+__device__ __forceinline__ Rec load_rec(ConstInts recs, int q) {
+  const ConstInts r = recs + 8 * q;
+  return Rec{r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7]};
+}
+
 template <typename Tin, typename Tacc, bool FROM_INPUT, bool RAGGED>
 __global__ __launch_bounds__(kFusedThreads) void fused_pass_kernel(FusedArgs a, RaggedMap rg) {
+  typedef typename std::conditional<FROM_INPUT, Tin, Tacc>::type Tsrc;
   extern __shared__ __align__(16) unsigned char smem[];
   Tacc *buf_a = reinterpret_cast<Tacc *>(smem);
-  Tacc *buf_b = buf_a + a.lds_a;
-  Rec *lrec = reinterpret_cast<Rec *>(buf_b + a.lds_b);
+  Tacc *buf_b = buf_a + a.lds_a + kLdsSlack;
 
   const int blk = xcd_local_order(blockIdx.x, a.nblocks);
   const BeamSpan bs = beam_span<RAGGED>(rg, a.nt, a.src_stride, a.src_bstride, a.dst_stride, a.dst_bstride);
   const int nt = bs.nt;
-  const int T0 = bs.tile * a.tile;
+  const int tile_first = bs.tile * a.tiles_per_wg;
+  const int ntiles = (nt + a.tile - 1) / a.tile;
+  const int tile_end = tile_first + a.tiles_per_wg < ntiles ? tile_first + a.tiles_per_wg : ntiles;
   const int wave = uniform(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int32_t *head = a.heads + blk * kRecHeader;
-  const Rec *grec = a.recs + head[0];
-  const int nrec = head[1 + a.k];
+  const ConstInts head = (ConstInts)(a.heads) + blk * kRecHeader;
+  const ConstInts rec = (ConstInts)(a.recs) + 8 * head[0];
   const int nstage = head[1];
+  const Tsrc *in_base = static_cast<const Tsrc *>(a.src) + bs.src_off;
+  const int64_t in_stride = FROM_INPUT ? static_cast<int64_t>(nt) : bs.src_stride;
+  Tacc *out_base = static_cast<Tacc *>(a.dst) + bs.dst_off;
 
-  // All records of the block into LDS (two 16-byte words per record).
-  {
-    const int4 *from = reinterpret_cast<const int4 *>(grec);
-    int4 *to = reinterpret_cast<int4 *>(lrec);
-    for (int x = threadIdx.x; x < 2 * nrec; x += kFusedThreads) to[x] = from[x];
-  }
-  __syncthreads();
-
-  // Stage the leaves, zero outside [0, nt). A wave takes two rows at a time
-  // and issues every load of both (up to 8 columns per lane each) before
-  // writing any of them to LDS.
-  {
-    typedef typename std::conditional<FROM_INPUT, Tin, Tacc>::type Tsrc;
-    const Tsrc *in_base = static_cast<const Tsrc *>(a.src) + bs.src_off;
-    for (int q0 = wave; q0 < nstage; q0 += 2 * kWaves) {
-      Tacc v[2][8];
-      int wd[2], dst[2];
+  // Leaf rows q0 and q0 + kWaves of the tile at T0 (first 512 columns) into
+  // registers, zero outside [0, nt); every load is issued before any use.
+  auto issue = [&](int q0, int T0, StageRegs<Tacc> &r) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int q = q0 + m * kWaves;
-        wd[m] = 0;
-        dst[m] = 0;
-        if (q < nstage) {
-          const Rec e = lrec[q];
-          const int t0 = T0 - e.d;
-          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * nt
-                                                  : static_cast<int64_t>(e.a) * bs.src_stride);
-          wd[m] = e.e;
-          dst[m] = e.c;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int c = 64 * j + lane;
-            const int t = t0 + c;
-            v[m][j] = (c < e.e && t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < 2; ++m) {
+      const int q = q0 + m * kWaves;
+      r.wd[m] = 0;
+      r.dst[m] = 0;
+      if (q < nstage) {
+        const Rec e = load_rec(rec, q);
+        const int t0 = T0 - e.d;
+        const Tsrc *row = in_base + static_cast<int64_t>(e.a) * in_stride;
+        r.wd[m] = e.e;
+        r.dst[m] = e.c;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int c = 64 * j + lane;
-          if (c < wd[m]) buf_a[dst[m] + c] = v[m][j];
-        }
-        if (wd[m] > 512) {  // rare: rows wider than 512 columns
-          const Rec e = lrec[q0 + m * kWaves];
-          const int t0 = T0 - e.d;
-          const Tsrc *row = in_base + (FROM_INPUT ? static_cast<int64_t>(e.a) * nt
-                                                  : static_cast<int64_t>(e.a) * bs.src_stride);
-          for (int c = 512 + lane; c < e.e; c += 64) {
-            const int t = t0 + c;
-            buf_a[e.c + c] = (t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
-          }
+          const int t = t0 + c;
+          r.v[m][j] = (c < e.e && t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
         }
       }
     }
-  }
-  __syncthreads();
-
-  for (int i = 1; i <= a.k; ++i) {
-    const Tacc *S = (i & 1) ? buf_a : buf_b;
-    Tacc *D = (i & 1) ? buf_b : buf_a;
-    const bool top = i == a.k;
-    const int qe = head[1 + i];
-    for (int q = head[i] + wave; q < qe; q += kWaves) {
-      const Rec e = lrec[q];
-      const Tacc *pl = S + e.a;
-      const Tacc *ph = S + e.b;
-      const int c_hi = e.d - T0;  // first column with t - s >= 0
-      int cmax = e.e;
-      Tacc *out;
-      if (top) {
-        out = static_cast<Tacc *>(a.dst) + bs.dst_off + e.c * bs.dst_stride + T0;
-        const int left = nt - T0;
-        if (left < cmax) cmax = left;
-      } else {
-        out = D + e.c;
-      }
-      int c0 = 0;
-      if (FROM_INPUT && i == 1) {
-        const int gl = e.g, gh = e.h;
-        if (c_hi <= 0) {
-          for (; c0 + 256 <= cmax; c0 += 256) {
+  };
+  auto store = [&](const StageRegs<Tacc> &r) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int c = c0 + 64 * j + lane;
-              out[c] = chain(pl, c, gl) + chain(ph, c, gh);
-            }
-          }
-        }
-        for (int c = c0 + lane; c < cmax; c += 64) {
-          Tacc v = chain(pl, c, gl);
-          if (c >= c_hi) v += chain(ph, c, gh);
-          out[c] = v;
-        }
-      } else {
-        if (c_hi <= 0) {
-          for (; c0 + 256 <= cmax; c0 += 256) {
-            const Tacc v0 = pl[c0 + lane] + ph[c0 + lane];
-            const Tacc v1 = pl[c0 + 64 + lane] + ph[c0 + 64 + lane];
-            const Tacc v2 = pl[c0 + 128 + lane] + ph[c0 + 128 + lane];
-            const Tacc v3 = pl[c0 + 192 + lane] + ph[c0 + 192 + lane];
-            out[c0 + lane] = v0;
-            out[c0 + 64 + lane] = v1;
-            out[c0 + 128 + lane] = v2;
-            out[c0 + 192 + lane] = v3;
-          }
-        }
-        for (int c = c0 + lane; c < cmax; c += 64) {
-          Tacc v = pl[c];
-          if (c >= c_hi) v += ph[c];
-          out[c] = v;
-        }
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = 64 * j + lane;
+        if (c < r.wd[m]) buf_a[r.dst[m] + c] = r.v[m][j];
       }
     }
+  };
+  // Writes the prefetched rows to LDS, then stages the wave's other rows
+  // (two at a time) and the columns past 512 of any row.
+  auto commit = [&](int T0, const StageRegs<Tacc> &r) {
+    store(r);
+    for (int q0 = wave + 2 * kWaves; q0 < nstage; q0 += 2 * kWaves) {
+      StageRegs<Tacc> t;
+      issue(q0, T0, t);
+      store(t);
+    }
+    for (int q = wave; q < nstage; q += kWaves) {
+      const Rec e = load_rec(rec, q);
+      if (e.e <= 512) continue;
+      const int t0 = T0 - e.d;
+      const Tsrc *row = in_base + static_cast<int64_t>(e.a) * in_stride;
+      for (int c = 512 + lane; c < e.e; c += 64) {
+        const int t = t0 + c;
+        buf_a[e.c + c] = (t >= 0 && t < nt) ? widen<Tacc>(row[t]) : Tacc(0);
+      }
+    }
+  };
+
+  // One merged row: o[c] = lower[c] (+ chains) + (c >= c_hi ? upper[c] : 0)
+  // for c < w, lanes on columns lane + 64j. LDS operands may be read up to 63
+  // columns past a row's end (the buffers carry that much slack); those
+  // columns are never written. `limit` < w only at the end of the record.
+  auto merge_row = [&](const Rec &e, const Tacc *S, auto o, int T0, int w, bool chained) {
+    const int c_hi = e.d - T0;  // first column with t - s >= 0
+    const Tacc *pl = S + e.a + lane;
+    const Tacc *ph = S + e.b + lane;
+    if (chained) {
+      const int gl = e.g, gh = e.h;
+      for (int c0 = 0; c0 < w; c0 += 64) {
+        Tacc v = chain(pl, c0, gl);
+        if (c0 + lane >= c_hi) v += chain(ph, c0, gh);
+        if (c0 + lane < w) o[c0] = v;
+      }
+      return;
+    }
+    if (c_hi > 0) {
+      for (int c0 = 0; c0 < w; c0 += 64) {
+        Tacc v = pl[c0];
+        if (c0 + lane >= c_hi) v += ph[c0];
+        if (c0 + lane < w) o[c0] = v;
+      }
+      return;
+    }
+    const int full = w & ~63;
+    int c0 = 0;
+    for (; c0 + 256 <= full; c0 += 256) {
+      const Tacc v0 = pl[c0] + ph[c0];
+      const Tacc v1 = pl[c0 + 64] + ph[c0 + 64];
+      const Tacc v2 = pl[c0 + 128] + ph[c0 + 128];
+      const Tacc v3 = pl[c0 + 192] + ph[c0 + 192];
+      o[c0] = v0;
+      o[c0 + 64] = v1;
+      o[c0 + 128] = v2;
+      o[c0 + 192] = v3;
+    }
+    for (; c0 < full; c0 += 64) o[c0] = pl[c0] + ph[c0];
+    if (c0 < w) {
+      const Tacc v = pl[c0] + ph[c0];
+      if (c0 + lane < w) o[c0] = v;
+    }
+  };
+
+  StageRegs<Tacc> regs;
+  if (tile_first < tile_end) issue(wave, tile_first * a.tile, regs);
+  for (int tl = tile_first; tl < tile_end; ++tl) {
+    const int T0 = tl * a.tile;
+    commit(T0, regs);
     __syncthreads();
+    // The next tile's leaves are in flight while this tile's levels run.
+    if (tl + 1 < tile_end) issue(wave, T0 + a.tile, regs);
+
+    for (int i = 1; i <= a.k; ++i) {
+      const Tacc *S = (i & 1) ? buf_a : buf_b;
+      Tacc *D = (i & 1) ? buf_b : buf_a;
+      const bool chained = FROM_INPUT && i == 1;
+      const int qe = head[1 + i];
+      if (i < a.k) {
+        for (int q = head[i] + wave; q < qe; q += kWaves) {
+          const Rec e = load_rec(rec, q);
+          merge_row(e, S, D + e.c + lane, T0, e.e, chained);
+        }
+      } else {
+        const int w = nt - T0 < a.tile ? nt - T0 : a.tile;
+        for (int q = head[i] + wave; q < qe; q += kWaves) {
+          const Rec e = load_rec(rec, q);
+          merge_row(e, S, out_base + e.c * bs.dst_stride + T0 + lane, T0, w, chained);
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -436,6 +470,139 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
       const int ts = t - e[j].y;
 #pragma unroll
       for (int i = 0; i < 4; ++i) v[j][i] = ts + i >= 0 ? row[ts + i] : Tacc(0);
+    }
+  }
+#pragma unroll
+  for (int span = 1; span < N; span *= 2)
+#pragma unroll
+    for (int j = 0; j < N; j += 2 * span) v[j] = v[j] + v[j + span];
+  Tacc *o = dst + bs.dst_off + r * bs.dst_stride + t;
+  if (t + 4 <= nt) {
+    *reinterpret_cast<V *>(o) = v[0];
+  } else {
+    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = v[0][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register gather straight from the input: the first k iterations and the
+// Option-1 initialisation in one pass. An output row of plane k is the tree
+// sum of its 2^k terms (InTerm), each term channel ch's partial sum
+// I[t - shift] + I[t - shift - 1] + ... + I[t - shift - chain], added in that
+// order, and the terms added as the recursion adds them. Every element
+// therefore equals the level-by-level result bit for bit. Work split as in
+// gather_pass_kernel; a lane loads 4 consecutive input samples per access.
+template <typename T>
+struct In4;
+template <>
+struct In4<float> {
+  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct In4<int32_t> {
+  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct In4<_Float16> {
+  typedef _Float16 type __attribute__((ext_vector_type(4), aligned(2)));
+};
+template <>
+struct In4<uint8_t> {
+  typedef uint8_t type __attribute__((ext_vector_type(4), aligned(1)));
+};
+
+template <typename Tin, typename Tacc, int K, bool RAGGED>
+__global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
+    const Tin *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ terms,
+    int32_t nt_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
+    int32_t rows_per_wg, RaggedMap rg) {
+  typedef typename Vec4<Tacc>::type V;
+  typedef typename In4<Tin>::type I4;
+  constexpr int N = 1 << K;
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
+  const int nt = bs.nt;
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256;  // first sample of the wave
+  const int t = tw + lane * 4;
+  if (t >= nt) return;
+  const Tin *base = src + bs.src_off;
+  const int4 *tm = terms + static_cast<int64_t>(r) * N;
+  int4 e[N];
+  int reach = 0;  // furthest sample back any term reads
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    e[j] = tm[j];
+    const int back = e[j].y + e[j].z;
+    reach = back > reach ? back : reach;
+  }
+  int longest = 0;  // longest chain of any term
+#pragma unroll
+  for (int j = 0; j < N; ++j) longest = e[j].z > longest ? e[j].z : longest;
+  V v[N];
+  if (std::is_same<Tin, uint8_t>::value && (reinterpret_cast<uintptr_t>(src) & 3) == 0 && tw >= reach &&
+      tw + 268 <= nt && longest <= 4) {
+    // Bytes: the misalignment of a term's samples is the same for every lane
+    // (t is a multiple of 4), so each lane loads the three aligned words from
+    // just before its window and shifts them into place. They start at most 3
+    // bytes before the window, never before the (word-aligned) buffer, and end
+    // at most 11 bytes after its first sample, inside the row as 12 samples
+    // follow the wave's last one. All loads are issued before any is used.
+    uint32_t w[N][3];
+    int mis[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + static_cast<int64_t>(e[j].x) * nt +
+                         (t - e[j].y - e[j].z);
+      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+      const uint32_t *q = reinterpret_cast<const uint32_t *>(p - mis[j]);
+      w[j][0] = q[0];
+      w[j][1] = q[1];
+      w[j][2] = q[2];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      // chain element i (sample t - shift - i) starts mis + chain - i bytes in
+      auto take = [&](int o) {
+        const uint32_t lo = o < 4 ? w[j][0] : w[j][1], hi = o < 4 ? w[j][1] : w[j][2];
+        const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+        V r;
+        r[0] = static_cast<Tacc>(x & 0xffu);
+        r[1] = static_cast<Tacc>((x >> 8) & 0xffu);
+        r[2] = static_cast<Tacc>((x >> 16) & 0xffu);
+        r[3] = static_cast<Tacc>(x >> 24);
+        return r;
+      };
+      const int d = e[j].z;
+      V acc = take(mis[j] + d);
+      for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + d - i);
+      v[j] = acc;
+    }
+  } else if (tw >= reach && tw + 256 <= nt) {  // every access of the wave inside [0, nt)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t - e[j].y);
+      V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
+      for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
+      v[j] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt;
+      const int ts = t - e[j].y;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        Tacc acc = (ts + i >= 0 && ts + i < nt) ? widen<Tacc>(p[ts + i]) : Tacc(0);
+        for (int d = 1; d <= e[j].z; ++d)
+          acc += (ts + i - d >= 0 && ts + i - d < nt) ? widen<Tacc>(p[ts + i - d]) : Tacc(0);
+        v[j][i] = acc;
+      }
     }
   }
 #pragma unroll
@@ -734,7 +901,7 @@ __global__ __launch_bounds__(kStagedThreads) void staged_pass_kernel(StagedArgs 
 size_t fused_lds_bytes(const Pass &ps) {
   if (ps.kind == PassKind::Staged)  // staged rows, partial sums, records, terms (4-byte units)
     return static_cast<size_t>(ps.lds_a + ps.lds_p + ps.lds_b + ps.max_recs) * 4;
-  return static_cast<size_t>(ps.lds_a + ps.lds_b) * 4 + static_cast<size_t>(ps.max_recs) * sizeof(Rec);
+  return static_cast<size_t>(ps.lds_a + ps.lds_b + 2 * kLdsSlack) * 4;  // two level buffers
 }
 
 View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, bool adjoint,
@@ -866,6 +1033,29 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
 #undef FDMT_STAGED
         return hipGetLastError();
       }
+      if (ps.gather && ps.from_input) {
+        const int k = ps.l1 - ps.l0;
+        if (k < 1 || k > 4) return hipErrorInvalidValue;
+        const int rpw = p.gather_rows;
+        const int tile = 256 * (kGatherThreads / 64 / rpw);
+        const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
+        const int32_t nt32 = static_cast<int32_t>(nt);
+        const int4 *tm = p.dev_iterms + ps.term_offset;
+        const Tin *sp = static_cast<const Tin *>(src.ptr);
+        Tacc *dp = static_cast<Tacc *>(dst.ptr);
+        return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+          constexpr bool R = decltype(r)::value;
+          const dim3 grid(gx, gy, gz);
+#define FDMT_IGATHER(KK) hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
+          switch (k) {
+            case 1: FDMT_IGATHER(1); break;
+            case 2: FDMT_IGATHER(2); break;
+            case 3: FDMT_IGATHER(3); break;
+            default: FDMT_IGATHER(4); break;
+          }
+#undef FDMT_IGATHER
+        });
+      }
       if (ps.gather) {
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
@@ -904,8 +1094,9 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
       a.tile = ps.tile;
       a.lds_a = ps.lds_a;
       a.lds_b = ps.lds_b;
+      a.tiles_per_wg = p.rec_tiles;
       const size_t lds = fused_lds_bytes(ps);
-      return for_each_launch(p, rb, st, false, ps.tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+      return for_each_launch(p, rb, st, false, ps.tile * p.rec_tiles, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         constexpr bool R = decltype(r)::value;
         const dim3 grid(static_cast<unsigned>(a.nblocks), gy, gz);
         if (ps.from_input)
@@ -1138,7 +1329,7 @@ int step_tile(const Plan &p, bool adjoint, int i) {
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;
-      return ps.gather ? gather_tile : ps.tile;
+      return ps.gather ? gather_tile : ps.tile * p.rec_tiles;
     }
   }
   return 0;

@@ -53,9 +53,11 @@ struct Plan {
   const Rec *dev_recs = nullptr;
   const int32_t *dev_heads = nullptr;
   const int2 *dev_terms = nullptr;
+  const int4 *dev_iterms = nullptr;
   const Rec *dev_stage = nullptr;
   const Rec *dev_psums = nullptr;
   int tiles_per_wg = 1;        // time tiles one staged workgroup streams over
+  int rec_tiles = 8;           // time tiles one level-by-level (LDS) workgroup runs
   int gather_rows = 8;         // output rows per register-gather workgroup
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;

@@ -398,21 +398,28 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
       return "";
     }
     if (kind == PassKind::Register) {
-      if (first) return "the first pass cannot be a register gather";
-      // Later iterations as register gathers: walking the tables down from
-      // each output row gives its 2^k (row, shift) terms of plane l0, in the
-      // order the recursion adds them (lower half before upper half).
+      // Iterations as register gathers: walking the tables down from each
+      // output row gives its 2^k (row, shift) terms of plane l0, in the order
+      // the recursion adds them (lower half before upper half). From the
+      // input, a plane-0 term is channel ch's Option-1 partial-sum row d:
+      // the chain of input samples at shifts sigma .. sigma + d.
       const int k = std::min(k_req, L - l0);
       if (k > 4) return "at most 4 iterations per register pass";
       Pass ps;
       ps.gather = true;
       ps.kind = PassKind::Register;
+      ps.from_input = first;
       ps.l0 = l0;
       ps.l1 = l0 + k;
-      ps.rows_in = t.total[l0];
+      ps.rows_in = first ? t.nf : t.total[l0];
       ps.rows_out = t.total[ps.l1];
-      ps.staged_rows = ps.rows_out << k;
-      ps.term_offset = static_cast<int64_t>(s.terms.size());
+      ps.term_offset = static_cast<int64_t>(first ? s.iterms.size() : s.terms.size());
+      std::vector<int32_t> channel_of;
+      if (first) {
+        channel_of.resize(t.total[0]);
+        for (int ch = 0; ch < t.nf; ++ch)
+          for (int d = 0; d < t.leaf_rows[ch]; ++d) channel_of[t.leaf_off[ch] + d] = ch;
+      }
       std::vector<Term> cur, nxt;
       for (int64_t r = 0; r < ps.rows_out; ++r) {
         cur.assign(1, Term{static_cast<int32_t>(r), 0});
@@ -427,7 +434,17 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
         }
         for (const Term &x : cur)
           if (x.row < 0 || x.row >= t.total[l0] || x.shift < 0) return "gather term out of range";
-        s.terms.insert(s.terms.end(), cur.begin(), cur.end());
+        if (first) {
+          for (const Term &x : cur) {
+            const int ch = channel_of[x.row];
+            const int d = x.row - t.leaf_off[ch];
+            s.iterms.push_back(InTerm{ch, x.shift, d, 0});
+            ps.staged_rows += d + 1;
+          }
+        } else {
+          s.terms.insert(s.terms.end(), cur.begin(), cur.end());
+          ps.staged_rows += static_cast<int64_t>(cur.size());
+        }
       }
       ps.nblocks = static_cast<int>(ps.rows_out);
       s.passes.push_back(ps);
@@ -455,10 +472,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
         Tree tr;  // level-by-level LDS pass
         for (;;) {
           tr = build_tree(t, first, l0, ps.l1, sub, r0, nr, p.tile);
-          int64_t rows = 0;
-          for (const Node &n : tr.nodes) rows += n.nrows;
-          const int64_t rec_elems = rows * static_cast<int64_t>(sizeof(Rec)) / p.acc_bytes;
-          if (tr.need[0] + tr.need[1] + rec_elems <= budget) break;
+          if (tr.need[0] + tr.need[1] + 2 * kLdsSlack <= budget) break;
           if (nr == 1) return "LDS budget too small for one row of pass " + std::to_string(l0);
           nr = std::max(1, nr * 3 / 4);
         }
@@ -500,7 +514,8 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
     for (;;) {
       // Remember the sizes so a pass that does not fit can be taken back.
       const size_t n_nodes = s.nodes.size(), n_recs = s.recs.size(), n_heads = s.heads.size(),
-                   n_terms = s.terms.size(), n_sterms = s.sterms.size(), n_stage = s.stage.size(),
+                   n_terms = s.terms.size(), n_iterms = s.iterms.size(), n_sterms = s.sterms.size(),
+                   n_stage = s.stage.size(),
                    n_psums = s.psums.size(), n_sheads = s.sheads.size();
       const std::string err = build_pass(s, t, p, l0, k, first);
       if (err.empty()) break;
@@ -508,6 +523,7 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
       s.recs.resize(n_recs);
       s.heads.resize(n_heads);
       s.terms.resize(n_terms);
+      s.iterms.resize(n_iterms);
       s.sterms.resize(n_sterms);
       s.stage.resize(n_stage);
       s.psums.resize(n_psums);

@@ -37,6 +37,9 @@ struct Rec {
 };
 
 constexpr int kRecHeader = 12;  // per block: first record, then level ends (k+1 values)
+// Elements past each level buffer of a level-by-level pass: a merge reads its
+// operands in whole 64-column groups, up to 63 columns past a row's end.
+constexpr int kLdsSlack = 64;
 
 // How a pass evaluates its iterations.
 enum class PassKind {
@@ -62,7 +65,8 @@ struct Pass {
   bool from_input = false;  // leaves are input channels (first pass)
   PassKind kind = PassKind::Staged;
   bool gather = false;      // kind == Register
-  int64_t term_offset = 0;  // Register: index of this pass's first Term in Schedule::terms;
+  int64_t term_offset = 0;  // Register: index of this pass's first Term in Schedule::terms
+                            // (from the input: first InTerm in Schedule::iterms);
                             // Staged: first StagedTerm in Schedule::sterms
   int l0 = 0, l1 = 0;       // consumes plane l0 (or the input), produces plane l1
   int tile = 0;             // W: output samples per block
@@ -72,7 +76,7 @@ struct Pass {
   int64_t node_offset = 0;  // index of this pass's first node in Schedule::nodes
   int64_t rec_offset = 0;   // index of this pass's first record in Schedule::recs
   int64_t head_offset = 0;  // index of this pass's first block header in Schedule::heads
-  int max_recs = 0;         // most records of any block (LDS is reserved for them)
+  int max_recs = 0;         // most records of any block (staged passes keep them in LDS)
   int64_t rows_in = 0;      // unique rows of the consumed plane (input: channels)
   int64_t rows_out = 0;     // rows of the produced plane
   int64_t staged_rows = 0;  // leaf rows staged, summed over blocks (overlap included)
@@ -99,6 +103,12 @@ struct Term {
   int32_t row, shift;
 };
 
+// A term of a register gather from the input: channel ch's Option-1 partial
+// sum of chain length `chain` (samples t - shift, t - shift - 1, ...).
+struct InTerm {
+  int32_t ch, shift, chain, pad;
+};
+
 struct Schedule {
   bool init_separate = false;   // the initialisation runs as its own step (writes plane 0)
   std::vector<Pass> passes;
@@ -106,6 +116,7 @@ struct Schedule {
   std::vector<Rec> recs;        // per block, level by level
   std::vector<int32_t> heads;   // kRecHeader per block: record base (pass-relative), level ends
   std::vector<Term> terms;      // register passes: 2^k terms per output row, recursion order
+  std::vector<InTerm> iterms;   // register pass from the input: 2^k terms per output row
   std::vector<StagedTerm> sterms;  // staged passes: 2^k terms per block row, recursion order
   std::vector<Rec> stage;       // staged passes: leaf rows (a = source row, c = LDS, d = win, e = width)
   std::vector<Rec> psums;       // staged first pass, per channel: a = LDS of partial-sum row 0,

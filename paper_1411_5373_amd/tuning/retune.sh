@@ -1,0 +1,19 @@
+#!/bin/bash
+# Re-tunes the schedules of the benchmark workloads on the current GPU and
+# writes them to the cache file given as $1 (default: this directory's
+# <arch>.json). Each workload takes a few seconds.
+set -e
+cd "$(dirname "$0")/../.."
+export FDMT_TUNE_CACHE=${1:-}
+T="python -u -m paper_1411_5373_amd.autotune --write"
+# Nf=4096, Nt=65536, Nd=2048, 1.2-1.6 GHz: the step's forms
+$T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype u8 --acc-dtype f32
+$T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype f16 --acc-dtype f32
+$T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
+$T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype u8 --acc-dtype i32
+$T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype i32 --acc-dtype i32
+# ragged beams (base plan Nt = the longest beam, 32511), Nf=1024, Nd=512
+$T --nf 1024 --nt 32768 --nd 512 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
+# Nf=1024, Nt=8192, Nd=1024 and the 0.4-0.8 GHz batch-16 form
+$T --nf 1024 --nt 8192 --nd 1024 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
+$T --nf 1024 --nt 16384 --nd 1024 --band 0.4 0.8 --in-dtype f32 --acc-dtype f32

@@ -269,6 +269,13 @@ SCHEDULES = [
     dict(first_levels=2, later_levels=3, tile=1024, lds_kib=96),
     dict(first_levels=4, later_levels=3, stream_tiles=1),
     dict(first_levels=4, later_levels=4, stream_tiles=5),
+    # level-by-level merges over several time tiles per workgroup
+    dict(first_levels=4, later_levels=2, first_kernel=2, later_kernel=2, stream_tiles=3),
+    # gathers straight from the input for the first pass
+    dict(first_levels=1, later_levels=2, first_kernel=3),
+    dict(first_levels=2, later_levels=3, first_kernel=3, gather_rows=4),
+    dict(first_levels=3, later_levels=3, first_kernel=3, gather_rows=16),
+    dict(first_levels=4, later_levels=4, first_kernel=3, gather_rows=1),
 ]
 
 

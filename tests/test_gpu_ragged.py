@@ -110,6 +110,26 @@ def test_ragged_adjoint_bitwise(nf, nd, band, unfused):
                 np.testing.assert_array_equal(xbb, oadj(g, *band, nf, acc=np.float32))
 
 
+@pytest.mark.parametrize("sched", [dict(first_kernel=3), dict(first_kernel=2, later_kernel=2, stream_tiles=3),
+                                   dict(first_levels=2, first_kernel=3, later_levels=4, gather_rows=2)])
+@pytest.mark.parametrize("nf,nd,band", [(256, 128, (1.2, 1.6)), (8, 300, (0.4, 0.8))])
+def test_ragged_other_kernel_forms(sched, nf, nd, band):
+    """Other pass kernels: ragged output bit-identical to the oracle per beam."""
+    print(f"ragged {sched} nf={nf} nd={nd}", flush=True)
+    xs = _beam_inputs(nf, LENGTHS, np.float32, 3 * nf + nd)
+    p = F.Plan(nf, 4096, nd, *band, **sched)
+    y = _unpack(F.RaggedPlan(p, LENGTHS).forward(_pack(xs, np.float32)).cpu().numpy(), nd, LENGTHS)
+    for x, yb, n in zip(xs, y, LENGTHS):
+        if n:
+            np.testing.assert_array_equal(yb, ofdmt(x, *band, nd, acc=np.float32))
+    xu = _beam_inputs(nf, LENGTHS, np.uint8, 5 * nf + nd)
+    pu = F.Plan(nf, 4096, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, **sched)
+    yu = _unpack(F.RaggedPlan(pu, LENGTHS).forward(_pack(xu, np.uint8)).cpu().numpy(), nd, LENGTHS)
+    for x, yb, n in zip(xu, yu, LENGTHS):
+        if n:
+            np.testing.assert_array_equal(yb.astype(np.int64), ofdmt(x, *band, nd))
+
+
 def test_ragged_all_empty_and_single_beam():
     p = F.Plan(64, 1000, 64, 1.2, 1.6)
     r = F.RaggedPlan(p, [0, 0])
