@@ -2,11 +2,11 @@
 fastest per workload in a JSON cache that `Plan(..., tuned=True)` consults.
 
 Every candidate is a set of `fdmt_options_t` schedule fields (kernel form and
-iterations of each pass, tile width, LDS budget, rows per gather workgroup,
-adjoint pass depths). Schedule fields never change results, only speed, so
-the tuner compares times alone. Forward and adjoint are tuned separately;
-the one field they share (rows per gather workgroup) is chosen to minimise
-their sum.
+iterations of each pass, tile width, LDS budget, rows and samples per gather
+workgroup, adjoint pass depths). Schedule fields never change results, only
+speed, so the tuner compares times alone. Forward and adjoint are tuned
+separately; the fields they share (the gather workgroup shape) are chosen to
+minimise their sum.
 
 Cache key: GPU architecture, Nf, Nd, band, input and accumulation dtypes and
 Nt rounded up to a power of two. The cache shipped with the package
@@ -37,7 +37,7 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
                   "max_block_rows", "stream_tiles")
 ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels")
-SHARED_FIELDS = ("gather_rows",)
+SHARED_FIELDS = ("gather_rows", "gather_vecs")
 
 
 def forward_candidates():
@@ -57,6 +57,7 @@ def adjoint_candidates():
 
 
 GATHER_ROWS = (4, 8)
+GATHER_VECS = (1, 2)
 
 
 def arch():
@@ -124,10 +125,11 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
     xb = torch.empty(nf, nt, device=dev, dtype=acc_dtype)
     tried = []
     best = {}
-    for rows in GATHER_ROWS:
+    for rows, vecs in [(r, v) for r in GATHER_ROWS for v in GATHER_VECS]:
+        shared = dict(gather_rows=rows, gather_vecs=vecs)
         fwd_best, adj_best = None, None
         for cand in forward_candidates():
-            opts = dict(cand, gather_rows=rows)
+            opts = dict(cand, **shared)
             try:
                 p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, **opts)
             except B.FDMTError:
@@ -141,7 +143,7 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
                 fwd_best = (ms, cand)
             del p, ws
         for cand in adjoint_candidates():
-            opts = dict(cand, gather_rows=rows)
+            opts = dict(cand, **shared)
             try:
                 p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, **opts)
             except B.FDMTError:
@@ -158,7 +160,7 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
             continue
         total = fwd_best[0] + adj_best[0]
         if not best or total < best["forward_ms"] + best["adjoint_ms"]:
-            best = {"options": dict(fwd_best[1], **adj_best[1], gather_rows=rows),
+            best = {"options": dict(fwd_best[1], **adj_best[1], **shared),
                     "forward_ms": round(fwd_best[0], 4), "adjoint_ms": round(adj_best[0], 4)}
     if not best:
         raise RuntimeError("no candidate schedule fits this workload")

@@ -178,7 +178,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
                         double f_max, const fdmt_options_t *opt) {
   if (!out) return fail(FDMT_E_INVALID, "out is NULL");
   *out = nullptr;
-  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (opt) o = *opt;
   if (nf < 1 || nf > 65536) return fail(FDMT_E_INVALID, "Nf must be in [1, 65536]");
   if ((nf & (nf - 1)) != 0) return fail(FDMT_E_UNSUPPORTED, "Nf must be a power of two");
@@ -200,6 +200,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_rows must be 1, 2, 4, 8 or 16");
   if (o.adjoint_levels < 0 || o.adjoint_levels > 5 || o.adjoint_last_levels < 0 || o.adjoint_last_levels > 4)
     return fail(FDMT_E_INVALID, "adjoint_levels must be in [1, 5], adjoint_last_levels in [1, 4]");
+  if (o.gather_vecs < 0 || o.gather_vecs > 2)
+    return fail(FDMT_E_INVALID, "gather_vecs must be 1 or 2");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED))
@@ -227,6 +229,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   p.flags = o.flags;
   if (o.stream_tiles) p.tiles_per_wg = p.rec_tiles = o.stream_tiles;
   if (o.gather_rows) p.gather_rows = o.gather_rows;
+  if (o.gather_vecs) p.gather_vecs = o.gather_vecs;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
   if (!(o.flags & FDMT_PLAN_UNFUSED)) {
     fdmt::ScheduleParams sp;
@@ -271,10 +274,16 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     }
   }
   fdmt::plan_steps(p);
-  // Time tiles run along the grid's y dimension (at most 65535 workgroups).
-  int64_t min_tile = 1024;
-  for (const fdmt::Pass &ps : p.fwd.passes)
-    if (!ps.gather) min_tile = std::min<int64_t>(min_tile, ps.tile);
+  // Time tiles of uniform batches run along the grid's y dimension (at most
+  // 65535 workgroups).
+  int64_t min_tile = INT32_MAX;
+  for (int adj = 0; adj < 2; ++adj) {
+    const int n = static_cast<int>(adj ? p.adj_steps.size() : p.fwd_steps.size());
+    for (int i = 0; i < n; ++i) {
+      const int w = fdmt::step_tile(p, adj != 0, i);
+      if (w > 0) min_tile = std::min<int64_t>(min_tile, w);
+    }
+  }
   if ((nt + min_tile - 1) / min_tile > 65535) {
     delete h;
     return fail(FDMT_E_UNSUPPORTED, "Nt too long for the time tile (more than 65535 tiles)");
@@ -358,7 +367,7 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->level_first = ps.from_input ? 0 : ps.l0 + 1;
       info->level_last = ps.l1;
       info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
-                                                          ((nt + 4096 / P.gather_rows - 1) / (4096 / P.gather_rows)))
+                                                          ((nt + 4096 * P.gather_vecs / P.gather_rows - 1) / (4096 * P.gather_vecs / P.gather_rows)))
                                    : static_cast<int32_t>(
                                          ps.nblocks *
                                          ((nt + ps.tile - 1) / ps.tile +
@@ -390,7 +399,7 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->level_first = ps.to_input ? 0 : ps.l_lo + 1;
       info->level_last = ps.l_hi;
       info->work_items = static_cast<int32_t>(((ps.nrows + P.gather_rows - 1) / P.gather_rows) *
-                                              ((nt + 4096 / P.gather_rows - 1) / (4096 / P.gather_rows)));
+                                              ((nt + 4096 * P.gather_vecs / P.gather_rows - 1) / (4096 * P.gather_vecs / P.gather_rows)));
       info->bytes_read = T.total[ps.l_hi] * nt * 4;
       info->bytes_written = static_cast<int64_t>(ps.nrows) * nt * 4;
       info->staged_bytes = ps.leaves * nt * 4;

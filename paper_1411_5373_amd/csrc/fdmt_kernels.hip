@@ -426,16 +426,17 @@ struct Vec4<int32_t> {
   typedef int type __attribute__((ext_vector_type(4), aligned(4)));
 };
 
-template <typename Tacc, int K, bool RAGGED>
+template <typename Tacc, int K, int CV, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
     int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
     int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   constexpr int N = 1 << K;
-  // A workgroup holds rows_per_wg consecutive output rows (one wave each, the
-  // rows share most terms, so repeats hit this CU's L1) over one tile of
-  // 256 * (kGatherThreads / 64 / rows_per_wg) samples.
+  // A workgroup holds rows_per_wg consecutive output rows (the rows share
+  // most terms, so repeats hit this CU's L1) over one tile of
+  // 256 * CV * (kGatherThreads / 64 / rows_per_wg) samples; a lane handles CV
+  // runs of 4 samples, 256 apart.
   const int waves = kGatherThreads / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;  // waves per row
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
   const int nt = bs.nt;
   const int64_t src_stride = bs.src_stride;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256;  // first sample of the wave
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
   if (t >= nt) return;
   const Tacc *base = src + bs.src_off;
@@ -458,29 +459,42 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     e[j] = tm[j];
     smax = e[j].y > smax ? e[j].y : smax;
   }
-  V v[N];
+  V v[N][CV];
   if (tw >= smax) {  // every term inside the record for the whole wave
 #pragma unroll
     for (int j = 0; j < N; ++j)
-      v[j] = *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t - e[j].y));
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        v[j][c] = t + 256 * c < nt
+                      ? *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y))
+                      : V(0);
   } else {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const Tacc *row = base + e[j].x * src_stride;
-      const int ts = t - e[j].y;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[j][i] = ts + i >= 0 ? row[ts + i] : Tacc(0);
+      for (int c = 0; c < CV; ++c) {
+        const int ts = t + 256 * c - e[j].y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i >= 0 && t + 256 * c < nt ? row[ts + i] : Tacc(0);
+      }
     }
   }
 #pragma unroll
   for (int span = 1; span < N; span *= 2)
 #pragma unroll
-    for (int j = 0; j < N; j += 2 * span) v[j] = v[j] + v[j + span];
-  Tacc *o = dst + bs.dst_off + r * bs.dst_stride + t;
-  if (t + 4 <= nt) {
-    *reinterpret_cast<V *>(o) = v[0];
-  } else {
-    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = v[0][i];
+    for (int j = 0; j < N; j += 2 * span)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
+#pragma unroll
+  for (int c = 0; c < CV; ++c) {
+    const int tc = t + 256 * c;
+    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    if (tc + 4 <= nt) {
+      *reinterpret_cast<V *>(o) = v[0][c];
+    } else {
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+    }
   }
 }
 
@@ -511,7 +525,7 @@ struct In4<uint8_t> {
   typedef uint8_t type __attribute__((ext_vector_type(4), aligned(1)));
 };
 
-template <typename Tin, typename Tacc, int K, bool RAGGED>
+template <typename Tin, typename Tacc, int K, int CV, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
     const Tin *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ terms,
     int32_t nt_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
@@ -528,92 +542,109 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
   if (r >= nrows) return;
   const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
   const int nt = bs.nt;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256;  // first sample of the wave
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
   if (t >= nt) return;
   const Tin *base = src + bs.src_off;
   const int4 *tm = terms + static_cast<int64_t>(r) * N;
   int4 e[N];
-  int reach = 0;  // furthest sample back any term reads
+  int reach = 0;    // furthest sample back any term reads
+  int longest = 0;  // longest chain of any term
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     e[j] = tm[j];
     const int back = e[j].y + e[j].z;
     reach = back > reach ? back : reach;
+    longest = e[j].z > longest ? e[j].z : longest;
   }
-  int longest = 0;  // longest chain of any term
-#pragma unroll
-  for (int j = 0; j < N; ++j) longest = e[j].z > longest ? e[j].z : longest;
-  V v[N];
+  V v[N][CV];
   if (std::is_same<Tin, uint8_t>::value && (reinterpret_cast<uintptr_t>(src) & 3) == 0 && tw >= reach &&
-      tw + 268 <= nt && longest <= 4) {
+      tw + 256 * CV + 12 <= nt && longest <= 4) {
     // Bytes: the misalignment of a term's samples is the same for every lane
     // (t is a multiple of 4), so each lane loads the three aligned words from
     // just before its window and shifts them into place. They start at most 3
     // bytes before the window, never before the (word-aligned) buffer, and end
     // at most 11 bytes after its first sample, inside the row as 12 samples
     // follow the wave's last one. All loads are issued before any is used.
-    uint32_t w[N][3];
+    uint32_t w[N][CV][3];
     int mis[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + static_cast<int64_t>(e[j].x) * nt +
                          (t - e[j].y - e[j].z);
       mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
-      const uint32_t *q = reinterpret_cast<const uint32_t *>(p - mis[j]);
-      w[j][0] = q[0];
-      w[j][1] = q[1];
-      w[j][2] = q[2];
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 256 * c - mis[j]);
+        w[j][c][0] = q[0];
+        w[j][c][1] = q[1];
+        w[j][c][2] = q[2];
+      }
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      // chain element i (sample t - shift - i) starts mis + chain - i bytes in
-      auto take = [&](int o) {
-        const uint32_t lo = o < 4 ? w[j][0] : w[j][1], hi = o < 4 ? w[j][1] : w[j][2];
-        const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
-        V r;
-        r[0] = static_cast<Tacc>(x & 0xffu);
-        r[1] = static_cast<Tacc>((x >> 8) & 0xffu);
-        r[2] = static_cast<Tacc>((x >> 16) & 0xffu);
-        r[3] = static_cast<Tacc>(x >> 24);
-        return r;
-      };
-      const int d = e[j].z;
-      V acc = take(mis[j] + d);
-      for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + d - i);
-      v[j] = acc;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        // chain element i (sample t - shift - i) starts mis + chain - i bytes in
+        auto take = [&](int o) {
+          const uint32_t lo = o < 4 ? w[j][c][0] : w[j][c][1], hi = o < 4 ? w[j][c][1] : w[j][c][2];
+          const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+          V r4;
+          r4[0] = static_cast<Tacc>(x & 0xffu);
+          r4[1] = static_cast<Tacc>((x >> 8) & 0xffu);
+          r4[2] = static_cast<Tacc>((x >> 16) & 0xffu);
+          r4[3] = static_cast<Tacc>(x >> 24);
+          return r4;
+        };
+        const int d = e[j].z;
+        V acc = take(mis[j] + d);
+        for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + d - i);
+        v[j][c] = acc;
+      }
     }
-  } else if (tw >= reach && tw + 256 <= nt) {  // every access of the wave inside [0, nt)
+  } else if (tw >= reach && tw + 256 * CV <= nt) {  // every access of the wave inside [0, nt)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t - e[j].y);
-      V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
-      for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
-      v[j] = acc;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t + 256 * c - e[j].y);
+        V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
+        for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
+        v[j][c] = acc;
+      }
     }
   } else {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const Tin *p = base + static_cast<int64_t>(e[j].x) * nt;
-      const int ts = t - e[j].y;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        Tacc acc = (ts + i >= 0 && ts + i < nt) ? widen<Tacc>(p[ts + i]) : Tacc(0);
-        for (int d = 1; d <= e[j].z; ++d)
-          acc += (ts + i - d >= 0 && ts + i - d < nt) ? widen<Tacc>(p[ts + i - d]) : Tacc(0);
-        v[j][i] = acc;
+      for (int c = 0; c < CV; ++c) {
+        const int ts = t + 256 * c - e[j].y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          Tacc acc = (ts + i >= 0 && ts + i < nt) ? widen<Tacc>(p[ts + i]) : Tacc(0);
+          for (int d = 1; d <= e[j].z; ++d)
+            acc += (ts + i - d >= 0 && ts + i - d < nt) ? widen<Tacc>(p[ts + i - d]) : Tacc(0);
+          v[j][c][i] = acc;
+        }
       }
     }
   }
 #pragma unroll
   for (int span = 1; span < N; span *= 2)
 #pragma unroll
-    for (int j = 0; j < N; j += 2 * span) v[j] = v[j] + v[j + span];
-  Tacc *o = dst + bs.dst_off + r * bs.dst_stride + t;
-  if (t + 4 <= nt) {
-    *reinterpret_cast<V *>(o) = v[0];
-  } else {
-    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = v[0][i];
+    for (int j = 0; j < N; j += 2 * span)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
+#pragma unroll
+  for (int c = 0; c < CV; ++c) {
+    const int tc = t + 256 * c;
+    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    if (tc + 4 <= nt) {
+      *reinterpret_cast<V *>(o) = v[0][c];
+    } else {
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+    }
   }
 }
 
@@ -630,13 +661,14 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
 // eight loads in flight before any is used.
 constexpr int kAdjChunk = 8;
 
-template <typename Tacc, int K, bool RAGGED>
+template <typename Tacc, int K, int CV, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
     const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u,
     int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride,
     int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
+  constexpr int kChunk = kAdjChunk / CV;  // leaves loaded at once
   const int waves = kGatherThreads / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
@@ -647,55 +679,71 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
   const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
   const int nt = bs.nt;
   const int64_t src_stride = bs.src_stride;
-  const int t = (bs.tile * col_waves + wave % col_waves) * 256 + lane * 4;
+  const int t = (bs.tile * col_waves + wave % col_waves) * 256 * CV + lane * 4;
   if (t >= nt) return;
   const Tacc *base = src + bs.src_off;
   const int x_begin = starts[r], x_end = starts[r + 1];
   const int out_row = order[r];
-  V acc[K];
+  V acc[K][CV];
 #pragma unroll
-  for (int d = 0; d < K; ++d) acc[d] = V(0);
-  for (int x0 = x_begin; x0 < x_end; x0 += kAdjChunk) {
-    const int n = x_end - x0 < kAdjChunk ? x_end - x0 : kAdjChunk;
-    int4 e[kAdjChunk];
-    V v[kAdjChunk];
+  for (int d = 0; d < K; ++d)
 #pragma unroll
-    for (int j = 0; j < kAdjChunk; ++j) {
+    for (int c = 0; c < CV; ++c) acc[d][c] = V(0);
+  for (int x0 = x_begin; x0 < x_end; x0 += kChunk) {
+    const int n = x_end - x0 < kChunk ? x_end - x0 : kChunk;
+    int4 e[kChunk];
+    V v[kChunk][CV];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
       if (j < n) {
         e[j] = leaves[x0 + j];
         const Tacc *row = base + e[j].x * src_stride;
-        const int ts = t + e[j].y;
-        if (ts + 4 <= nt) {
-          v[j] = *reinterpret_cast<const V *>(row + ts);
-        } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[j][i] = ts + i < nt ? row[ts + i] : Tacc(0);
+        for (int c = 0; c < CV; ++c) {
+          const int ts = t + 256 * c + e[j].y;
+          if (ts + 4 <= nt) {
+            v[j][c] = *reinterpret_cast<const V *>(row + ts);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i < nt ? row[ts + i] : Tacc(0);
+          }
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < kAdjChunk; ++j) {
+    for (int j = 0; j < kChunk; ++j) {
       if (j < n) {
         if (x0 + j != x_begin) {
           const int b = e[j].z;
 #pragma unroll
           for (int d = K - 1; d >= 1; --d)
-            if (d > b) acc[d - 1] = acc[d - 1] + acc[d];
+            if (d > b)
+#pragma unroll
+              for (int c = 0; c < CV; ++c) acc[d - 1][c] = acc[d - 1][c] + acc[d][c];
 #pragma unroll
           for (int d = 1; d < K; ++d)
-            if (d > b) acc[d] = V(0);
+            if (d > b)
+#pragma unroll
+              for (int c = 0; c < CV; ++c) acc[d][c] = V(0);
         }
-        acc[K - 1] = acc[K - 1] + v[j];
+#pragma unroll
+        for (int c = 0; c < CV; ++c) acc[K - 1][c] = acc[K - 1][c] + v[j][c];
       }
     }
   }
 #pragma unroll
-  for (int d = K - 1; d >= 1; --d) acc[d - 1] = acc[d - 1] + acc[d];
-  Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + t;
-  if (t + 4 <= nt) {
-    *reinterpret_cast<V *>(o) = acc[0];
-  } else {
-    for (int i = 0; i < 4 && t + i < nt; ++i) o[i] = acc[0][i];
+  for (int d = K - 1; d >= 1; --d)
+#pragma unroll
+    for (int c = 0; c < CV; ++c) acc[d - 1][c] = acc[d - 1][c] + acc[d][c];
+#pragma unroll
+  for (int c = 0; c < CV; ++c) {
+    const int tc = t + 256 * c;
+    Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + tc;
+    if (tc + 4 <= nt) {
+      *reinterpret_cast<V *>(o) = acc[0][c];
+    } else {
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = acc[0][c][i];
+    }
   }
 }
 
@@ -1037,7 +1085,8 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;
-        const int tile = 256 * (kGatherThreads / 64 / rpw);
+        const int cv = p.gather_vecs;
+        const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int4 *tm = p.dev_iterms + ps.term_offset;
@@ -1046,12 +1095,21 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           constexpr bool R = decltype(r)::value;
           const dim3 grid(gx, gy, gz);
-#define FDMT_IGATHER(KK) hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
-          switch (k) {
-            case 1: FDMT_IGATHER(1); break;
-            case 2: FDMT_IGATHER(2); break;
-            case 3: FDMT_IGATHER(3); break;
-            default: FDMT_IGATHER(4); break;
+#define FDMT_IGATHER(KK, CC) hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
+          if (cv == 2) {
+            switch (k) {
+              case 1: FDMT_IGATHER(1, 2); break;
+              case 2: FDMT_IGATHER(2, 2); break;
+              case 3: FDMT_IGATHER(3, 2); break;
+              default: FDMT_IGATHER(4, 2); break;
+            }
+          } else {
+            switch (k) {
+              case 1: FDMT_IGATHER(1, 1); break;
+              case 2: FDMT_IGATHER(2, 1); break;
+              case 3: FDMT_IGATHER(3, 1); break;
+              default: FDMT_IGATHER(4, 1); break;
+            }
           }
 #undef FDMT_IGATHER
         });
@@ -1060,7 +1118,8 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
-        const int tile = 256 * (kGatherThreads / 64 / rpw);
+        const int cv = p.gather_vecs;   // runs of 4 samples per lane: 1 or 2
+        const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int2 *tm = p.dev_terms + ps.term_offset;
@@ -1069,12 +1128,21 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           constexpr bool R = decltype(r)::value;
           const dim3 grid(gx, gy, gz);
-#define FDMT_GATHER(KK) hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
-          switch (k) {
-            case 1: FDMT_GATHER(1); break;
-            case 2: FDMT_GATHER(2); break;
-            case 3: FDMT_GATHER(3); break;
-            default: FDMT_GATHER(4); break;
+#define FDMT_GATHER(KK, CC) hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
+          if (cv == 2) {
+            switch (k) {
+              case 1: FDMT_GATHER(1, 2); break;
+              case 2: FDMT_GATHER(2, 2); break;
+              case 3: FDMT_GATHER(3, 2); break;
+              default: FDMT_GATHER(4, 2); break;
+            }
+          } else {
+            switch (k) {
+              case 1: FDMT_GATHER(1, 1); break;
+              case 2: FDMT_GATHER(2, 1); break;
+              case 3: FDMT_GATHER(3, 1); break;
+              default: FDMT_GATHER(4, 1); break;
+            }
           }
 #undef FDMT_GATHER
         });
@@ -1131,7 +1199,8 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       const AdjPass &ps = p.adj.passes[st.index];
       if (ps.depth < 1 || ps.depth > 5) return hipErrorInvalidValue;
       const int rpw = p.gather_rows;
-      const int tile = 256 * (kGatherThreads / 64 / rpw);
+      const int cv = p.gather_vecs;
+      const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
       const unsigned gx = static_cast<unsigned>((ps.nrows + rpw - 1) / rpw);
       const int4 *lv = p.dev_adj_leaves + ps.leaf_offset;
       const int32_t *sr = p.dev_adj_starts + ps.start_offset;
@@ -1142,13 +1211,23 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         constexpr bool R = decltype(r)::value;
         const dim3 grid(gx, gy, gz);
-#define FDMT_ADJ(KK) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw, rg)
-        switch (ps.depth) {
-          case 1: FDMT_ADJ(1); break;
-          case 2: FDMT_ADJ(2); break;
-          case 3: FDMT_ADJ(3); break;
-          case 4: FDMT_ADJ(4); break;
-          default: FDMT_ADJ(5); break;
+#define FDMT_ADJ(KK, CC) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw, rg)
+        if (cv == 2) {
+          switch (ps.depth) {
+            case 1: FDMT_ADJ(1, 2); break;
+            case 2: FDMT_ADJ(2, 2); break;
+            case 3: FDMT_ADJ(3, 2); break;
+            case 4: FDMT_ADJ(4, 2); break;
+            default: FDMT_ADJ(5, 2); break;
+          }
+        } else {
+          switch (ps.depth) {
+            case 1: FDMT_ADJ(1, 1); break;
+            case 2: FDMT_ADJ(2, 1); break;
+            case 3: FDMT_ADJ(3, 1); break;
+            case 4: FDMT_ADJ(4, 1); break;
+            default: FDMT_ADJ(5, 1); break;
+          }
         }
 #undef FDMT_ADJ
       });
@@ -1319,7 +1398,7 @@ hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch,
 
 int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
-  const int gather_tile = 256 * (kGatherThreads / 64 / p.gather_rows);
+  const int gather_tile = 256 * p.gather_vecs * (kGatherThreads / 64 / p.gather_rows);
   switch (st.kind) {
     case Step::Init:
     case Step::Merge:

@@ -59,6 +59,7 @@ struct Plan {
   int tiles_per_wg = 1;        // time tiles one staged workgroup streams over
   int rec_tiles = 8;           // time tiles one level-by-level (LDS) workgroup runs
   int gather_rows = 8;         // output rows per register-gather workgroup
+  int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1 or 2)
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
   std::vector<Step> fwd_steps, adj_steps;

@@ -179,3 +179,19 @@ def test_ragged_plan_errors_before_any_device_work():
     assert F.fdmt_ragged_workspace_bytes(None) == 0
     assert lib.fdmt_ragged_info(None, None, None, None) == B.FDMT_E_INVALID
     assert B.fdmt_ragged_destroy(None) is None
+
+
+def test_nt_limit_follows_the_smallest_time_tile():
+    """Uniform batches put time tiles on the grid's y axis (at most 65535):
+    the plan refuses an Nt that the narrowest step's tile cannot cover."""
+    # 16 rows per gather workgroup: 256-sample tiles
+    ok = 65535 * 256
+    F.Plan(64, ok, 64, 1.2, 1.6, host_only=True, gather_rows=16)
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(64, ok + 1, 64, 1.2, 1.6, host_only=True, gather_rows=16)
+    assert e.value.status == B.FDMT_E_UNSUPPORTED
+    # two runs of 4 samples per lane double the tile
+    F.Plan(64, ok + 1, 64, 1.2, 1.6, host_only=True, gather_rows=16, gather_vecs=2)
+    with pytest.raises(F.FDMTError) as e:
+        B.fdmt_plan(64, 1000, 64, 1.2, 1.6, flags=B.FDMT_PLAN_HOST_ONLY, gather_vecs=3)
+    assert e.value.status == B.FDMT_E_INVALID

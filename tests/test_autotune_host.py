@@ -37,7 +37,8 @@ def test_candidates_build_host_plans(nf, nd, band):
     for rows in A.GATHER_ROWS:
         for cand in A.forward_candidates() + A.adjoint_candidates():
             try:
-                F.Plan(nf, 8192, nd, *band, host_only=True, gather_rows=rows, **cand)
+                F.Plan(nf, 8192, nd, *band, host_only=True, gather_rows=rows, gather_vecs=A.GATHER_VECS[-1],
+                       **cand)
                 built += 1
             except F.FDMTError as e:
                 assert e.status == 2, str(e)

@@ -276,6 +276,10 @@ SCHEDULES = [
     dict(first_levels=2, later_levels=3, first_kernel=3, gather_rows=4),
     dict(first_levels=3, later_levels=3, first_kernel=3, gather_rows=16),
     dict(first_levels=4, later_levels=4, first_kernel=3, gather_rows=1),
+    # two runs of 4 samples per lane in every cache gather, forward and adjoint
+    dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=2),
+    dict(first_levels=4, later_levels=2, gather_rows=16, gather_vecs=2, adjoint_levels=3,
+         adjoint_last_levels=1),
 ]
 
 
@@ -299,3 +303,36 @@ def test_schedules_bit_identical(sched, nf, nt, nd, band):
     refi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, unfused=True).forward(xi)
     pi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, **sched)
     assert torch.equal(pi.forward(xi), refi)
+
+
+ADJOINT_SCHEDULES = [
+    dict(adjoint_levels=1, adjoint_last_levels=1),
+    dict(adjoint_levels=2, adjoint_last_levels=1, gather_rows=4),
+    dict(adjoint_levels=3, adjoint_last_levels=2, gather_rows=16),
+    dict(adjoint_levels=4, adjoint_last_levels=3, gather_rows=1),
+    dict(adjoint_levels=5, adjoint_last_levels=4),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_vecs=2),
+    dict(adjoint_levels=3, adjoint_last_levels=1, gather_rows=2, gather_vecs=2),
+]
+
+
+@pytest.mark.parametrize("sched", ADJOINT_SCHEDULES)
+@pytest.mark.parametrize("nf,nt,nd,band", [(256, 3001, 300, (1.2, 1.6)), (1024, 2000, 1024, (0.4, 0.8)),
+                                           (64, 50, 100, (1.2, 1.6)), (2, 500, 1999, (0.4, 0.8))])
+def test_adjoint_schedules_bit_identical(sched, nf, nt, nd, band):
+    """Any adjoint pass split gives the bits of the per-iteration transposes
+    (FP32), and the exact int64 oracle adjoint (int32)."""
+    print(f"adjoint schedule {sched} nf={nf} nt={nt} nd={nd}", flush=True)
+    g = torch.randn(nd, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(nf + nd))
+    ref = F.Plan(nf, nt, nd, *band, unfused=True).adjoint(g)
+    try:
+        p = F.Plan(nf, nt, nd, *band, **sched)
+    except F.FDMTError as e:
+        assert e.status == 2
+        pytest.skip(str(e))
+    assert torch.equal(p.adjoint(g), ref)
+    gi = torch.randint(-50, 50, (nd, nt), device=DEV, dtype=torch.int32,
+                       generator=torch.Generator(DEV).manual_seed(nt))
+    pi = F.Plan(nf, nt, nd, *band, in_dtype=torch.int32, acc_dtype=torch.int32, **sched)
+    got = pi.adjoint(gi).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(got, oadj(gi.cpu().numpy().astype(np.int64), *band, nf))
