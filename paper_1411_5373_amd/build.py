@@ -9,6 +9,7 @@ from __future__ import annotations
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
@@ -26,7 +27,7 @@ HIP_FLAGS = [
 ]
 CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
-HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_api.hip"]
+HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_gather.hip", "fdmt_adjoint.hip", "fdmt_api.hip"]
 CXX_SOURCES = ["fdmt_tables.cpp", "fdmt_schedule.cpp"]
 
 
@@ -42,15 +43,14 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     """Compile every source and link libfdmt.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in CXX_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
-    for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+    jobs = [(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+            for src in CXX_SOURCES]
+    jobs += [([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+             for src in HIP_SOURCES]
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as pool:
+        list(pool.map(lambda cmd: _run(cmd, verbose), jobs))
+    objs = [cmd[-1] for cmd in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -1,0 +1,98 @@
+// Device helpers shared by the FDMT kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fdmt_schedule.h"
+
+namespace fdmt {
+
+template <typename Tacc, typename Tin>
+__device__ __forceinline__ Tacc widen(Tin x) {
+  return static_cast<Tacc>(x);
+}
+template <>
+__device__ __forceinline__ float widen<float, _Float16>(_Float16 x) {
+  return static_cast<float>(x);
+}
+
+// Where a workgroup's beam lives. Uniform batches take the beam from
+// blockIdx.z and share one Nt; ragged batches look the tile (blockIdx.y) up in
+// host-built maps: beam b has its own Nt, its input/output start at
+// rows * (samples of the beams before it) and its workspace planes at
+// rows * (padded samples before it).
+struct RaggedMap {
+  const int4 *beam;   // per beam: {nt, padded nt, first sample, first padded sample}
+  const int2 *tiles;  // per tile of the launch: {beam, tile within the beam}
+  int32_t src_rows, dst_rows;      // rows per beam of the source / destination buffer
+  int32_t src_padded, dst_padded;  // 1: workspace plane (row stride = padded nt)
+};
+
+struct BeamSpan {
+  int nt, tile;                    // samples of the beam; tile index within the beam
+  int64_t src_off, dst_off;        // element offsets of the beam in src / dst
+  int64_t src_stride, dst_stride;  // row strides (elements)
+};
+
+template <bool RAGGED>
+__device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64_t src_stride,
+                                              int64_t src_bstride, int64_t dst_stride,
+                                              int64_t dst_bstride) {
+  BeamSpan b;
+  if constexpr (RAGGED) {
+    const int2 tb = rg.tiles[blockIdx.y];
+    const int4 bm = rg.beam[tb.x];
+    b.nt = bm.x;
+    b.tile = tb.y;
+    b.src_off = static_cast<int64_t>(rg.src_rows) * (rg.src_padded ? bm.w : bm.z);
+    b.dst_off = static_cast<int64_t>(rg.dst_rows) * (rg.dst_padded ? bm.w : bm.z);
+    b.src_stride = rg.src_padded ? bm.y : bm.x;
+    b.dst_stride = rg.dst_padded ? bm.y : bm.x;
+  } else {
+    b.nt = nt;
+    b.tile = blockIdx.y;
+    b.src_off = blockIdx.z * src_bstride;
+    b.dst_off = blockIdx.z * dst_bstride;
+    b.src_stride = src_stride;
+    b.dst_stride = dst_stride;
+  }
+  return b;
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so each XCD
+// runs a contiguous range of work items (neighbouring blocks share leaf rows
+// and time halos through that XCD's L2).
+__device__ __forceinline__ int xcd_local_order(int id, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = id & 7, slot = id >> 3;
+  return x * q + (x < r ? x : r) + slot;
+}
+
+
+
+// Block records and headers are read-only for the whole launch and the same
+// for every lane of a wave: reading them through the constant address space
+// makes them scalar loads.
+typedef const __attribute__((address_space(4))) int32_t *ConstInts;
+
+// Workgroup size of the register-gather kernels.
+constexpr int kGatherThreads = 1024;
+
+// Four consecutive elements at 4-byte alignment: one 16-byte global access.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct Vec4<int32_t> {
+  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
+};
+
+
+} // namespace fdmt

@@ -1,0 +1,314 @@
+// Register-gather kernels of the forward transform: later iterations from a
+// plane, and the first iterations straight from the input.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "fdmt_launch.h"
+
+namespace fdmt {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Register gather over k fused iterations: walking the tables down from an
+// output row of plane l1 gives 2^k terms (row of plane l0, accumulated shift
+// sigma); the output is their sum, evaluated as the recursion evaluates it:
+// sibling pairs first, then pairs of pairs, lower half before upper half.
+// A term whose time t - sigma is negative is zero (the record starts at 0),
+// and an upper half made only of such terms adds +0, so each element equals
+// the per-iteration result exactly (the copy rule).
+//
+// Work split: a workgroup covers 1024 consecutive samples of one output row,
+// 4 per lane; every term is one unaligned 16-byte load per lane, all issued
+// before any add. Rows run fastest in the workgroup order so neighbouring
+// rows - which share most of their terms - meet in one XCD's L2.
+template <typename Tacc, int K, int CV, bool RAGGED>
+__global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
+    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
+    int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
+    int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
+  typedef typename Vec4<Tacc>::type V;
+  constexpr int N = 1 << K;
+  // A workgroup holds rows_per_wg consecutive output rows (the rows share
+  // most terms, so repeats hit this CU's L1) over one tile of
+  // 256 * CV * (kGatherThreads / 64 / rows_per_wg) samples; a lane handles CV
+  // runs of 4 samples, 256 apart.
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;  // waves per row
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
+  const int nt = bs.nt;
+  const int64_t src_stride = bs.src_stride;
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int t = tw + lane * 4;
+  if (t >= nt) return;
+  const Tacc *base = src + bs.src_off;
+  const int2 *tm = terms + static_cast<int64_t>(r) * N;
+  int2 e[N];
+  int smax = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    e[j] = tm[j];
+    smax = e[j].y > smax ? e[j].y : smax;
+  }
+  V v[N][CV];
+  if (tw >= smax) {  // every term inside the record for the whole wave
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        v[j][c] = t + 256 * c < nt
+                      ? *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y))
+                      : V(0);
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tacc *row = base + e[j].x * src_stride;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const int ts = t + 256 * c - e[j].y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i >= 0 && t + 256 * c < nt ? row[ts + i] : Tacc(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int span = 1; span < N; span *= 2)
+#pragma unroll
+    for (int j = 0; j < N; j += 2 * span)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
+#pragma unroll
+  for (int c = 0; c < CV; ++c) {
+    const int tc = t + 256 * c;
+    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    if (tc + 4 <= nt) {
+      *reinterpret_cast<V *>(o) = v[0][c];
+    } else {
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register gather straight from the input: the first k iterations and the
+// Option-1 initialisation in one pass. An output row of plane k is the tree
+// sum of its 2^k terms (InTerm), each term channel ch's partial sum
+// I[t - shift] + I[t - shift - 1] + ... + I[t - shift - chain], added in that
+// order, and the terms added as the recursion adds them. Every element
+// therefore equals the level-by-level result bit for bit. Work split as in
+// gather_pass_kernel; a lane loads 4 consecutive input samples per access.
+template <typename T>
+struct In4;
+template <>
+struct In4<float> {
+  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct In4<int32_t> {
+  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct In4<_Float16> {
+  typedef _Float16 type __attribute__((ext_vector_type(4), aligned(2)));
+};
+template <>
+struct In4<uint8_t> {
+  typedef uint8_t type __attribute__((ext_vector_type(4), aligned(1)));
+};
+
+template <typename Tin, typename Tacc, int K, int CV, bool RAGGED>
+__global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
+    const Tin *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ terms,
+    int32_t nt_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
+    int32_t rows_per_wg, RaggedMap rg) {
+  typedef typename Vec4<Tacc>::type V;
+  typedef typename In4<Tin>::type I4;
+  constexpr int N = 1 << K;
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
+  const int nt = bs.nt;
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int t = tw + lane * 4;
+  if (t >= nt) return;
+  const Tin *base = src + bs.src_off;
+  const int4 *tm = terms + static_cast<int64_t>(r) * N;
+  int4 e[N];
+  int reach = 0;    // furthest sample back any term reads
+  int longest = 0;  // longest chain of any term
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    e[j] = tm[j];
+    const int back = e[j].y + e[j].z;
+    reach = back > reach ? back : reach;
+    longest = e[j].z > longest ? e[j].z : longest;
+  }
+  V v[N][CV];
+  if (std::is_same<Tin, uint8_t>::value && (reinterpret_cast<uintptr_t>(src) & 3) == 0 && tw >= reach &&
+      tw + 256 * CV + 12 <= nt && longest <= 4) {
+    // Bytes: the misalignment of a term's samples is the same for every lane
+    // (t is a multiple of 4), so each lane loads the three aligned words from
+    // just before its window and shifts them into place. They start at most 3
+    // bytes before the window, never before the (word-aligned) buffer, and end
+    // at most 11 bytes after its first sample, inside the row as 12 samples
+    // follow the wave's last one. All loads are issued before any is used.
+    uint32_t w[N][CV][3];
+    int mis[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + static_cast<int64_t>(e[j].x) * nt +
+                         (t - e[j].y - e[j].z);
+      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 256 * c - mis[j]);
+        w[j][c][0] = q[0];
+        w[j][c][1] = q[1];
+        w[j][c][2] = q[2];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        // chain element i (sample t - shift - i) starts mis + chain - i bytes in
+        auto take = [&](int o) {
+          const uint32_t lo = o < 4 ? w[j][c][0] : w[j][c][1], hi = o < 4 ? w[j][c][1] : w[j][c][2];
+          const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+          V r4;
+          r4[0] = static_cast<Tacc>(x & 0xffu);
+          r4[1] = static_cast<Tacc>((x >> 8) & 0xffu);
+          r4[2] = static_cast<Tacc>((x >> 16) & 0xffu);
+          r4[3] = static_cast<Tacc>(x >> 24);
+          return r4;
+        };
+        const int d = e[j].z;
+        V acc = take(mis[j] + d);
+        for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + d - i);
+        v[j][c] = acc;
+      }
+    }
+  } else if (tw >= reach && tw + 256 * CV <= nt) {  // every access of the wave inside [0, nt)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t + 256 * c - e[j].y);
+        V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
+        for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
+        v[j][c] = acc;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt;
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const int ts = t + 256 * c - e[j].y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          Tacc acc = (ts + i >= 0 && ts + i < nt) ? widen<Tacc>(p[ts + i]) : Tacc(0);
+          for (int d = 1; d <= e[j].z; ++d)
+            acc += (ts + i - d >= 0 && ts + i - d < nt) ? widen<Tacc>(p[ts + i - d]) : Tacc(0);
+          v[j][c][i] = acc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int span = 1; span < N; span *= 2)
+#pragma unroll
+    for (int j = 0; j < N; j += 2 * span)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
+#pragma unroll
+  for (int c = 0; c < CV; ++c) {
+    const int tc = t + 256 * c;
+    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    if (tc + 4 <= nt) {
+      *reinterpret_cast<V *>(o) = v[0][c];
+    } else {
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+    }
+  }
+}
+
+} // namespace
+
+template <typename Tacc>
+hipError_t launch_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int2 *terms, int32_t nt,
+                         int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                         int32_t nrows) {
+#define FDMT_GATHER(KK, CC, RR)                                                                             \
+  hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, g.stream, src, dst, \
+                     terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, g.rows_per_wg, g.rg)
+#define FDMT_GATHER_K(CC, RR)             \
+  switch (g.depth) {                      \
+    case 1: FDMT_GATHER(1, CC, RR); break; \
+    case 2: FDMT_GATHER(2, CC, RR); break; \
+    case 3: FDMT_GATHER(3, CC, RR); break; \
+    case 4: FDMT_GATHER(4, CC, RR); break; \
+    default: return hipErrorInvalidValue; \
+  }
+  if (g.ragged) {
+    if (g.vecs == 2) { FDMT_GATHER_K(2, true) } else { FDMT_GATHER_K(1, true) }
+  } else {
+    if (g.vecs == 2) { FDMT_GATHER_K(2, false) } else { FDMT_GATHER_K(1, false) }
+  }
+#undef FDMT_GATHER_K
+#undef FDMT_GATHER
+  return hipGetLastError();
+}
+
+template <typename Tin, typename Tacc>
+hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tacc *dst, const int4 *terms, int32_t nt,
+                               int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows) {
+#define FDMT_IGATHER(KK, CC, RR)                                                                   \
+  hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, g.stream, \
+                     src, dst, terms, nt, src_bstride, dst_stride, dst_bstride, nrows, g.rows_per_wg, g.rg)
+#define FDMT_IGATHER_K(CC, RR)             \
+  switch (g.depth) {                       \
+    case 1: FDMT_IGATHER(1, CC, RR); break; \
+    case 2: FDMT_IGATHER(2, CC, RR); break; \
+    case 3: FDMT_IGATHER(3, CC, RR); break; \
+    case 4: FDMT_IGATHER(4, CC, RR); break; \
+    default: return hipErrorInvalidValue;  \
+  }
+  if (g.ragged) {
+    if (g.vecs == 2) { FDMT_IGATHER_K(2, true) } else { FDMT_IGATHER_K(1, true) }
+  } else {
+    if (g.vecs == 2) { FDMT_IGATHER_K(2, false) } else { FDMT_IGATHER_K(1, false) }
+  }
+#undef FDMT_IGATHER_K
+#undef FDMT_IGATHER
+  return hipGetLastError();
+}
+
+template hipError_t launch_gather<float>(const GatherLaunch &, const float *, float *, const int2 *, int32_t,
+                                         int64_t, int64_t, int64_t, int64_t, int32_t);
+template hipError_t launch_gather<int32_t>(const GatherLaunch &, const int32_t *, int32_t *, const int2 *,
+                                           int32_t, int64_t, int64_t, int64_t, int64_t, int32_t);
+#define FDMT_IG_INST(TI, TA)                                                                                  \
+  template hipError_t launch_input_gather<TI, TA>(const GatherLaunch &, const TI *, TA *, const int4 *, int32_t, \
+                                                  int64_t, int64_t, int64_t, int32_t);
+FDMT_IG_INST(float, float)
+FDMT_IG_INST(_Float16, float)
+FDMT_IG_INST(uint8_t, float)
+FDMT_IG_INST(uint8_t, int32_t)
+FDMT_IG_INST(int32_t, int32_t)
+#undef FDMT_IG_INST
+
+} // namespace fdmt

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "fdmt_launch.h"
 #include "fdmt_plan.h"
 
 namespace fdmt {
@@ -21,58 +22,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPerThread = 4;
 constexpr int kTile = kThreads * kPerThread;  // samples per workgroup
-
-template <typename Tacc, typename Tin>
-__device__ __forceinline__ Tacc widen(Tin x) {
-  return static_cast<Tacc>(x);
-}
-template <>
-__device__ __forceinline__ float widen<float, _Float16>(_Float16 x) {
-  return static_cast<float>(x);
-}
-
-// Where a workgroup's beam lives. Uniform batches take the beam from
-// blockIdx.z and share one Nt; ragged batches look the tile (blockIdx.y) up in
-// host-built maps: beam b has its own Nt, its input/output start at
-// rows * (samples of the beams before it) and its workspace planes at
-// rows * (padded samples before it).
-struct RaggedMap {
-  const int4 *beam;   // per beam: {nt, padded nt, first sample, first padded sample}
-  const int2 *tiles;  // per tile of the launch: {beam, tile within the beam}
-  int32_t src_rows, dst_rows;      // rows per beam of the source / destination buffer
-  int32_t src_padded, dst_padded;  // 1: workspace plane (row stride = padded nt)
-};
-
-struct BeamSpan {
-  int nt, tile;                    // samples of the beam; tile index within the beam
-  int64_t src_off, dst_off;        // element offsets of the beam in src / dst
-  int64_t src_stride, dst_stride;  // row strides (elements)
-};
-
-template <bool RAGGED>
-__device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64_t src_stride,
-                                              int64_t src_bstride, int64_t dst_stride,
-                                              int64_t dst_bstride) {
-  BeamSpan b;
-  if constexpr (RAGGED) {
-    const int2 tb = rg.tiles[blockIdx.y];
-    const int4 bm = rg.beam[tb.x];
-    b.nt = bm.x;
-    b.tile = tb.y;
-    b.src_off = static_cast<int64_t>(rg.src_rows) * (rg.src_padded ? bm.w : bm.z);
-    b.dst_off = static_cast<int64_t>(rg.dst_rows) * (rg.dst_padded ? bm.w : bm.z);
-    b.src_stride = rg.src_padded ? bm.y : bm.x;
-    b.dst_stride = rg.dst_padded ? bm.y : bm.x;
-  } else {
-    b.nt = nt;
-    b.tile = blockIdx.y;
-    b.src_off = blockIdx.z * src_bstride;
-    b.dst_off = blockIdx.z * dst_bstride;
-    b.src_stride = src_stride;
-    b.dst_stride = dst_stride;
-  }
-  return b;
-}
 
 // ---------------------------------------------------------------------------
 // Option-1 initialisation (Sec. 4): row d of channel k holds
@@ -205,17 +154,6 @@ struct FusedArgs {
   int32_t tiles_per_wg; // consecutive time tiles one workgroup runs
 };
 
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Workgroups are dealt round-robin to the 8 XCDs; renumber them so each XCD
-// runs a contiguous range of work items (neighbouring blocks share leaf rows
-// and time halos through that XCD's L2).
-__device__ __forceinline__ int xcd_local_order(int id, int n) {
-  const int q = n >> 3, r = n & 7;
-  const int x = id & 7, slot = id >> 3;
-  return x * q + (x < r ? x : r) + slot;
-}
-
 // Option-1 partial sum of chain length n at column c: x[c] + x[c-1] + ... + x[c-n].
 template <typename Tacc>
 __device__ __forceinline__ Tacc chain(const Tacc *x, int c, int n) {
@@ -233,10 +171,6 @@ struct StageRegs {
   int wd[2], dst[2];
 };
 
-// Block records and headers are read-only for the whole launch and the same
-// for every lane of a wave: reading them through the constant address space
-// makes them scalar loads.
-typedef const __attribute__((address_space(4))) int32_t *ConstInts;
 
 __device__ __forceinline__ Rec load_rec(ConstInts recs, int q) {
   const ConstInts r = recs + 8 * q;
@@ -398,354 +332,6 @@ struct View {
   void *ptr;
   int64_t stride, bstride;
 };
-
-// ---------------------------------------------------------------------------
-// Register gather over k fused iterations: walking the tables down from an
-// output row of plane l1 gives 2^k terms (row of plane l0, accumulated shift
-// sigma); the output is their sum, evaluated as the recursion evaluates it:
-// sibling pairs first, then pairs of pairs, lower half before upper half.
-// A term whose time t - sigma is negative is zero (the record starts at 0),
-// and an upper half made only of such terms adds +0, so each element equals
-// the per-iteration result exactly (the copy rule).
-//
-// Work split: a workgroup covers 1024 consecutive samples of one output row,
-// 4 per lane; every term is one unaligned 16-byte load per lane, all issued
-// before any add. Rows run fastest in the workgroup order so neighbouring
-// rows - which share most of their terms - meet in one XCD's L2.
-constexpr int kGatherThreads = 1024;
-
-// Four consecutive elements at 4-byte alignment: one 16-byte global access.
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
-};
-template <>
-struct Vec4<int32_t> {
-  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
-};
-
-template <typename Tacc, int K, int CV, bool RAGGED>
-__global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
-    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
-    int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
-    int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
-  typedef typename Vec4<Tacc>::type V;
-  constexpr int N = 1 << K;
-  // A workgroup holds rows_per_wg consecutive output rows (the rows share
-  // most terms, so repeats hit this CU's L1) over one tile of
-  // 256 * CV * (kGatherThreads / 64 / rows_per_wg) samples; a lane handles CV
-  // runs of 4 samples, 256 apart.
-  const int waves = kGatherThreads / 64;
-  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;  // waves per row
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int g = xcd_local_order(blockIdx.x, groups);
-  const int r = g * rows_per_wg + wave / col_waves;
-  if (r >= nrows) return;
-  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
-  const int nt = bs.nt;
-  const int64_t src_stride = bs.src_stride;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
-  const int t = tw + lane * 4;
-  if (t >= nt) return;
-  const Tacc *base = src + bs.src_off;
-  const int2 *tm = terms + static_cast<int64_t>(r) * N;
-  int2 e[N];
-  int smax = 0;
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    e[j] = tm[j];
-    smax = e[j].y > smax ? e[j].y : smax;
-  }
-  V v[N][CV];
-  if (tw >= smax) {  // every term inside the record for the whole wave
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int c = 0; c < CV; ++c)
-        v[j][c] = t + 256 * c < nt
-                      ? *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y))
-                      : V(0);
-  } else {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const Tacc *row = base + e[j].x * src_stride;
-#pragma unroll
-      for (int c = 0; c < CV; ++c) {
-        const int ts = t + 256 * c - e[j].y;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i >= 0 && t + 256 * c < nt ? row[ts + i] : Tacc(0);
-      }
-    }
-  }
-#pragma unroll
-  for (int span = 1; span < N; span *= 2)
-#pragma unroll
-    for (int j = 0; j < N; j += 2 * span)
-#pragma unroll
-      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
-#pragma unroll
-  for (int c = 0; c < CV; ++c) {
-    const int tc = t + 256 * c;
-    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
-    if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = v[0][c];
-    } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Register gather straight from the input: the first k iterations and the
-// Option-1 initialisation in one pass. An output row of plane k is the tree
-// sum of its 2^k terms (InTerm), each term channel ch's partial sum
-// I[t - shift] + I[t - shift - 1] + ... + I[t - shift - chain], added in that
-// order, and the terms added as the recursion adds them. Every element
-// therefore equals the level-by-level result bit for bit. Work split as in
-// gather_pass_kernel; a lane loads 4 consecutive input samples per access.
-template <typename T>
-struct In4;
-template <>
-struct In4<float> {
-  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
-};
-template <>
-struct In4<int32_t> {
-  typedef int type __attribute__((ext_vector_type(4), aligned(4)));
-};
-template <>
-struct In4<_Float16> {
-  typedef _Float16 type __attribute__((ext_vector_type(4), aligned(2)));
-};
-template <>
-struct In4<uint8_t> {
-  typedef uint8_t type __attribute__((ext_vector_type(4), aligned(1)));
-};
-
-template <typename Tin, typename Tacc, int K, int CV, bool RAGGED>
-__global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
-    const Tin *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ terms,
-    int32_t nt_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
-    int32_t rows_per_wg, RaggedMap rg) {
-  typedef typename Vec4<Tacc>::type V;
-  typedef typename In4<Tin>::type I4;
-  constexpr int N = 1 << K;
-  const int waves = kGatherThreads / 64;
-  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int g = xcd_local_order(blockIdx.x, groups);
-  const int r = g * rows_per_wg + wave / col_waves;
-  if (r >= nrows) return;
-  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
-  const int nt = bs.nt;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
-  const int t = tw + lane * 4;
-  if (t >= nt) return;
-  const Tin *base = src + bs.src_off;
-  const int4 *tm = terms + static_cast<int64_t>(r) * N;
-  int4 e[N];
-  int reach = 0;    // furthest sample back any term reads
-  int longest = 0;  // longest chain of any term
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    e[j] = tm[j];
-    const int back = e[j].y + e[j].z;
-    reach = back > reach ? back : reach;
-    longest = e[j].z > longest ? e[j].z : longest;
-  }
-  V v[N][CV];
-  if (std::is_same<Tin, uint8_t>::value && (reinterpret_cast<uintptr_t>(src) & 3) == 0 && tw >= reach &&
-      tw + 256 * CV + 12 <= nt && longest <= 4) {
-    // Bytes: the misalignment of a term's samples is the same for every lane
-    // (t is a multiple of 4), so each lane loads the three aligned words from
-    // just before its window and shifts them into place. They start at most 3
-    // bytes before the window, never before the (word-aligned) buffer, and end
-    // at most 11 bytes after its first sample, inside the row as 12 samples
-    // follow the wave's last one. All loads are issued before any is used.
-    uint32_t w[N][CV][3];
-    int mis[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + static_cast<int64_t>(e[j].x) * nt +
-                         (t - e[j].y - e[j].z);
-      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
-#pragma unroll
-      for (int c = 0; c < CV; ++c) {
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 256 * c - mis[j]);
-        w[j][c][0] = q[0];
-        w[j][c][1] = q[1];
-        w[j][c][2] = q[2];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-      for (int c = 0; c < CV; ++c) {
-        // chain element i (sample t - shift - i) starts mis + chain - i bytes in
-        auto take = [&](int o) {
-          const uint32_t lo = o < 4 ? w[j][c][0] : w[j][c][1], hi = o < 4 ? w[j][c][1] : w[j][c][2];
-          const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
-          V r4;
-          r4[0] = static_cast<Tacc>(x & 0xffu);
-          r4[1] = static_cast<Tacc>((x >> 8) & 0xffu);
-          r4[2] = static_cast<Tacc>((x >> 16) & 0xffu);
-          r4[3] = static_cast<Tacc>(x >> 24);
-          return r4;
-        };
-        const int d = e[j].z;
-        V acc = take(mis[j] + d);
-        for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + d - i);
-        v[j][c] = acc;
-      }
-    }
-  } else if (tw >= reach && tw + 256 * CV <= nt) {  // every access of the wave inside [0, nt)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-      for (int c = 0; c < CV; ++c) {
-        const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t + 256 * c - e[j].y);
-        V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
-        for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
-        v[j][c] = acc;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt;
-#pragma unroll
-      for (int c = 0; c < CV; ++c) {
-        const int ts = t + 256 * c - e[j].y;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          Tacc acc = (ts + i >= 0 && ts + i < nt) ? widen<Tacc>(p[ts + i]) : Tacc(0);
-          for (int d = 1; d <= e[j].z; ++d)
-            acc += (ts + i - d >= 0 && ts + i - d < nt) ? widen<Tacc>(p[ts + i - d]) : Tacc(0);
-          v[j][c][i] = acc;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int span = 1; span < N; span *= 2)
-#pragma unroll
-    for (int j = 0; j < N; j += 2 * span)
-#pragma unroll
-      for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
-#pragma unroll
-  for (int c = 0; c < CV; ++c) {
-    const int tc = t + 256 * c;
-    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
-    if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = v[0][c];
-    } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint over several iterations as a register gather. An output row (of
-// plane l_lo, or an input channel in the last pass) is a nested sum whose
-// leaves are rows of plane l_hi at accumulated shifts (AdjLeaf, host-built in
-// depth-first order). One accumulator per tree depth reproduces the order of
-// the level-by-level transpose exactly: before a leaf whose path leaves the
-// previous one below depth b, the finished nodes deeper than b are added to
-// their parents (deepest first) and restarted from zero; each leaf is added
-// to its parent at depth K-1. A leaf sample at or past nt is zero, which is
-// the transpose's "t + s < nt" rule. Leaves are loaded eight at a time, all
-// eight loads in flight before any is used.
-constexpr int kAdjChunk = 8;
-
-template <typename Tacc, int K, int CV, bool RAGGED>
-__global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
-    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
-    const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u,
-    int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride,
-    int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
-  typedef typename Vec4<Tacc>::type V;
-  constexpr int kChunk = kAdjChunk / CV;  // leaves loaded at once
-  const int waves = kGatherThreads / 64;
-  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int g = xcd_local_order(blockIdx.x, groups);
-  const int r = g * rows_per_wg + wave / col_waves;
-  if (r >= nrows) return;
-  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
-  const int nt = bs.nt;
-  const int64_t src_stride = bs.src_stride;
-  const int t = (bs.tile * col_waves + wave % col_waves) * 256 * CV + lane * 4;
-  if (t >= nt) return;
-  const Tacc *base = src + bs.src_off;
-  const int x_begin = starts[r], x_end = starts[r + 1];
-  const int out_row = order[r];
-  V acc[K][CV];
-#pragma unroll
-  for (int d = 0; d < K; ++d)
-#pragma unroll
-    for (int c = 0; c < CV; ++c) acc[d][c] = V(0);
-  for (int x0 = x_begin; x0 < x_end; x0 += kChunk) {
-    const int n = x_end - x0 < kChunk ? x_end - x0 : kChunk;
-    int4 e[kChunk];
-    V v[kChunk][CV];
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (j < n) {
-        e[j] = leaves[x0 + j];
-        const Tacc *row = base + e[j].x * src_stride;
-#pragma unroll
-        for (int c = 0; c < CV; ++c) {
-          const int ts = t + 256 * c + e[j].y;
-          if (ts + 4 <= nt) {
-            v[j][c] = *reinterpret_cast<const V *>(row + ts);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i < nt ? row[ts + i] : Tacc(0);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (j < n) {
-        if (x0 + j != x_begin) {
-          const int b = e[j].z;
-#pragma unroll
-          for (int d = K - 1; d >= 1; --d)
-            if (d > b)
-#pragma unroll
-              for (int c = 0; c < CV; ++c) acc[d - 1][c] = acc[d - 1][c] + acc[d][c];
-#pragma unroll
-          for (int d = 1; d < K; ++d)
-            if (d > b)
-#pragma unroll
-              for (int c = 0; c < CV; ++c) acc[d][c] = V(0);
-        }
-#pragma unroll
-        for (int c = 0; c < CV; ++c) acc[K - 1][c] = acc[K - 1][c] + v[j][c];
-      }
-    }
-  }
-#pragma unroll
-  for (int d = K - 1; d >= 1; --d)
-#pragma unroll
-    for (int c = 0; c < CV; ++c) acc[d - 1][c] = acc[d - 1][c] + acc[d][c];
-#pragma unroll
-  for (int c = 0; c < CV; ++c) {
-    const int tc = t + 256 * c;
-    Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + tc;
-    if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = acc[0][c];
-    } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = acc[0][c][i];
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Staged gather over k fused iterations. A block is a row range of one
@@ -982,14 +568,15 @@ constexpr int64_t kMaxGridY = 65535;
 // Issues the launches of one step over time tiles of width `tile`. A uniform
 // batch is one launch: ceil(nt / tile) tiles in grid y, beams in grid z. A
 // ragged batch walks the flattened tile map of that width, at most 65535
-// tiles per launch. `launch(ragged, grid_y, grid_z, map)` issues one launch.
+// tiles per launch. `launch(ragged, grid_y, grid_z, map)` issues one launch
+// and returns its status.
 template <typename F>
 hipError_t for_each_launch(const Plan &p, const RaggedBatch *rb, const Step &st, bool adjoint,
                            int tile, int batch, F &&launch) {
   if (rb == nullptr) {
-    launch(std::false_type{}, static_cast<unsigned>((p.nt + tile - 1) / tile),
-           static_cast<unsigned>(batch), RaggedMap{});
-    return hipGetLastError();
+    const hipError_t e = launch(std::false_type{}, static_cast<unsigned>((p.nt + tile - 1) / tile),
+                                static_cast<unsigned>(batch), RaggedMap{});
+    return e != hipSuccess ? e : hipGetLastError();
   }
   const RaggedBatch::Map *m = nullptr;
   for (const RaggedBatch::Map &x : rb->maps)
@@ -1003,8 +590,8 @@ hipError_t for_each_launch(const Plan &p, const RaggedBatch *rb, const Step &st,
   rg.dst_padded = st.dst == Buf::Ws0 || st.dst == Buf::Ws1;
   for (int64_t off = 0; off < m->count; off += kMaxGridY) {
     rg.tiles = m->tiles + off;
-    launch(std::true_type{}, static_cast<unsigned>(std::min(kMaxGridY, m->count - off)), 1u, rg);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = launch(std::true_type{}, static_cast<unsigned>(std::min(kMaxGridY, m->count - off)), 1u, rg);
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1023,6 +610,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0, stream,
                            static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
                            p.dev.leaf_off, p.dev.leaf_rows, nt, src.bstride, dst.stride, dst.bstride, rg);
+        return hipSuccess;
       });
     case Step::Merge:
       return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
@@ -1030,6 +618,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
                            dim3(static_cast<unsigned>(T.total[st.index]), gy, gz), dim3(kThreads), 0, stream,
                            static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
                            p.dev.merge[st.index], nt, src.stride, src.bstride, dst.stride, dst.bstride, rg);
+        return hipSuccess;
       });
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
@@ -1093,25 +682,9 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const Tin *sp = static_cast<const Tin *>(src.ptr);
         Tacc *dp = static_cast<Tacc *>(dst.ptr);
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-          constexpr bool R = decltype(r)::value;
-          const dim3 grid(gx, gy, gz);
-#define FDMT_IGATHER(KK, CC) hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
-          if (cv == 2) {
-            switch (k) {
-              case 1: FDMT_IGATHER(1, 2); break;
-              case 2: FDMT_IGATHER(2, 2); break;
-              case 3: FDMT_IGATHER(3, 2); break;
-              default: FDMT_IGATHER(4, 2); break;
-            }
-          } else {
-            switch (k) {
-              case 1: FDMT_IGATHER(1, 1); break;
-              case 2: FDMT_IGATHER(2, 1); break;
-              case 3: FDMT_IGATHER(3, 1); break;
-              default: FDMT_IGATHER(4, 1); break;
-            }
-          }
-#undef FDMT_IGATHER
+          const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          return launch_input_gather<Tin, Tacc>(g, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride,
+                                                ps.nblocks);
         });
       }
       if (ps.gather) {
@@ -1126,25 +699,9 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const Tacc *sp = static_cast<const Tacc *>(src.ptr);
         Tacc *dp = static_cast<Tacc *>(dst.ptr);
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-          constexpr bool R = decltype(r)::value;
-          const dim3 grid(gx, gy, gz);
-#define FDMT_GATHER(KK, CC) hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nblocks, rpw, rg)
-          if (cv == 2) {
-            switch (k) {
-              case 1: FDMT_GATHER(1, 2); break;
-              case 2: FDMT_GATHER(2, 2); break;
-              case 3: FDMT_GATHER(3, 2); break;
-              default: FDMT_GATHER(4, 2); break;
-            }
-          } else {
-            switch (k) {
-              case 1: FDMT_GATHER(1, 1); break;
-              case 2: FDMT_GATHER(2, 1); break;
-              case 3: FDMT_GATHER(3, 1); break;
-              default: FDMT_GATHER(4, 1); break;
-            }
-          }
-#undef FDMT_GATHER
+          const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          return launch_gather<Tacc>(g, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride,
+                                     ps.nblocks);
         });
       }
       FusedArgs a{};
@@ -1171,6 +728,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
           hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, true, R>), grid, dim3(kFusedThreads), lds, stream, a, rg);
         else
           hipLaunchKernelGGL((fused_pass_kernel<Tin, Tacc, false, R>), grid, dim3(kFusedThreads), lds, stream, a, rg);
+        return hipSuccess;
       });
     }
     default: return hipErrorInvalidValue;
@@ -1193,6 +751,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
                            static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
                            p.dev.adj[l], p.dev.merge[l], nt, src.stride, src.bstride, dst.stride,
                            dst.bstride, rg);
+        return hipSuccess;
       });
     }
     case Step::AdjGather: {
@@ -1209,27 +768,9 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       Tacc *dp = static_cast<Tacc *>(dst.ptr);
       const int32_t nt32 = static_cast<int32_t>(nt);
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-        constexpr bool R = decltype(r)::value;
-        const dim3 grid(gx, gy, gz);
-#define FDMT_ADJ(KK, CC) hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, R>), grid, dim3(kGatherThreads), 0, stream, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride, dst.bstride, ps.nrows, rpw, rg)
-        if (cv == 2) {
-          switch (ps.depth) {
-            case 1: FDMT_ADJ(1, 2); break;
-            case 2: FDMT_ADJ(2, 2); break;
-            case 3: FDMT_ADJ(3, 2); break;
-            case 4: FDMT_ADJ(4, 2); break;
-            default: FDMT_ADJ(5, 2); break;
-          }
-        } else {
-          switch (ps.depth) {
-            case 1: FDMT_ADJ(1, 1); break;
-            case 2: FDMT_ADJ(2, 1); break;
-            case 3: FDMT_ADJ(3, 1); break;
-            case 4: FDMT_ADJ(4, 1); break;
-            default: FDMT_ADJ(5, 1); break;
-          }
-        }
-#undef FDMT_ADJ
+        const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw};
+        return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride,
+                                           dst.bstride, ps.nrows);
       });
     }
     case Step::InitAdj:
@@ -1237,6 +778,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
         hipLaunchKernelGGL((init_adjoint_kernel<Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0,
                            stream, static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
                            p.dev.leaf_off, p.dev.leaf_rows, nt, src.stride, src.bstride, dst.bstride, rg);
+        return hipSuccess;
       });
     default: return hipErrorInvalidValue;
   }

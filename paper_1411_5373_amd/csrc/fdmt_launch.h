@@ -1,0 +1,40 @@
+// Host launchers of the register-gather kernels (fdmt_gather.hip,
+// fdmt_adjoint.hip), called by the step glue in fdmt_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fdmt_device.h"
+
+namespace fdmt {
+
+// Geometry of one gather launch: grid, stream, ragged map (used when
+// `ragged`), k or tree depth, runs of 4 samples per lane, rows per workgroup.
+struct GatherLaunch {
+  dim3 grid;
+  hipStream_t stream;
+  RaggedMap rg;
+  bool ragged;
+  int depth, vecs, rows_per_wg;
+};
+
+// Register gather of 2^depth plane-l0 terms per output row.
+template <typename Tacc>
+hipError_t launch_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int2 *terms, int32_t nt,
+                         int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                         int32_t nrows);
+
+// Register gather of 2^depth Option-1 chain terms straight from the input.
+template <typename Tin, typename Tacc>
+hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tacc *dst, const int4 *terms, int32_t nt,
+                               int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
+
+// Adjoint register gather over a depth-first leaf list.
+template <typename Tacc>
+hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int4 *leaves,
+                                 const int32_t *starts, const int32_t *order, int32_t nt, int64_t src_stride,
+                                 int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
+
+} // namespace fdmt
