@@ -31,8 +31,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
+# Files whose change invalidates the committed counter traffic: kernels,
+# schedule builder and the tuned schedule choice.
 KERNEL_SOURCES = ("paper_1411_5373_amd/csrc/fdmt_kernels.hip",
-                  "paper_1411_5373_amd/csrc/fdmt_schedule.cpp")
+                  "paper_1411_5373_amd/csrc/fdmt_gather.hip",
+                  "paper_1411_5373_amd/csrc/fdmt_adjoint.hip",
+                  "paper_1411_5373_amd/csrc/fdmt_device.h",
+                  "paper_1411_5373_amd/csrc/fdmt_schedule.cpp",
+                  "paper_1411_5373_amd/tuning/gfx950.json")
 
 
 def source_hash():

@@ -144,8 +144,12 @@ fdmt_status_t fdmt_adjoint(fdmt_plan_t p, const void *grad_out, void *grad_in, i
  * exactly one fdmt_forward() (adjoint = 0) or fdmt_adjoint() (adjoint = 1)
  * call. This exists to time and profile individual kernels. */
 typedef struct {
-  int32_t kind;          /* 0 init, 1 one iteration, 2 fused iterations,
-                            3 transpose of one iteration, 4 transpose of the init */
+  int32_t kind;          /* 0 init, 1 one iteration, 2 iterations merged level by level
+                            in LDS, 3 transpose of one iteration, 4 transpose of the
+                            init, 5 iterations as a gather through the caches, 6 the init
+                            and iterations as a gather from the input, 7 iterations as a
+                            staged gather, 8 transposes of several iterations (and of the
+                            init, in the last pass) as a gather */
   int32_t level_first;   /* first iteration covered (0 = the initialisation) */
   int32_t level_last;    /* last iteration covered */
   int32_t work_items;    /* workgroups per beam */

@@ -364,6 +364,7 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       break;
     case fdmt::Step::Fused: {
       const fdmt::Pass &ps = P.fwd.passes[st.index];
+      info->kind = ps.kind == fdmt::PassKind::Staged ? 7 : !ps.gather ? 2 : ps.from_input ? 6 : 5;
       info->level_first = ps.from_input ? 0 : ps.l0 + 1;
       info->level_last = ps.l1;
       info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
@@ -395,7 +396,7 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       break;
     case fdmt::Step::AdjGather: {
       const fdmt::AdjPass &ps = P.adj.passes[st.index];
-      info->kind = 3;
+      info->kind = 8;
       info->level_first = ps.to_input ? 0 : ps.l_lo + 1;
       info->level_last = ps.l_hi;
       info->work_items = static_cast<int32_t>(((ps.nrows + P.gather_rows - 1) / P.gather_rows) *
