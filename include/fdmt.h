@@ -80,6 +80,11 @@ typedef enum {
                                     and forward/adjoint return FDMT_E_UNSUPPORTED */
 #define FDMT_PLAN_UNFUSED 0x2u   /* run one kernel per iteration (reference schedule,
                                     same results; used to cross-check the fused one) */
+#define FDMT_PLAN_WIDE_PLANES 0x4u /* keep every intermediate plane in the accumulation
+                                      dtype. By default a uint8-input plan stores the
+                                      planes between two cache gathers as uint16 while
+                                      every sum on them is below 2^16 (exact integers,
+                                      same results, half the bytes) */
 
 /* Options of a plan. Zero in any schedule field selects the built-in default;
  * schedule fields change only the kernel schedule, never the results. */
@@ -158,6 +163,8 @@ typedef struct {
   int64_t bytes_written; /* algorithmic bytes per beam: each produced element once */
   int64_t staged_bytes;  /* bytes per beam the step's work items load, overlaps included */
   int64_t adds;          /* additions per beam */
+  int32_t in_elem_bytes; /* bytes per element of what the step reads (input or plane) */
+  int32_t out_elem_bytes;/* bytes per element of what the step writes */
 } fdmt_step_info_t;
 
 /* Number of steps of the forward (adjoint = 0) or adjoint (adjoint = 1)

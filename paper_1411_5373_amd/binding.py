@@ -20,6 +20,7 @@ FDMT_OK, FDMT_E_INVALID, FDMT_E_UNSUPPORTED, FDMT_E_NOMEM, FDMT_E_DEVICE, FDMT_E
 FDMT_F32, FDMT_F16, FDMT_U8, FDMT_I32 = range(4)
 FDMT_PLAN_HOST_ONLY = 0x1
 FDMT_PLAN_UNFUSED = 0x2
+FDMT_PLAN_WIDE_PLANES = 0x4
 
 EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_step_count", "fdmt_step_info", "fdmt_run_step",
@@ -58,7 +59,8 @@ class _StepInfo(ctypes.Structure):
                 ("level_last", ctypes.c_int32), ("work_items", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int64), ("bytes_read", ctypes.c_int64),
                 ("bytes_written", ctypes.c_int64), ("staged_bytes", ctypes.c_int64),
-                ("adds", ctypes.c_int64)]
+                ("adds", ctypes.c_int64), ("in_elem_bytes", ctypes.c_int32),
+                ("out_elem_bytes", ctypes.c_int32)]
 
 
 def library_path():
@@ -261,14 +263,15 @@ class Plan:
     shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
-                 host_only=False, unfused=False, tuned=False, **schedule):
+                 host_only=False, unfused=False, tuned=False, wide_planes=False, **schedule):
         """`schedule`: fdmt_options_t schedule fields (first_kernel, first_levels,
         ...). tuned=True first takes the autotuner's stored options for this
         workload, if any; explicit schedule fields override them."""
         self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
         self.f_min, self.f_max = float(f_min), float(f_max)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
-        flags = (FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0)
+        flags = ((FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0) |
+                 (FDMT_PLAN_WIDE_PLANES if wide_planes else 0))
         self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
         self.tuned = None
         if tuned and not host_only and not unfused:

@@ -204,7 +204,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_vecs must be 1 or 2");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
-  if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED))
+  if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES))
     return fail(FDMT_E_INVALID, "unknown option flag");
   if (!pair_supported(o.in_dtype, o.acc_dtype))
     return fail(FDMT_E_UNSUPPORTED, "unsupported (input, accumulation) dtype pair");
@@ -271,6 +271,22 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     } catch (const std::bad_alloc &) {
       delete h;
       return fail(FDMT_E_NOMEM, "host allocation of the adjoint schedule failed");
+    }
+  }
+  // uint16 planes between two cache gathers of a uint8-input plan: plane l
+  // sums at most 2^l + dt input samples per element (one per channel plus the
+  // chain lengths), so it is exact in 16 bits while 255 * (2^l + rows - 1)
+  // stays below 2^16. A run of such planes starts at the gather from the
+  // input: each narrow plane is made from the input or from a narrow plane.
+  p.narrow.assign(p.fwd.passes.size(), 0);
+  if (o.in_dtype == FDMT_U8 && !(o.flags & FDMT_PLAN_WIDE_PLANES)) {
+    for (size_t i = 0; i + 1 < p.fwd.passes.size(); ++i) {
+      const fdmt::Pass &a = p.fwd.passes[i], &b = p.fwd.passes[i + 1];
+      if (!a.gather || !b.gather || b.from_input) continue;
+      if (!a.from_input && !(i > 0 && p.narrow[i - 1])) continue;
+      int64_t rows = 0;
+      for (int32_t r : p.tab.rows[a.l1]) rows = std::max<int64_t>(rows, r);
+      if (255 * ((int64_t(1) << a.l1) + rows - 1) <= 65535) p.narrow[i] = 1;
     }
   }
   fdmt::plan_steps(p);
@@ -340,6 +356,9 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
   const int64_t in_b = P.in_dtype == FDMT_U8 ? 1 : (P.in_dtype == FDMT_F16 ? 2 : 4);
   *info = fdmt_step_info_t{};
   info->kind = static_cast<int32_t>(st.kind);
+  // unless set below: reads the input (init) or a 4-byte plane, writes 4-byte elements
+  info->in_elem_bytes = st.kind == fdmt::Step::Init ? static_cast<int32_t>(in_b) : 4;
+  info->out_elem_bytes = 4;
   auto init_adds = [&]() {
     int64_t a = 0;
     for (int k = 0; k < T.nf; ++k) a += T.leaf_rows[k] - 1;
@@ -378,9 +397,13 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
                         : ps.kind == fdmt::PassKind::Staged
                             ? static_cast<int64_t>(ps.lds_a + ps.lds_p + ps.lds_b + ps.max_recs) * 4
                             : static_cast<int64_t>(ps.lds_a + ps.lds_b + 2 * fdmt::kLdsSlack) * 4;
-      const int64_t eb = ps.from_input ? in_b : 4;
+      const bool narrow_in = st.index > 0 && P.narrow[st.index - 1];
+      const int64_t eb = ps.from_input ? in_b : narrow_in ? 2 : 4;
+      const int64_t ob = P.narrow[st.index] ? 2 : 4;
+      info->in_elem_bytes = static_cast<int32_t>(eb);
+      info->out_elem_bytes = static_cast<int32_t>(ob);
       info->bytes_read = ps.rows_in * nt * eb;
-      info->bytes_written = ps.rows_out * nt * 4;
+      info->bytes_written = ps.rows_out * nt * ob;
       info->staged_bytes = ps.staged_rows * nt * eb;
       for (int l = ps.l0 + 1; l <= ps.l1; ++l) info->adds += T.total[l] * nt;
       if (ps.from_input) info->adds += init_adds();

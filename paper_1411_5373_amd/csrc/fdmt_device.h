@@ -90,6 +90,10 @@ struct Vec4<float> {
   typedef float type __attribute__((ext_vector_type(4), aligned(4)));
 };
 template <>
+struct Vec4<uint16_t> {
+  typedef uint16_t type __attribute__((ext_vector_type(4), aligned(2)));
+};
+template <>
 struct Vec4<int32_t> {
   typedef int type __attribute__((ext_vector_type(4), aligned(4)));
 };

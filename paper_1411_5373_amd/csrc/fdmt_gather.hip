@@ -24,12 +24,14 @@ namespace {
 // 4 per lane; every term is one unaligned 16-byte load per lane, all issued
 // before any add. Rows run fastest in the workgroup order so neighbouring
 // rows - which share most of their terms - meet in one XCD's L2.
-template <typename Tacc, int K, int CV, bool RAGGED>
+template <typename Tsrc, typename Tacc, typename Tdst, int K, int CV, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
-    const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int2 *__restrict__ terms,
+    const Tsrc *__restrict__ src, Tdst *__restrict__ dst, const int2 *__restrict__ terms,
     int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
     int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
+  typedef typename Vec4<Tsrc>::type S4;
+  typedef typename Vec4<Tdst>::type D4;
   constexpr int N = 1 << K;
   // A workgroup holds rows_per_wg consecutive output rows (the rows share
   // most terms, so repeats hit this CU's L1) over one tile of
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
   if (t >= nt) return;
-  const Tacc *base = src + bs.src_off;
+  const Tsrc *base = src + bs.src_off;
   const int2 *tm = terms + static_cast<int64_t>(r) * N;
   int2 e[N];
   int smax = 0;
@@ -58,23 +60,60 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     smax = e[j].y > smax ? e[j].y : smax;
   }
   V v[N][CV];
-  if (tw >= smax) {  // every term inside the record for the whole wave
+  if (std::is_same<Tsrc, uint16_t>::value && tw >= smax) {
+    // uint16 planes (workspace rows, word-aligned, padded): a term's samples
+    // start 2 bytes off a word exactly when its shift is odd, the same for
+    // every lane, so each lane loads the three aligned words around its run
+    // and shifts them into place. The words end at most 4 bytes past the run,
+    // inside the padded row or the workspace that follows it.
+    uint32_t w[N][CV][3];
+    int mis[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const char *p = reinterpret_cast<const char *>(base + e[j].x * src_stride + (t - e[j].y));
+      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        if (t + 256 * c < nt) {
+          const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 512 * c - mis[j]);
+          w[j][c][0] = q[0];
+          w[j][c][1] = q[1];
+          w[j][c][2] = q[2];
+        } else {
+          w[j][c][0] = w[j][c][1] = w[j][c][2] = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        const uint32_t lo = __builtin_amdgcn_alignbyte(w[j][c][1], w[j][c][0], mis[j]);
+        const uint32_t hi = __builtin_amdgcn_alignbyte(w[j][c][2], w[j][c][1], mis[j]);
+        v[j][c][0] = static_cast<Tacc>(lo & 0xffffu);
+        v[j][c][1] = static_cast<Tacc>(lo >> 16);
+        v[j][c][2] = static_cast<Tacc>(hi & 0xffffu);
+        v[j][c][3] = static_cast<Tacc>(hi >> 16);
+      }
+  } else if (tw >= smax) {  // every term inside the record for the whole wave
 #pragma unroll
     for (int j = 0; j < N; ++j)
 #pragma unroll
       for (int c = 0; c < CV; ++c)
         v[j][c] = t + 256 * c < nt
-                      ? *reinterpret_cast<const V *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y))
+                      ? __builtin_convertvector(
+                            *reinterpret_cast<const S4 *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y)), V)
                       : V(0);
   } else {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Tacc *row = base + e[j].x * src_stride;
+      const Tsrc *row = base + e[j].x * src_stride;
 #pragma unroll
       for (int c = 0; c < CV; ++c) {
         const int ts = t + 256 * c - e[j].y;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i >= 0 && t + 256 * c < nt ? row[ts + i] : Tacc(0);
+        for (int i = 0; i < 4; ++i)
+          v[j][c][i] = ts + i >= 0 && t + 256 * c < nt ? static_cast<Tacc>(row[ts + i]) : Tacc(0);
       }
     }
   }
@@ -87,11 +126,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
 #pragma unroll
   for (int c = 0; c < CV; ++c) {
     const int tc = t + 256 * c;
-    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    Tdst *o = dst + bs.dst_off + r * bs.dst_stride + tc;
     if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = v[0][c];
+      *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
     } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = static_cast<Tdst>(v[0][c][i]);
     }
   }
 }
@@ -123,12 +162,13 @@ struct In4<uint8_t> {
   typedef uint8_t type __attribute__((ext_vector_type(4), aligned(1)));
 };
 
-template <typename Tin, typename Tacc, int K, int CV, bool RAGGED>
+template <typename Tin, typename Tacc, typename Tdst, int K, int CV, bool RAGGED>
 __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
-    const Tin *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ terms,
+    const Tin *__restrict__ src, Tdst *__restrict__ dst, const int4 *__restrict__ terms,
     int32_t nt_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
     int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
+  typedef typename Vec4<Tdst>::type D4;
   typedef typename In4<Tin>::type I4;
   constexpr int N = 1 << K;
   const int waves = kGatherThreads / 64;
@@ -237,24 +277,25 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
 #pragma unroll
   for (int c = 0; c < CV; ++c) {
     const int tc = t + 256 * c;
-    Tacc *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+    Tdst *o = dst + bs.dst_off + r * bs.dst_stride + tc;
     if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = v[0][c];
+      *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
     } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = v[0][c][i];
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = static_cast<Tdst>(v[0][c][i]);
     }
   }
 }
 
 } // namespace
 
-template <typename Tacc>
-hipError_t launch_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int2 *terms, int32_t nt,
+template <typename Tsrc, typename Tacc, typename Tdst>
+hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, const int2 *terms, int32_t nt,
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
-#define FDMT_GATHER(KK, CC, RR)                                                                             \
-  hipLaunchKernelGGL((gather_pass_kernel<Tacc, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, g.stream, src, dst, \
-                     terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, g.rows_per_wg, g.rg)
+#define FDMT_GATHER(KK, CC, RR)                                                                         \
+  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, \
+                     g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, \
+                     g.rows_per_wg, g.rg)
 #define FDMT_GATHER_K(CC, RR)             \
   switch (g.depth) {                      \
     case 1: FDMT_GATHER(1, CC, RR); break; \
@@ -273,12 +314,13 @@ hipError_t launch_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, cons
   return hipGetLastError();
 }
 
-template <typename Tin, typename Tacc>
-hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tacc *dst, const int4 *terms, int32_t nt,
+template <typename Tin, typename Tacc, typename Tdst>
+hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows) {
-#define FDMT_IGATHER(KK, CC, RR)                                                                   \
-  hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, g.stream, \
-                     src, dst, terms, nt, src_bstride, dst_stride, dst_bstride, nrows, g.rows_per_wg, g.rg)
+#define FDMT_IGATHER(KK, CC, RR)                                                                          \
+  hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, \
+                     g.stream, src, dst, terms, nt, src_bstride, dst_stride, dst_bstride, nrows,          \
+                     g.rows_per_wg, g.rg)
 #define FDMT_IGATHER_K(CC, RR)             \
   switch (g.depth) {                       \
     case 1: FDMT_IGATHER(1, CC, RR); break; \
@@ -297,18 +339,24 @@ hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tacc *dst,
   return hipGetLastError();
 }
 
-template hipError_t launch_gather<float>(const GatherLaunch &, const float *, float *, const int2 *, int32_t,
-                                         int64_t, int64_t, int64_t, int64_t, int32_t);
-template hipError_t launch_gather<int32_t>(const GatherLaunch &, const int32_t *, int32_t *, const int2 *,
-                                           int32_t, int64_t, int64_t, int64_t, int64_t, int32_t);
-#define FDMT_IG_INST(TI, TA)                                                                                  \
-  template hipError_t launch_input_gather<TI, TA>(const GatherLaunch &, const TI *, TA *, const int4 *, int32_t, \
-                                                  int64_t, int64_t, int64_t, int32_t);
-FDMT_IG_INST(float, float)
-FDMT_IG_INST(_Float16, float)
-FDMT_IG_INST(uint8_t, float)
-FDMT_IG_INST(uint8_t, int32_t)
-FDMT_IG_INST(int32_t, int32_t)
+#define FDMT_G_INST(TS, TA, TD)                                                                             \
+  template hipError_t launch_gather<TS, TA, TD>(const GatherLaunch &, const TS *, TD *, const int2 *, int32_t, \
+                                                int64_t, int64_t, int64_t, int64_t, int32_t);
+FDMT_G_INST(float, float, float)
+FDMT_G_INST(int32_t, int32_t, int32_t)
+FDMT_G_INST(uint16_t, int32_t, uint16_t)
+FDMT_G_INST(uint16_t, int32_t, float)
+FDMT_G_INST(uint16_t, int32_t, int32_t)
+#undef FDMT_G_INST
+#define FDMT_IG_INST(TI, TA, TD)                                                                           \
+  template hipError_t launch_input_gather<TI, TA, TD>(const GatherLaunch &, const TI *, TD *, const int4 *, \
+                                                      int32_t, int64_t, int64_t, int64_t, int32_t);
+FDMT_IG_INST(float, float, float)
+FDMT_IG_INST(_Float16, float, float)
+FDMT_IG_INST(uint8_t, float, float)
+FDMT_IG_INST(uint8_t, int32_t, int32_t)
+FDMT_IG_INST(int32_t, int32_t, int32_t)
+FDMT_IG_INST(uint8_t, int32_t, uint16_t)
 #undef FDMT_IG_INST
 
 } // namespace fdmt

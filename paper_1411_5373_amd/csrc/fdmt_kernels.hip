@@ -680,11 +680,17 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int4 *tm = p.dev_iterms + ps.term_offset;
         const Tin *sp = static_cast<const Tin *>(src.ptr);
-        Tacc *dp = static_cast<Tacc *>(dst.ptr);
+        const bool narrow_out = p.narrow[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
-          return launch_input_gather<Tin, Tacc>(g, sp, dp, tm, nt32, src.bstride, dst.stride, dst.bstride,
-                                                ps.nblocks);
+          if constexpr (std::is_same<Tin, uint8_t>::value) {
+            if (narrow_out)  // exact integer sums below 2^16
+              return launch_input_gather<uint8_t, int32_t, uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm,
+                                                                     nt32, src.bstride, dst.stride, dst.bstride,
+                                                                     ps.nblocks);
+          }
+          return launch_input_gather<Tin, Tacc, Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.bstride,
+                                                      dst.stride, dst.bstride, ps.nblocks);
         });
       }
       if (ps.gather) {
@@ -696,12 +702,23 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int2 *tm = p.dev_terms + ps.term_offset;
-        const Tacc *sp = static_cast<const Tacc *>(src.ptr);
-        Tacc *dp = static_cast<Tacc *>(dst.ptr);
+        const bool narrow_in = st.index > 0 && p.narrow[st.index - 1];
+        const bool narrow_out = p.narrow[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
-          return launch_gather<Tacc>(g, sp, dp, tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride,
-                                     ps.nblocks);
+          if (narrow_in) {  // uint16 plane in: exact integer sums
+            const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
+            if (narrow_out)
+              return launch_gather<uint16_t, int32_t, uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
+                                                                src.stride, src.bstride, dst.stride, dst.bstride,
+                                                                ps.nblocks);
+            return launch_gather<uint16_t, int32_t, Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.stride,
+                                                          src.bstride, dst.stride, dst.bstride, ps.nblocks);
+          }
+          if (narrow_out) return hipErrorInvalidValue;  // narrow planes are made from narrow planes
+          return launch_gather<Tacc, Tacc, Tacc>(g, static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
+                                                 tm, nt32, src.stride, src.bstride, dst.stride, dst.bstride,
+                                                 ps.nblocks);
         });
       }
       FusedArgs a{};

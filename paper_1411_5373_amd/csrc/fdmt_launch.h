@@ -20,15 +20,16 @@ struct GatherLaunch {
   int depth, vecs, rows_per_wg;
 };
 
-// Register gather of 2^depth plane-l0 terms per output row.
-template <typename Tacc>
-hipError_t launch_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int2 *terms, int32_t nt,
+// Register gather of 2^depth plane-l0 terms per output row: loads Tsrc,
+// adds in Tacc, stores Tdst (uint16 planes hold exact integer sums).
+template <typename Tsrc, typename Tacc, typename Tdst>
+hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, const int2 *terms, int32_t nt,
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows);
 
 // Register gather of 2^depth Option-1 chain terms straight from the input.
-template <typename Tin, typename Tacc>
-hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tacc *dst, const int4 *terms, int32_t nt,
+template <typename Tin, typename Tacc, typename Tdst>
+hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
 
 // Adjoint register gather over a depth-first leaf list.

@@ -62,6 +62,7 @@ struct Plan {
   int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1 or 2)
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
+  std::vector<uint8_t> narrow; // per forward pass: its output plane holds uint16 sums
   std::vector<Step> fwd_steps, adj_steps;
   int64_t ws_rows = 0;         // rows of each workspace plane
 };

@@ -195,3 +195,38 @@ def test_nt_limit_follows_the_smallest_time_tile():
     with pytest.raises(F.FDMTError) as e:
         B.fdmt_plan(64, 1000, 64, 1.2, 1.6, flags=B.FDMT_PLAN_HOST_ONLY, gather_vecs=3)
     assert e.value.status == B.FDMT_E_INVALID
+
+
+def test_uint8_plans_store_exact_uint16_planes():
+    """Planes between two cache gathers of a uint8-input plan are uint16 while
+    255 * (2^l + rows - 1) < 2^16 (plane l sums at most 2^l + dt samples)."""
+    import torch
+    from oracle import build_tables
+    kw = dict(first_kernel=3, first_levels=3, later_levels=3)
+    p = F.Plan(4096, 65536, 2048, 1.2, 1.6, host_only=True, in_dtype=torch.uint8, **kw)
+    steps = p.steps()
+    assert [(s["in_elem_bytes"], s["out_elem_bytes"]) for s in steps] == [(1, 2), (2, 2), (2, 4), (4, 4)]
+    tab = build_tables(4096, 2048, 1.2, 1.6)
+    for s in steps[:-1]:
+        l = s["level_last"]
+        fits = 255 * (2 ** l + max(tab.rows[l]) - 1) < 2 ** 16
+        assert (s["out_elem_bytes"] == 2) == fits
+    wide = F.Plan(4096, 65536, 2048, 1.2, 1.6, host_only=True, in_dtype=torch.uint8, wide_planes=True, **kw)
+    assert all(s["out_elem_bytes"] == 4 for s in wide.steps())
+    f32 = F.Plan(4096, 65536, 2048, 1.2, 1.6, host_only=True, in_dtype=torch.float32, **kw)
+    assert all(s["out_elem_bytes"] == 4 for s in f32.steps())
+
+
+def test_uint16_planes_start_at_the_input_gather():
+    """With a level-by-level first pass no plane is narrowed: a narrow plane is
+    always made from the input or from another narrow plane."""
+    import torch
+    p = F.Plan(512, 2048, 96, 0.4, 0.8, host_only=True, in_dtype=torch.uint8, acc_dtype=torch.int32,
+               first_kernel=2, later_kernel=3)
+    assert all(s["out_elem_bytes"] == 4 for s in p.steps())
+    q = F.Plan(512, 2048, 96, 0.4, 0.8, host_only=True, in_dtype=torch.uint8, acc_dtype=torch.int32,
+               first_kernel=3, first_levels=2, later_levels=2)
+    outs = [s["out_elem_bytes"] for s in q.steps()]
+    ins = [s["in_elem_bytes"] for s in q.steps()]
+    assert outs[0] == 2 and ins[1:] == outs[:-1]
+    assert outs == sorted(outs)  # narrow planes form one run from the input

@@ -336,3 +336,26 @@ def test_adjoint_schedules_bit_identical(sched, nf, nt, nd, band):
     pi = F.Plan(nf, nt, nd, *band, in_dtype=torch.int32, acc_dtype=torch.int32, **sched)
     got = pi.adjoint(gi).cpu().numpy().astype(np.int64)
     np.testing.assert_array_equal(got, oadj(gi.cpu().numpy().astype(np.int64), *band, nf))
+
+
+@pytest.mark.parametrize("sched", [dict(first_kernel=3, first_levels=3, later_levels=3),
+                                   dict(first_kernel=3, first_levels=2, later_levels=2, gather_vecs=2),
+                                   dict(first_kernel=3, first_levels=1, later_levels=1, gather_rows=16)])
+@pytest.mark.parametrize("nf,nt,nd,band", [(4096, 3000, 2048, (1.2, 1.6)), (1024, 2000, 1024, (0.4, 0.8)),
+                                           (256, 3001, 300, (1.2, 1.6)), (64, 1030, 100, (1.2, 1.6))])
+def test_uint16_planes_exact(sched, nf, nt, nd, band):
+    """uint8 input through uint16 intermediate planes: bit-identical to the
+    same schedule with full-width planes, and to the int64 oracle. The input
+    is all 255 in places, so the planes reach their largest sums."""
+    print(f"uint16 planes {sched} nf={nf} nt={nt} nd={nd}", flush=True)
+    x = W.random_input((nf, nt), np.uint8, nf + nt)
+    x[:, nt // 3: nt // 3 + 600] = 255
+    xd = _dev(x)
+    ref = ofdmt(x, *band, nd)
+    for acc in (torch.int32, torch.float32):
+        narrow = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=acc, **sched)
+        assert any(s["out_elem_bytes"] == 2 for s in narrow.steps()) or nf <= 64
+        wide = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=acc, wide_planes=True, **sched)
+        y = narrow.forward(xd)
+        assert torch.equal(y, wide.forward(xd))
+        np.testing.assert_array_equal(y.cpu().numpy().astype(np.int64), ref)
