@@ -108,7 +108,8 @@ typedef struct {
   int32_t adjoint_levels; /* iterations per adjoint pass, 1..5 (0 = default 2) */
   int32_t adjoint_last_levels; /* iterations folded into the last adjoint pass with the
                                   transposed initialisation, 1..4 (0 = default 2) */
-  int32_t gather_vecs;    /* runs of 4 samples per lane in cache gathers: 1 or 2 (0 = default 1) */
+  int32_t gather_vecs;    /* runs of 4 samples per lane in cache gathers: 1, 2 or 4; the
+                             forward gathers take at most 2 (0 = default 1) */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

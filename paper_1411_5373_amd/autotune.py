@@ -57,7 +57,7 @@ def adjoint_candidates():
 
 
 GATHER_ROWS = (4, 8)
-GATHER_VECS = (1, 2)
+GATHER_VECS = (1, 2, 4)
 
 
 def arch():

@@ -128,9 +128,9 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
     default: return hipErrorInvalidValue; \
   }
   if (g.ragged) {
-    if (g.vecs == 2) { FDMT_ADJ_K(2, true) } else { FDMT_ADJ_K(1, true) }
+    if (g.vecs == 4) { FDMT_ADJ_K(4, true) } else if (g.vecs == 2) { FDMT_ADJ_K(2, true) } else { FDMT_ADJ_K(1, true) }
   } else {
-    if (g.vecs == 2) { FDMT_ADJ_K(2, false) } else { FDMT_ADJ_K(1, false) }
+    if (g.vecs == 4) { FDMT_ADJ_K(4, false) } else if (g.vecs == 2) { FDMT_ADJ_K(2, false) } else { FDMT_ADJ_K(1, false) }
   }
 #undef FDMT_ADJ_K
 #undef FDMT_ADJ

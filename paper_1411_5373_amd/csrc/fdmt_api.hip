@@ -200,8 +200,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_rows must be 1, 2, 4, 8 or 16");
   if (o.adjoint_levels < 0 || o.adjoint_levels > 5 || o.adjoint_last_levels < 0 || o.adjoint_last_levels > 4)
     return fail(FDMT_E_INVALID, "adjoint_levels must be in [1, 5], adjoint_last_levels in [1, 4]");
-  if (o.gather_vecs < 0 || o.gather_vecs > 2)
-    return fail(FDMT_E_INVALID, "gather_vecs must be 1 or 2");
+  if (o.gather_vecs < 0 || o.gather_vecs > 4 || o.gather_vecs == 3)
+    return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES))
@@ -386,8 +386,9 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->kind = ps.kind == fdmt::PassKind::Staged ? 7 : !ps.gather ? 2 : ps.from_input ? 6 : 5;
       info->level_first = ps.from_input ? 0 : ps.l0 + 1;
       info->level_last = ps.l1;
+      const int fv = P.gather_vecs < 2 ? P.gather_vecs : 2;  // forward gathers take at most 2 runs
       info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
-                                                          ((nt + 4096 * P.gather_vecs / P.gather_rows - 1) / (4096 * P.gather_vecs / P.gather_rows)))
+                                                          ((nt + 4096 * fv / P.gather_rows - 1) / (4096 * fv / P.gather_rows)))
                                    : static_cast<int32_t>(
                                          ps.nblocks *
                                          ((nt + ps.tile - 1) / ps.tile +

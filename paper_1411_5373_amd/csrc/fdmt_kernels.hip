@@ -565,6 +565,10 @@ int64_t buf_rows(const Plan &p, Buf b, bool adjoint) {
 
 constexpr int64_t kMaxGridY = 65535;
 
+// Runs of 4 samples per lane in the forward gathers: at most 2 (their 2^k
+// terms per run live in registers); the adjoint gather takes the plan's value.
+inline int forward_vecs(const Plan &p) { return p.gather_vecs < 2 ? p.gather_vecs : 2; }
+
 // Issues the launches of one step over time tiles of width `tile`. A uniform
 // batch is one launch: ceil(nt / tile) tiles in grid y, beams in grid z. A
 // ragged batch walks the flattened tile map of that width, at most 65535
@@ -674,7 +678,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;
-        const int cv = p.gather_vecs;
+        const int cv = forward_vecs(p);
         const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
@@ -697,7 +701,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
-        const int cv = p.gather_vecs;   // runs of 4 samples per lane: 1 or 2
+        const int cv = forward_vecs(p);  // runs of 4 samples per lane: 1 or 2
         const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
@@ -957,13 +961,14 @@ hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch,
 
 int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
-  const int gather_tile = 256 * p.gather_vecs * (kGatherThreads / 64 / p.gather_rows);
+  const int gather_tile = 256 * forward_vecs(p) * (kGatherThreads / 64 / p.gather_rows);
+  const int adjoint_tile = 256 * p.gather_vecs * (kGatherThreads / 64 / p.gather_rows);
   switch (st.kind) {
     case Step::Init:
     case Step::Merge:
     case Step::MergeAdj:
     case Step::InitAdj: return kTile;
-    case Step::AdjGather: return gather_tile;
+    case Step::AdjGather: return adjoint_tile;
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;

@@ -280,6 +280,7 @@ SCHEDULES = [
     dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=2),
     dict(first_levels=4, later_levels=2, gather_rows=16, gather_vecs=2, adjoint_levels=3,
          adjoint_last_levels=1),
+    dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=4),
 ]
 
 
@@ -313,6 +314,8 @@ ADJOINT_SCHEDULES = [
     dict(adjoint_levels=5, adjoint_last_levels=4),
     dict(adjoint_levels=2, adjoint_last_levels=2, gather_vecs=2),
     dict(adjoint_levels=3, adjoint_last_levels=1, gather_rows=2, gather_vecs=2),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=4),
+    dict(adjoint_levels=4, adjoint_last_levels=1, gather_rows=16, gather_vecs=4),
 ]
 
 

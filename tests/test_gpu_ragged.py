@@ -112,10 +112,11 @@ def test_ragged_adjoint_bitwise(nf, nd, band, unfused):
 
 @pytest.mark.parametrize("sched", [dict(first_kernel=3), dict(first_kernel=2, later_kernel=2, stream_tiles=3),
                                    dict(first_levels=2, first_kernel=3, later_levels=4, gather_rows=2),
-                                   dict(first_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4)])
+                                   dict(first_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4),
+                                   dict(first_levels=3, first_kernel=3, gather_vecs=4, gather_rows=8)])
 @pytest.mark.parametrize("nf,nd,band", [(256, 128, (1.2, 1.6)), (8, 300, (0.4, 0.8))])
 def test_ragged_other_kernel_forms(sched, nf, nd, band):
-    """Other pass kernels: ragged output bit-identical to the oracle per beam."""
+    """Other pass kernels: ragged forward and adjoint bit-identical to the oracle per beam."""
     print(f"ragged {sched} nf={nf} nd={nd}", flush=True)
     xs = _beam_inputs(nf, LENGTHS, np.float32, 3 * nf + nd)
     p = F.Plan(nf, 4096, nd, *band, **sched)
@@ -129,6 +130,11 @@ def test_ragged_other_kernel_forms(sched, nf, nd, band):
     for x, yb, n in zip(xu, yu, LENGTHS):
         if n:
             np.testing.assert_array_equal(yb.astype(np.int64), ofdmt(x, *band, nd))
+    gs = _beam_inputs(nd, LENGTHS, np.float32, 9 * nf + nd)
+    xb = _unpack(F.RaggedPlan(p, LENGTHS).adjoint(_pack(gs, np.float32)).cpu().numpy(), nf, LENGTHS)
+    for g, xbb, n in zip(gs, xb, LENGTHS):
+        if n:
+            np.testing.assert_array_equal(xbb, oadj(g, *band, nf, acc=np.float32))
 
 
 def test_ragged_all_empty_and_single_beam():
