@@ -9,8 +9,10 @@ Inputs are synthetic and resident in HBM before timing starts.
 
 Prints one JSON line. `value` is DM-trial x samples per second of the whole
 step (Nd * Nt / step time); forward-only and adjoint-only rates, achieved HBM
-bandwidth, the adjoint/forward time ratio and the other precision forms are
-reported beside it. `roofline` describes the step's longest kernel: its
+bandwidth, the adjoint/forward time ratio and the other precision forms (with
+their speedup over the FP32 form and the accuracy against the oracle recorded
+in profiles/precision_c3.txt) are reported beside it, and so are the ragged
+256-beam workload and the batch-16 differentiable workload. `roofline` describes the step's longest kernel: its
 algorithmic bytes (every element it must read and write, once) over its
 average duration measured with HIP events on the launch stream.
 `cpu_baseline` times the CPU oracle (NumPy, one core) on a bounded slice of
@@ -125,6 +127,54 @@ def cpu_baseline(nt_sample, min_seconds=10.0, max_reps=4):
                       f"NumPy, single thread"}
 
 
+PRECISION_FILE = os.path.join(ROOT, "profiles", "precision_c3.txt")
+
+
+def read_precision():
+    """Per-form accuracy measured against the oracle (tests/precision_report.py):
+    {form: {"exact": bool, "rms_rel_err": x, "max_err_rel_rms": y}}. Accuracy
+    does not depend on the schedule (every schedule adds the same tree)."""
+    out = {}
+    if not os.path.exists(PRECISION_FILE):
+        return out
+    for line in open(PRECISION_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        out[f[0]] = {"exact": f[3] == "1", "rms_rel_err": float(f[4]), "max_err_rel_rms": float(f[5])}
+    return out
+
+
+def differentiable_c5(F, torch, W, reps=3):
+    """The differentiable form: batch 16, Nf=1024, 0.4-0.8 GHz, Nt=16384,
+    Nd=1024, FP32; loss = logsumexp over each beam's DM-time plane, backward
+    through the hand-written adjoint (torch.autograd)."""
+    w = W.WORKLOADS["c5"]
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, tuned=True)
+    x = W.torch_noise((w.batch, w.nf, w.nt), W.SEED_BASE + 50, "cuda").requires_grad_(True)
+
+    def step():
+        x.grad = None
+        y = F.fdmt(x, plan)
+        loss = torch.logsumexp(y.reshape(w.batch, -1), dim=1).sum()
+        loss.backward()
+
+    step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"workload": f"batch {w.batch}, Nf={w.nf} 0.4-0.8 GHz, Nt={w.nt}, Nd={w.nd}, FP32; "
+                        "loss = logsumexp per beam; forward + autograd backward (hand-written adjoint)",
+            "ms_per_step": round(ms, 4),
+            "dm_trial_samples_per_s": w.batch * w.nd * w.nt / (ms / 1000.0),
+            "schedule": plan.options}
+
+
 def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, tuned=True)
     gen = torch.Generator(device="cuda").manual_seed(11)
@@ -207,7 +257,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="samples of the workload the CPU oracle baseline processes (0: skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
-    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch workload")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the ragged-batch and differentiable workloads")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -286,17 +337,27 @@ def main():
                      "traffic": traffic},
     }
     if not args.no_forms:
-        out["precision_forms"] = {
+        forms = {
             "u8_in_f32_acc": forward_only(F, torch, w, torch.uint8, torch.float32),
             "f16_in_f32_acc": forward_only(F, torch, w, torch.float16, torch.float32),
             "f32_in_f32_acc": forward_only(F, torch, w, torch.float32, torch.float32),
             "u8_in_i32_acc": forward_only(F, torch, w, torch.uint8, torch.int32),
             "i32_in_i32_acc": forward_only(F, torch, w, torch.int32, torch.int32),
         }
+        acc = read_precision()
+        for name, form in forms.items():
+            form["speedup_vs_f32"] = round(forms["f32_in_f32_acc"]["ms"] / form["ms"], 3)
+            if name in acc:
+                form["accuracy_vs_oracle"] = acc[name]
+        out["precision_forms"] = forms
+        if "adjoint_f32" in acc:
+            out["adjoint"]["accuracy_vs_oracle"] = acc["adjoint_f32"]
     del x, g, y, xb, ws, plan
     if not args.no_ragged:
         torch.cuda.empty_cache()
         out["ragged"] = ragged_c4(F, torch, W)
+        torch.cuda.empty_cache()
+        out["differentiable"] = differentiable_c5(F, torch, W)
         torch.cuda.empty_cache()
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
