@@ -156,8 +156,11 @@ def differentiable_c5(F, torch, W, reps=3):
     def step():
         x.grad = None
         y = F.fdmt(x, plan)
-        loss = torch.logsumexp(y.reshape(w.batch, -1), dim=1).sum()
-        loss.backward()
+        # logsumexp over each beam's Nd*Nt plane, in two stages (over time,
+        # then over delay) so torch spreads the reduction over the GPU; the
+        # value is the same up to rounding
+        lse = torch.logsumexp(torch.logsumexp(y.reshape(w.batch, w.nd, -1), dim=2), dim=1)
+        lse.sum().backward()
 
     step()
     torch.cuda.synchronize()
