@@ -1,0 +1,37 @@
+"""The schedule autotuner on the GPU: it times the candidates, stores the
+fastest, and a plan built from the stored options computes the same bits as
+the per-iteration reference schedule."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1411_5373_amd as F  # noqa: E402
+from paper_1411_5373_amd import autotune as A  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("in_dtype", [torch.uint8, torch.float32])
+def test_tuned_schedule_round_trip(tmp_path, monkeypatch, in_dtype):
+    monkeypatch.setenv("FDMT_TUNE_CACHE", str(tmp_path / "cache.json"))
+    args = (256, 3000, 300, 1.2, 1.6, in_dtype, torch.float32)
+    res = A.tune(*args, reps=1)
+    assert res["forward_ms"] > 0 and res["adjoint_ms"] > 0
+    assert len(res["tried"]) >= len(A.forward_candidates())
+    A.store(*args, res)
+    p = F.Plan(256, 2900, 300, 1.2, 1.6, in_dtype=in_dtype, tuned=True)  # same Nt bucket
+    assert p.tuned == res["options"]
+    gen = torch.Generator(DEV).manual_seed(3)
+    if in_dtype == torch.uint8:
+        x = torch.randint(0, 256, (256, 2900), device=DEV, dtype=torch.uint8, generator=gen)
+    else:
+        x = torch.randn(256, 2900, device=DEV, generator=gen)
+    ref = F.Plan(256, 2900, 300, 1.2, 1.6, in_dtype=in_dtype, unfused=True)
+    assert torch.equal(p.forward(x), ref.forward(x))
+    g = torch.randn(300, 2900, device=DEV, generator=gen)
+    pa = F.Plan(256, 2900, 300, 1.2, 1.6, tuned=False, **{k: v for k, v in res["options"].items()})
+    assert torch.equal(pa.adjoint(g), F.Plan(256, 2900, 300, 1.2, 1.6, unfused=True).adjoint(g))
