@@ -110,6 +110,10 @@ typedef struct {
                                   transposed initialisation, 1..4 (0 = default 2) */
   int32_t gather_vecs;    /* runs of 4 samples per lane in cache gathers: 1, 2 or 4; the
                              forward gathers take at most 2 (0 = default 1) */
+  int32_t adjoint_last_rows; /* output rows (channels) per workgroup of the last adjoint
+                                pass: 1, 2, 4, 8 or 16 (0 = gather_rows). Channels of one
+                                sub-band read the same rows, so a workgroup of one whole
+                                sub-band reads them through one L1 */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

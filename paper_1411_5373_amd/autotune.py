@@ -33,10 +33,14 @@ _NAMES = {v: k for k, v in DTYPES.items()}
 
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 
+GATHER_ROWS = (4, 8)
+GATHER_VECS = (1, 2, 4)
+GATHER_ROWS_DEFAULT = 8  # the library's gather_rows when the option is 0
+
 # Fields that shape only the forward or only the adjoint schedule.
 FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
                   "max_block_rows", "stream_tiles")
-ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels")
+ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows")
 SHARED_FIELDS = ("gather_rows", "gather_vecs")
 
 
@@ -52,12 +56,14 @@ def forward_candidates():
     return out
 
 
-def adjoint_candidates():
-    return [dict(adjoint_levels=a, adjoint_last_levels=b) for a in (1, 2, 3) for b in (1, 2, 3)]
+def adjoint_candidates(gather_rows=GATHER_ROWS_DEFAULT):
+    """Adjoint pass depths, and channels per workgroup of the last pass: the
+    shared gather shape, or a larger one (a whole sub-band per workgroup)."""
+    last_rows = [0] + [r for r in (8, 16) if r > gather_rows]
+    return [dict(adjoint_levels=a, adjoint_last_levels=b, adjoint_last_rows=r)
+            for a in (1, 2, 3) for b in (1, 2, 3) for r in last_rows]
 
 
-GATHER_ROWS = (4, 8)
-GATHER_VECS = (1, 2, 4)
 
 
 def arch():
@@ -142,7 +148,7 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
             if fwd_best is None or ms < fwd_best[0]:
                 fwd_best = (ms, cand)
             del p, ws
-        for cand in adjoint_candidates():
+        for cand in adjoint_candidates(rows):
             opts = dict(cand, **shared)
             try:
                 p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, **opts)

@@ -202,6 +202,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "adjoint_levels must be in [1, 5], adjoint_last_levels in [1, 4]");
   if (o.gather_vecs < 0 || o.gather_vecs > 4 || o.gather_vecs == 3)
     return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
+  if (o.adjoint_last_rows < 0 || o.adjoint_last_rows > 16 || (o.adjoint_last_rows & (o.adjoint_last_rows - 1)))
+    return fail(FDMT_E_INVALID, "adjoint_last_rows must be 1, 2, 4, 8 or 16");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES))
@@ -230,6 +232,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (o.stream_tiles) p.tiles_per_wg = p.rec_tiles = o.stream_tiles;
   if (o.gather_rows) p.gather_rows = o.gather_rows;
   if (o.gather_vecs) p.gather_vecs = o.gather_vecs;
+  p.adjoint_last_rows = o.adjoint_last_rows;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
   if (!(o.flags & FDMT_PLAN_UNFUSED)) {
     fdmt::ScheduleParams sp;
@@ -423,8 +426,9 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->kind = 8;
       info->level_first = ps.to_input ? 0 : ps.l_lo + 1;
       info->level_last = ps.l_hi;
-      info->work_items = static_cast<int32_t>(((ps.nrows + P.gather_rows - 1) / P.gather_rows) *
-                                              ((nt + 4096 * P.gather_vecs / P.gather_rows - 1) / (4096 * P.gather_vecs / P.gather_rows)));
+      const int rows = fdmt::adjoint_rows(P, st.index);
+      const int64_t tile = fdmt::step_tile(P, true, step);
+      info->work_items = static_cast<int32_t>(((ps.nrows + rows - 1) / rows) * ((nt + tile - 1) / tile));
       info->bytes_read = T.total[ps.l_hi] * nt * 4;
       info->bytes_written = static_cast<int64_t>(ps.nrows) * nt * 4;
       info->staged_bytes = ps.leaves * nt * 4;

@@ -778,7 +778,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
     case Step::AdjGather: {
       const AdjPass &ps = p.adj.passes[st.index];
       if (ps.depth < 1 || ps.depth > 5) return hipErrorInvalidValue;
-      const int rpw = p.gather_rows;
+      const int rpw = adjoint_rows(p, st.index);
       const int cv = p.gather_vecs;
       const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
       const unsigned gx = static_cast<unsigned>((ps.nrows + rpw - 1) / rpw);
@@ -790,8 +790,8 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       const int32_t nt32 = static_cast<int32_t>(nt);
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw};
-        return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, src.stride, src.bstride, dst.stride,
-                                           dst.bstride, ps.nrows);
+        return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, ps.max_shift, src.stride, src.bstride,
+                                           dst.stride, dst.bstride, ps.nrows);
       });
     }
     case Step::InitAdj:
@@ -959,16 +959,19 @@ hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch,
   return hipSuccess;
 }
 
+int adjoint_rows(const Plan &p, int pass) {
+  return p.adj.passes[pass].to_input && p.adjoint_last_rows ? p.adjoint_last_rows : p.gather_rows;
+}
+
 int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
   const int gather_tile = 256 * forward_vecs(p) * (kGatherThreads / 64 / p.gather_rows);
-  const int adjoint_tile = 256 * p.gather_vecs * (kGatherThreads / 64 / p.gather_rows);
   switch (st.kind) {
     case Step::Init:
     case Step::Merge:
     case Step::MergeAdj:
     case Step::InitAdj: return kTile;
-    case Step::AdjGather: return adjoint_tile;
+    case Step::AdjGather: return 256 * p.gather_vecs * (kGatherThreads / 64 / adjoint_rows(p, st.index));
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;

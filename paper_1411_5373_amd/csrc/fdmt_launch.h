@@ -32,10 +32,12 @@ template <typename Tin, typename Tacc, typename Tdst>
 hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
 
-// Adjoint register gather over a depth-first leaf list.
+// Adjoint register gather over a depth-first leaf list; max_shift bounds the
+// shifts of every leaf.
 template <typename Tacc>
 hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *dst, const int4 *leaves,
-                                 const int32_t *starts, const int32_t *order, int32_t nt, int64_t src_stride,
-                                 int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
+                                 const int32_t *starts, const int32_t *order, int32_t nt, int32_t max_shift,
+                                 int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                                 int32_t nrows);
 
 } // namespace fdmt

@@ -59,7 +59,8 @@ struct Plan {
   int tiles_per_wg = 1;        // time tiles one staged workgroup streams over
   int rec_tiles = 8;           // time tiles one level-by-level (LDS) workgroup runs
   int gather_rows = 8;         // output rows per register-gather workgroup
-  int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1 or 2)
+  int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1, 2 or 4)
+  int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: gather_rows)
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
   std::vector<uint8_t> narrow; // per forward pass: its output plane holds uint16 sums
@@ -96,6 +97,8 @@ hipError_t launch_adjoint(const Plan &p, const void *grad_out, void *grad_in, in
                           hipStream_t stream, const RaggedBatch *rb = nullptr);
 // Time-tile width of a step's launches; 0 when the step has no ragged form.
 int step_tile(const Plan &p, bool adjoint, int step);
+// Output rows per workgroup of adjoint register-gather pass `pass`.
+int adjoint_rows(const Plan &p, int pass);
 size_t workspace_bytes(const Plan &p, int batch);
 // Sets the dynamic-LDS limit of the fused kernels the plan uses.
 hipError_t prepare_kernels(const Plan &p);

@@ -634,6 +634,7 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
       const AdjLeaf &e = s.leaves[x];
       if (e.row < 0 || e.row >= t.total[l_hi] || e.shift < 0 || e.branch < 0 || e.branch >= ps.depth)
         return "adjoint leaf out of range";
+      ps.max_shift = std::max(ps.max_shift, e.shift);
     }
     s.passes.push_back(ps);
     l_hi = ps.l_lo;

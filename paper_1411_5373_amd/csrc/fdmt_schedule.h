@@ -150,6 +150,7 @@ struct AdjPass {
   int64_t start_offset = 0;   // first entry in AdjSchedule::starts (nrows + 1 per pass)
   int64_t order_offset = 0;   // first entry in AdjSchedule::order (nrows per pass)
   int64_t leaves = 0;         // leaves of this pass
+  int32_t max_shift = 0;      // largest leaf shift of this pass
 };
 
 struct AdjSchedule {

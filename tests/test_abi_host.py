@@ -197,6 +197,31 @@ def test_nt_limit_follows_the_smallest_time_tile():
     assert e.value.status == B.FDMT_E_INVALID
 
 
+def test_adjoint_last_rows_shapes_only_the_last_pass():
+    """adjoint_last_rows sets the channels per workgroup of the adjoint pass
+    into the channels alone: its tile, its work items and the Nt limit follow."""
+    nf, nt = 64, 8192
+    base = F.Plan(nf, nt, 64, 1.2, 1.6, host_only=True, gather_rows=4)
+    wide = F.Plan(nf, nt, 64, 1.2, 1.6, host_only=True, gather_rows=4, adjoint_last_rows=16)
+    a, b = base.steps(adjoint=True), wide.steps(adjoint=True)
+    assert [s["kind"] for s in a] == [s["kind"] for s in b]
+    assert a[-1]["kind"] == B.STEP_KINDS[8] and a[-1]["level_first"] == 0
+    for s0, s1 in zip(a[:-1], b[:-1]):
+        assert s0["work_items"] == s1["work_items"]
+    # 4 rows: 1024-sample tiles; 16 rows: 256-sample tiles
+    assert a[-1]["work_items"] == (nf // 4) * (nt // 1024)
+    assert b[-1]["work_items"] == (nf // 16) * (nt // 256)
+    ok = 65535 * 256
+    F.Plan(64, ok + 1, 64, 1.2, 1.6, host_only=True, gather_rows=4)
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(64, ok + 1, 64, 1.2, 1.6, host_only=True, gather_rows=4, adjoint_last_rows=16)
+    assert e.value.status == B.FDMT_E_UNSUPPORTED
+    for bad in (3, 32, -1):
+        with pytest.raises(F.FDMTError) as e:
+            F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, adjoint_last_rows=bad)
+        assert e.value.status == B.FDMT_E_INVALID
+
+
 def test_uint8_plans_store_exact_uint16_planes():
     """Planes between two cache gathers of a uint8-input plan are uint16 while
     255 * (2^l + rows - 1) < 2^16 (plane l sums at most 2^l + dt samples)."""

@@ -35,7 +35,7 @@ def test_candidates_build_host_plans(nf, nd, band):
     (the tuner skips those); the default-built ones cover both directions."""
     built = 0
     for rows in A.GATHER_ROWS:
-        for cand in A.forward_candidates() + A.adjoint_candidates():
+        for cand in A.forward_candidates() + A.adjoint_candidates(rows):
             try:
                 F.Plan(nf, 8192, nd, *band, host_only=True, gather_rows=rows, gather_vecs=A.GATHER_VECS[-1],
                        **cand)

@@ -316,6 +316,9 @@ ADJOINT_SCHEDULES = [
     dict(adjoint_levels=3, adjoint_last_levels=1, gather_rows=2, gather_vecs=2),
     dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=4),
     dict(adjoint_levels=4, adjoint_last_levels=1, gather_rows=16, gather_vecs=4),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=4, gather_vecs=4, adjoint_last_rows=8),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=2, adjoint_last_rows=16),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=8, gather_vecs=4, adjoint_last_rows=1),
 ]
 
 

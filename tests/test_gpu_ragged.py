@@ -113,7 +113,9 @@ def test_ragged_adjoint_bitwise(nf, nd, band, unfused):
 @pytest.mark.parametrize("sched", [dict(first_kernel=3), dict(first_kernel=2, later_kernel=2, stream_tiles=3),
                                    dict(first_levels=2, first_kernel=3, later_levels=4, gather_rows=2),
                                    dict(first_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4),
-                                   dict(first_levels=3, first_kernel=3, gather_vecs=4, gather_rows=8)])
+                                   dict(first_levels=3, first_kernel=3, gather_vecs=4, gather_rows=8),
+                                   dict(gather_vecs=4, gather_rows=4, adjoint_levels=3, adjoint_last_levels=3,
+                                        adjoint_last_rows=16)])
 @pytest.mark.parametrize("nf,nd,band", [(256, 128, (1.2, 1.6)), (8, 300, (0.4, 0.8))])
 def test_ragged_other_kernel_forms(sched, nf, nd, band):
     """Other pass kernels: ragged forward and adjoint bit-identical to the oracle per beam."""
