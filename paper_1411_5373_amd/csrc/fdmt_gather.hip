@@ -240,6 +240,52 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
         v[j][c] = acc;
       }
     }
+  } else if (std::is_same<Tin, _Float16>::value && (reinterpret_cast<uintptr_t>(src) & 3) == 0 &&
+             tw >= reach && tw + 256 * CV + 8 <= nt && longest <= 2) {
+    // Halves: as for bytes, a term's misalignment (0 or 2 bytes) is the same
+    // for every lane. Each lane loads the four aligned words that start at or
+    // just before its earliest chain sample t - shift - chain (never before the
+    // word-aligned buffer, as tw >= reach); they end at most 14 bytes after
+    // it, inside the row as 8 samples follow the wave's last one.
+    uint32_t w[N][CV][4];
+    int mis[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const char *p = reinterpret_cast<const char *>(base + static_cast<int64_t>(e[j].x) * nt +
+                                                     (t - e[j].y - e[j].z));
+      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        typedef uint32_t W4 __attribute__((ext_vector_type(4), aligned(4)));
+        const W4 q = *reinterpret_cast<const W4 *>(p + 512 * c - mis[j]);
+        w[j][c][0] = q[0];
+        w[j][c][1] = q[1];
+        w[j][c][2] = q[2];
+        w[j][c][3] = q[3];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int c = 0; c < CV; ++c) {
+        // chain element i (sample t - shift - i) starts mis + 2 (chain - i) bytes in
+        auto take = [&](int o) {
+          const int k = o >> 2;
+          const uint32_t lo = __builtin_amdgcn_alignbyte(k ? w[j][c][2] : w[j][c][1], k ? w[j][c][1] : w[j][c][0], o & 3);
+          const uint32_t hi = __builtin_amdgcn_alignbyte(k ? w[j][c][3] : w[j][c][2], k ? w[j][c][2] : w[j][c][1], o & 3);
+          V r4;
+          r4[0] = static_cast<Tacc>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(lo & 0xffffu)));
+          r4[1] = static_cast<Tacc>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(lo >> 16)));
+          r4[2] = static_cast<Tacc>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hi & 0xffffu)));
+          r4[3] = static_cast<Tacc>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hi >> 16)));
+          return r4;
+        };
+        const int d = e[j].z;
+        V acc = take(mis[j] + 2 * d);
+        for (int i = 1; i <= d; ++i) acc = acc + take(mis[j] + 2 * (d - i));
+        v[j][c] = acc;
+      }
+    }
   } else if (tw >= reach && tw + 256 * CV <= nt) {  // every access of the wave inside [0, nt)
 #pragma unroll
     for (int j = 0; j < N; ++j) {

@@ -289,7 +289,8 @@ SCHEDULES = [
                                            (64, 50, 100, (1.2, 1.6)), (4096, 3000, 2048, (1.2, 1.6))])
 def test_schedules_bit_identical(sched, nf, nt, nd, band):
     """Any fusion schedule (block splits, tiles, LDS budgets) gives the same bits
-    as the per-iteration kernels, which match the oracle."""
+    as the per-iteration kernels, which match the oracle: FP32 and FP16 input
+    (FP32 sums), and uint8 input with int32 sums."""
     print(f"schedule {sched} nf={nf} nt={nt} nd={nd}", flush=True)
     x = torch.randn(nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(nf + nt))
     ref = F.Plan(nf, nt, nd, *band, unfused=True).forward(x)
@@ -299,6 +300,9 @@ def test_schedules_bit_identical(sched, nf, nt, nd, band):
         assert e.status == 2  # FDMT_E_UNSUPPORTED: this explicit schedule does not fit the shape
         pytest.skip(str(e))
     assert torch.equal(p.forward(x), ref)
+    xh = x.half()
+    refh = F.Plan(nf, nt, nd, *band, in_dtype=torch.float16, unfused=True).forward(xh)
+    assert torch.equal(F.Plan(nf, nt, nd, *band, in_dtype=torch.float16, **sched).forward(xh), refh)
     xi = torch.randint(0, 256, (nf, nt), device=DEV, dtype=torch.uint8,
                        generator=torch.Generator(DEV).manual_seed(nd))
     refi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, unfused=True).forward(xi)
