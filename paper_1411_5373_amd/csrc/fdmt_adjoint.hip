@@ -2,8 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fdmt_launch.h"
+#include "fdmt_schedule.h"
 
 namespace fdmt {
 
@@ -31,11 +33,22 @@ constexpr int kAdjChunk = 8;
 template <typename T>
 using Reg4 = T __attribute__((ext_vector_type(4)));
 
-// Adds one leaf (CV runs of 4 samples) whose path branches off the previous
-// leaf's at depth b.
-template <typename V, int K, int CV>
-__device__ __forceinline__ void add_leaf(V (&acc)[K][CV], const V (&v)[CV], int b, bool first) {
-  if (!first) {
+// Running sums of one output row: one accumulator per tree depth, CV runs of
+// 4 samples per lane.
+template <typename Tacc, int K, int CV>
+struct DepthSums {
+  typedef Reg4<Tacc> R;
+  R acc[K][CV];
+
+  __device__ __forceinline__ DepthSums() {
+#pragma unroll
+    for (int d = 0; d < K; ++d)
+#pragma unroll
+      for (int c = 0; c < CV; ++c) acc[d][c] = R(0);
+  }
+
+  // Finished nodes deeper than b into their parents, deepest first; restart them.
+  __device__ __forceinline__ void flush_below(int b) {
 #pragma unroll
     for (int d = K - 1; d >= 1; --d)
       if (d > b)
@@ -45,61 +58,89 @@ __device__ __forceinline__ void add_leaf(V (&acc)[K][CV], const V (&v)[CV], int 
     for (int d = 1; d < K; ++d)
       if (d > b)
 #pragma unroll
-        for (int c = 0; c < CV; ++c) acc[d][c] = V(0);
+        for (int c = 0; c < CV; ++c) acc[d][c] = R(0);
   }
-#pragma unroll
-  for (int c = 0; c < CV; ++c) acc[K - 1][c] = acc[K - 1][c] + v[c];
-}
 
-// Interior path: t + 256 * CV + max_shift <= nt for the whole wave.
-template <typename Tacc, int K, int CV>
-__device__ __forceinline__ void gather_interior(Reg4<Tacc> (&acc)[K][CV], const Tacc *base,
-                                                int64_t stride, const int4 *__restrict__ leaves, int x_begin,
-                                                int x_end, int t) {
-  typedef typename Vec4<Tacc>::type V;
-  typedef Reg4<Tacc> R;
-  constexpr int kChunk = kAdjChunk / CV;
-  for (int x0 = x_begin; x0 < x_end; x0 += kChunk) {
-    const int n = x_end - x0 < kChunk ? x_end - x0 : kChunk;
-    int br[kChunk];
-    R v[kChunk][CV];
+  // One leaf whose path branches off the previous leaf's at depth b.
+  __device__ __forceinline__ void add(const R (&v)[CV], int b, bool first) {
+    if (!first) flush_below(b);
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (j < n) {
-        const int4 e = leaves[x0 + j];
-        br[j] = e.z;
-        const Tacc *row = base + e.x * stride + t + e.y;
+    for (int c = 0; c < CV; ++c) acc[K - 1][c] = acc[K - 1][c] + v[c];
+  }
+
+  static __device__ __forceinline__ Tacc exchange(int addr, Tacc x) {
+    return __builtin_bit_cast(Tacc, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, x)));
+  }
+
+  // Lagged pass: the subtree of one partial-sum row (depth 1) is complete;
+  // add its values at t + i, i = 0..L-1, to the channel (acc[0]) in lag
+  // order. Sample t + q + i of run c is this lane's component q + i, or for
+  // q + i >= 4 the next lane's component q + i - 4 (lane 63: lane 0's of run
+  // c + 1; lane 63 of the last run is not stored). All 64 lanes take part.
+  template <int L>
+  __device__ __forceinline__ void add_lags(int lane) {
+    const int addr = ((lane + 1) & 63) << 2;
+    Tacc next[L > 1 ? L - 1 : 1];
 #pragma unroll
-        for (int c = 0; c < CV; ++c) v[j][c] = *reinterpret_cast<const V *>(row + 256 * c);
+    for (int k = 0; k < L - 1; ++k) next[k] = exchange(addr, acc[1][0][k]);
+#pragma unroll
+    for (int c = 0; c < CV; ++c) {
+      Tacc nb[L > 1 ? L - 1 : 1];
+#pragma unroll
+      for (int k = 0; k < L - 1; ++k) {
+        nb[k] = next[k];
+        if (c + 1 < CV) {
+          next[k] = exchange(addr, acc[1][c + 1][k]);
+          if (lane == 63) nb[k] = next[k];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        R sh;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh[q] = q + i < 4 ? acc[1][c][q + i] : nb[q + i - 4];
+        acc[0][c] = acc[0][c] + sh;
       }
     }
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j)
-      if (j < n) add_leaf<R, K, CV>(acc, v[j], br[j], x0 + j == x_begin);
   }
-}
 
-// Edge path: every run checked against nt.
-template <typename Tacc, int K, int CV>
-__device__ __forceinline__ void gather_edge(Reg4<Tacc> (&acc)[K][CV], const Tacc *base,
-                                            int64_t stride, const int4 *__restrict__ leaves, int x_begin,
-                                            int x_end, int t, int nt) {
+  __device__ __forceinline__ void finish_subtree(int lags, int lane) {
+    if constexpr (K >= 2) {
+      flush_below(1);
+      switch (lags) {
+        case 1: add_lags<1>(lane); break;
+        case 2: add_lags<2>(lane); break;
+        case 3: add_lags<3>(lane); break;
+        default: add_lags<4>(lane); break;
+      }
+#pragma unroll
+      for (int c = 0; c < CV; ++c) acc[1][c] = R(0);
+    }
+  }
+};
+
+// Adds leaves x0 .. x1-1 (the first one flushes nothing), kChunk at a time.
+// INTERIOR: t + 256 * CV + max_shift <= nt for the whole wave, so no access
+// needs a check; otherwise every run is checked against nt.
+template <bool INTERIOR, typename Tacc, int K, int CV>
+__device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const Tacc *base, int64_t stride,
+                                             const int4 *__restrict__ leaves, int x0, int x1, int t, int nt) {
   typedef typename Vec4<Tacc>::type V;
   typedef Reg4<Tacc> R;
   constexpr int kChunk = kAdjChunk / CV;
-  for (int x0 = x_begin; x0 < x_end; x0 += kChunk) {
-    const int n = x_end - x0 < kChunk ? x_end - x0 : kChunk;
+  for (int x = x0; x < x1; x += kChunk) {
+    const int n = x1 - x < kChunk ? x1 - x : kChunk;
     int4 e[kChunk];
     R v[kChunk][CV];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
       if (j < n) {
-        e[j] = leaves[x0 + j];
+        e[j] = leaves[x + j];
         const Tacc *row = base + e[j].x * stride;
 #pragma unroll
         for (int c = 0; c < CV; ++c) {
           const int ts = t + 256 * c + e[j].y;
-          if (ts + 4 <= nt) {
+          if (INTERIOR || ts + 4 <= nt) {
             v[j][c] = *reinterpret_cast<const V *>(row + ts);
           } else {
 #pragma unroll
@@ -110,18 +151,21 @@ __device__ __forceinline__ void gather_edge(Reg4<Tacc> (&acc)[K][CV], const Tacc
     }
 #pragma unroll
     for (int j = 0; j < kChunk; ++j)
-      if (j < n) add_leaf<R, K, CV>(acc, v[j], e[j].z, x0 + j == x_begin);
+      if (j < n) sums.add(v[j], e[j].z, x + j == x0);
   }
 }
 
-template <typename Tacc, int K, int CV, bool RAGGED>
+// A wave covers 256 * CV consecutive samples (4 per lane, CV runs 256 apart)
+// and stores them all, or in a lagged pass all but the last lane's last run:
+// those 4 samples only feed the lane exchange, and the next wave starts there.
+template <typename Tacc, int K, int CV, bool RAGGED, bool LAG>
 __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
     const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u, int32_t max_shift,
     int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
     int32_t rows_per_wg, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
-  typedef Reg4<Tacc> R;
+  constexpr int kSpan = adjoint_wave_span(CV, LAG);
   const int waves = kGatherThreads / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
@@ -131,33 +175,42 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
   if (r >= nrows) return;
   const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
   const int nt = bs.nt;
-  const int t_wave = (bs.tile * col_waves + wave % col_waves) * 256 * CV;
+  const int t_wave = (bs.tile * col_waves + wave % col_waves) * kSpan;
   const int t = t_wave + lane * 4;
-  if (t >= nt) return;
+  if (LAG ? t_wave >= nt : t >= nt) return;
   const Tacc *base = src + bs.src_off;
   const int x_begin = starts[r], x_end = starts[r + 1];
   const int out_row = order[r];
-  R acc[K][CV];
-#pragma unroll
-  for (int d = 0; d < K; ++d)
-#pragma unroll
-    for (int c = 0; c < CV; ++c) acc[d][c] = R(0);
+  DepthSums<Tacc, K, CV> sums;
+  auto run = [&](auto interior) {
+    constexpr bool kInterior = decltype(interior)::value;
+    if constexpr (LAG) {
+      // one subtree (a partial-sum row) at a time: its first leaf holds
+      // lags | leaves << 3
+      for (int x = x_begin; x < x_end;) {
+        const int w = leaves[x].w;
+        gather_range<kInterior>(sums, base, bs.src_stride, leaves, x, x + (w >> 3), t, nt);
+        sums.finish_subtree(w & 7, lane);
+        x += w >> 3;
+      }
+    } else {
+      gather_range<kInterior>(sums, base, bs.src_stride, leaves, x_begin, x_end, t, nt);
+      sums.flush_below(0);
+    }
+  };
   if (t_wave + 256 * CV + max_shift <= nt)
-    gather_interior<Tacc, K, CV>(acc, base, bs.src_stride, leaves, x_begin, x_end, t);
+    run(std::true_type());
   else
-    gather_edge<Tacc, K, CV>(acc, base, bs.src_stride, leaves, x_begin, x_end, t, nt);
-#pragma unroll
-  for (int d = K - 1; d >= 1; --d)
-#pragma unroll
-    for (int c = 0; c < CV; ++c) acc[d - 1][c] = acc[d - 1][c] + acc[d][c];
+    run(std::false_type());
 #pragma unroll
   for (int c = 0; c < CV; ++c) {
     const int tc = t + 256 * c;
+    if (LAG && c == CV - 1 && lane == 63) continue;
     Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + tc;
     if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = acc[0][c];
+      *reinterpret_cast<V *>(o) = sums.acc[0][c];
     } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = acc[0][c][i];
+      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = sums.acc[0][c][i];
     }
   }
 }
@@ -169,18 +222,28 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
                                  const int32_t *starts, const int32_t *order, int32_t nt, int32_t max_shift,
                                  int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                                  int32_t nrows) {
-#define FDMT_ADJ(KK, CC, RR)                                                                              \
-  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, g.stream, src, \
-                     dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride, dst_bstride, \
-                     nrows, g.rows_per_wg, g.rg)
-#define FDMT_ADJ_K(CC, RR)             \
-  switch (g.depth) {                   \
-    case 1: FDMT_ADJ(1, CC, RR); break; \
-    case 2: FDMT_ADJ(2, CC, RR); break; \
-    case 3: FDMT_ADJ(3, CC, RR); break; \
-    case 4: FDMT_ADJ(4, CC, RR); break; \
-    case 5: FDMT_ADJ(5, CC, RR); break; \
-    default: return hipErrorInvalidValue; \
+#define FDMT_ADJ(KK, CC, RR, LL)                                                                         \
+  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL>), g.grid, dim3(kGatherThreads), 0, g.stream, \
+                     src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,      \
+                     dst_bstride, nrows, g.rows_per_wg, g.rg)
+#define FDMT_ADJ_K(CC, RR)                                    \
+  if (g.lagged) {                                             \
+    switch (g.depth) {                                        \
+      case 2: FDMT_ADJ(2, CC, RR, true); break;               \
+      case 3: FDMT_ADJ(3, CC, RR, true); break;               \
+      case 4: FDMT_ADJ(4, CC, RR, true); break;               \
+      case 5: FDMT_ADJ(5, CC, RR, true); break;               \
+      default: return hipErrorInvalidValue;                   \
+    }                                                         \
+  } else {                                                    \
+    switch (g.depth) {                                        \
+      case 1: FDMT_ADJ(1, CC, RR, false); break;              \
+      case 2: FDMT_ADJ(2, CC, RR, false); break;              \
+      case 3: FDMT_ADJ(3, CC, RR, false); break;              \
+      case 4: FDMT_ADJ(4, CC, RR, false); break;              \
+      case 5: FDMT_ADJ(5, CC, RR, false); break;              \
+      default: return hipErrorInvalidValue;                   \
+    }                                                         \
   }
   if (g.ragged) {
     if (g.vecs == 4) { FDMT_ADJ_K(4, true) } else if (g.vecs == 2) { FDMT_ADJ_K(2, true) } else { FDMT_ADJ_K(1, true) }

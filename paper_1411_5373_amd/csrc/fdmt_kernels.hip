@@ -780,7 +780,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       if (ps.depth < 1 || ps.depth > 5) return hipErrorInvalidValue;
       const int rpw = adjoint_rows(p, st.index);
       const int cv = p.gather_vecs;
-      const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
+      const int tile = adjoint_wave_span(cv, ps.lagged) * (kGatherThreads / 64 / rpw);
       const unsigned gx = static_cast<unsigned>((ps.nrows + rpw - 1) / rpw);
       const int4 *lv = p.dev_adj_leaves + ps.leaf_offset;
       const int32_t *sr = p.dev_adj_starts + ps.start_offset;
@@ -789,7 +789,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       Tacc *dp = static_cast<Tacc *>(dst.ptr);
       const int32_t nt32 = static_cast<int32_t>(nt);
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-        const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw};
+        const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw, ps.lagged};
         return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, ps.max_shift, src.stride, src.bstride,
                                            dst.stride, dst.bstride, ps.nrows);
       });
@@ -971,7 +971,9 @@ int step_tile(const Plan &p, bool adjoint, int i) {
     case Step::Merge:
     case Step::MergeAdj:
     case Step::InitAdj: return kTile;
-    case Step::AdjGather: return 256 * p.gather_vecs * (kGatherThreads / 64 / adjoint_rows(p, st.index));
+    case Step::AdjGather:
+      return adjoint_wave_span(p.gather_vecs, p.adj.passes[st.index].lagged) *
+             (kGatherThreads / 64 / adjoint_rows(p, st.index));
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;

@@ -18,7 +18,13 @@ struct GatherLaunch {
   RaggedMap rg;
   bool ragged;
   int depth, vecs, rows_per_wg;
+  bool lagged = false;  // adjoint: lagged leaf list (subtrees listed once)
 };
+
+// Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,
+// less the last lane's last run in a lagged pass (it only feeds the lane
+// exchange of its neighbour).
+constexpr int adjoint_wave_span(int cv, bool lagged) { return 256 * cv - (lagged ? 4 : 0); }
 
 // Register gather of 2^depth plane-l0 terms per output row: loads Tsrc,
 // adds in Tacc, stores Tdst (uint16 planes hold exact integer sums).

@@ -571,7 +571,8 @@ struct AdjWalker {
 
 } // namespace
 
-std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels) {
+std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels,
+                                   bool lag_reuse) {
   s = AdjSchedule();
   const int L = t.levels;
   if (L == 0) return "";
@@ -579,8 +580,11 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
   // Fold the init transpose into the last pass only while its fan-out (the
   // (d, i) pairs of a channel, quadratic in its partial-sum rows) is small;
   // otherwise the passes stop at plane 0 and the transpose runs on its own.
-  int fan = 0;
-  for (int k = 0; k < t.nf; ++k) fan = std::max(fan, t.leaf_rows[k] * (t.leaf_rows[k] + 1) / 2);
+  int fan = 0, rows_max = 0;
+  for (int k = 0; k < t.nf; ++k) {
+    fan = std::max(fan, t.leaf_rows[k] * (t.leaf_rows[k] + 1) / 2);
+    rows_max = std::max(rows_max, t.leaf_rows[k]);
+  }
   s.init_separate = fan > 16;
   int l_hi = L;
   while (l_hi > 0) {
@@ -592,6 +596,7 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
       ps.to_input = true;
       ps.depth = l_hi + 1;
       ps.nrows = t.nf;
+      ps.lagged = lag_reuse && rows_max > 1 && rows_max <= kMaxLags;
     } else {
       ps.l_lo = std::max(l_hi - levels_per_pass, s.init_separate ? 0 : last_levels);
       ps.depth = l_hi - ps.l_lo;
@@ -606,7 +611,15 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
     std::vector<std::vector<AdjLeaf>> per_row(ps.nrows);
     for (int r = 0; r < ps.nrows; ++r) {
       AdjWalker w{t, l_hi, per_row[r]};
-      if (ps.to_input) {
+      if (ps.lagged) {
+        // channel r: the subtree of each partial-sum row d once, at lag 0,
+        // its first leaf carrying the d + 1 lags it is added at
+        for (int d = 0; d < t.leaf_rows[r]; ++d) {
+          const size_t first = per_row[r].size();
+          w.visit(0, t.leaf_off[r] + d, 0, 1, 0);
+          per_row[r][first].lags = (d + 1) | static_cast<int32_t>(per_row[r].size() - first) << 3;
+        }
+      } else if (ps.to_input) {
         // channel r: partial-sum rows d at lags i, in (d, i) order; each starts
         // a new child of the root (branch depth 0)
         for (int d = 0; d < t.leaf_rows[r]; ++d)
@@ -634,7 +647,25 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
       const AdjLeaf &e = s.leaves[x];
       if (e.row < 0 || e.row >= t.total[l_hi] || e.shift < 0 || e.branch < 0 || e.branch >= ps.depth)
         return "adjoint leaf out of range";
+      if (!ps.lagged && e.lags != 0) return "adjoint leaf lags";
       ps.max_shift = std::max(ps.max_shift, e.shift);
+    }
+    // A lagged pass: each row is a sequence of subtrees, each opened by a leaf
+    // at branch 0 that holds its lags (1..kMaxLags) and leaf count, the other
+    // leaves below the root.
+    if (ps.lagged) {
+      for (int i = 0; i < ps.nrows; ++i) {
+        const int64_t end = ps.leaf_offset + s.starts[ps.start_offset + i + 1];
+        for (int64_t x = ps.leaf_offset + s.starts[ps.start_offset + i]; x < end;) {
+          const AdjLeaf &e = s.leaves[x];
+          const int lags = e.lags & 7, count = e.lags >> 3;
+          if (e.branch != 0 || lags < 1 || lags > kMaxLags || count < 1 || x + count > end)
+            return "adjoint leaf lags";
+          for (int64_t y = x + 1; y < x + count; ++y)
+            if (s.leaves[y].branch == 0 || s.leaves[y].lags != 0) return "adjoint leaf lags";
+          x += count;
+        }
+      }
     }
     s.passes.push_back(ps);
     l_hi = ps.l_lo;

@@ -137,8 +137,16 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
 // adds its partial-sum rows d at lags i = 0..d, in (d, i) order. A leaf is a
 // row of plane l_hi with its accumulated shift and the depth of the deepest
 // tree node it shares with the previous leaf.
+//
+// In a `lagged` pass (into the channels, some channel with two or more
+// partial-sum rows) the subtree of partial-sum row d is listed once, at lag 0,
+// and its first leaf carries lags = d + 1 and its leaf count: the kernel adds
+// the finished subtree to the channel at t, t + 1, ..., t + d, taking the
+// later samples from neighbouring lanes. The value at t + i is the lag-i
+// subtree's, so the sums and their order are those of the full list.
 struct AdjLeaf {
-  int32_t row, shift, branch, pad;
+  int32_t row, shift, branch;
+  int32_t lags;  // lagged pass, a subtree's first leaf: its lags | its leaf count << 3; else 0
 };
 
 struct AdjPass {
@@ -151,6 +159,7 @@ struct AdjPass {
   int64_t order_offset = 0;   // first entry in AdjSchedule::order (nrows per pass)
   int64_t leaves = 0;         // leaves of this pass
   int32_t max_shift = 0;      // largest leaf shift of this pass
+  bool lagged = false;        // subtrees listed once with their lag count (see AdjLeaf)
 };
 
 struct AdjSchedule {
@@ -162,8 +171,15 @@ struct AdjSchedule {
                                 // leaves are neighbours, so they meet in one XCD's L2)
 };
 
+// Largest lag count of a lagged pass: a channel's partial-sum rows are then
+// at most this many.
+constexpr int kMaxLags = 4;
+
 // Passes of at most `levels_per_pass` iterations from the output down to the
-// channels; the last pass includes the init transpose.
-std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels);
+// channels; the last pass includes the init transpose. With `lag_reuse`, a
+// last pass whose channels have several partial-sum rows (at most kMaxLags)
+// is lagged.
+std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_per_pass, int last_levels,
+                                   bool lag_reuse = true);
 
 } // namespace fdmt
