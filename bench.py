@@ -37,6 +37,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
 # schedule builder and the tuned schedule choice.
 KERNEL_SOURCES = ("paper_1411_5373_amd/csrc/fdmt_kernels.hip",
                   "paper_1411_5373_amd/csrc/fdmt_gather.hip",
+                  "paper_1411_5373_amd/csrc/fdmt_narrow.hip",
                   "paper_1411_5373_amd/csrc/fdmt_adjoint.hip",
                   "paper_1411_5373_amd/csrc/fdmt_device.h",
                   "paper_1411_5373_amd/csrc/fdmt_schedule.cpp",

@@ -292,6 +292,18 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
       if (255 * ((int64_t(1) << a.l1) + rows - 1) <= 65535) p.narrow[i] = 1;
     }
   }
+  // Gathers over uint8 input or uint16 planes whose sums stay integers below
+  // 2^24 (every plane-l value is at most 255 * (2^l + rows - 1)) may add in
+  // any order: int32 lanes, wide per-lane loads.
+  p.int_sums.assign(p.fwd.passes.size(), 0);
+  for (size_t i = 0; i < p.fwd.passes.size(); ++i) {
+    const fdmt::Pass &a = p.fwd.passes[i];
+    if (!a.gather) continue;
+    if (!(a.from_input ? o.in_dtype == FDMT_U8 : i > 0 && p.narrow[i - 1])) continue;
+    int64_t rows = 0;
+    for (int32_t r : p.tab.rows[a.l1]) rows = std::max<int64_t>(rows, r);
+    if (o.acc_dtype == FDMT_I32 || 255 * ((int64_t(1) << a.l1) + rows - 1) < (int64_t(1) << 24)) p.int_sums[i] = 1;
+  }
   fdmt::plan_steps(p);
   // Time tiles of uniform batches run along the grid's y dimension (at most
   // 65535 workgroups).

@@ -390,7 +390,6 @@ hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst,
                                                 int64_t, int64_t, int64_t, int64_t, int32_t);
 FDMT_G_INST(float, float, float)
 FDMT_G_INST(int32_t, int32_t, int32_t)
-FDMT_G_INST(uint16_t, int32_t, uint16_t)
 FDMT_G_INST(uint16_t, int32_t, float)
 FDMT_G_INST(uint16_t, int32_t, int32_t)
 #undef FDMT_G_INST
@@ -402,7 +401,6 @@ FDMT_IG_INST(_Float16, float, float)
 FDMT_IG_INST(uint8_t, float, float)
 FDMT_IG_INST(uint8_t, int32_t, int32_t)
 FDMT_IG_INST(int32_t, int32_t, int32_t)
-FDMT_IG_INST(uint8_t, int32_t, uint16_t)
 #undef FDMT_IG_INST
 
 } // namespace fdmt

@@ -685,13 +685,16 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int4 *tm = p.dev_iterms + ps.term_offset;
         const Tin *sp = static_cast<const Tin *>(src.ptr);
         const bool narrow_out = p.narrow[st.index];
+        const bool int_sums = p.int_sums[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           if constexpr (std::is_same<Tin, uint8_t>::value) {
             if (narrow_out)  // exact integer sums below 2^16
-              return launch_input_gather<uint8_t, int32_t, uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm,
-                                                                     nt32, src.bstride, dst.stride, dst.bstride,
-                                                                     ps.nblocks);
+              return launch_narrow_input_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
+                                                          src.bstride, dst.stride, dst.bstride, ps.nblocks);
+            if (int_sums)
+              return launch_narrow_input_gather<Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.bstride,
+                                                      dst.stride, dst.bstride, ps.nblocks);
           }
           return launch_input_gather<Tin, Tacc, Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.bstride,
                                                       dst.stride, dst.bstride, ps.nblocks);
@@ -712,10 +715,11 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
           const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
+            // uint16 out: a lane's 8 samples are one 16-byte store. 4-byte
+            // planes keep the 4-sample runs, whose stores are whole lines.
             if (narrow_out)
-              return launch_gather<uint16_t, int32_t, uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
-                                                                src.stride, src.bstride, dst.stride, dst.bstride,
-                                                                ps.nblocks);
+              return launch_narrow_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32, src.stride,
+                                                    src.bstride, dst.stride, dst.bstride, ps.nblocks);
             return launch_gather<uint16_t, int32_t, Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.stride,
                                                           src.bstride, dst.stride, dst.bstride, ps.nblocks);
           }

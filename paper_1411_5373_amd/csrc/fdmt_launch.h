@@ -38,6 +38,19 @@ template <typename Tin, typename Tacc, typename Tdst>
 hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows);
 
+// The same two gathers over uint8 input or uint16 planes when every partial
+// sum is an integer below 2^24: int32 sums in any order, a lane owning 4 * vecs
+// consecutive samples (vecs 1 or 2). Tdst: uint16_t, int32_t or float from the
+// input; uint16_t from a plane.
+template <typename Tdst>
+hipError_t launch_narrow_input_gather(const GatherLaunch &g, const uint8_t *src, Tdst *dst, const int4 *terms,
+                                      int32_t nt, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                                      int32_t nrows);
+template <typename Tdst>
+hipError_t launch_narrow_gather(const GatherLaunch &g, const uint16_t *src, Tdst *dst, const int2 *terms,
+                                int32_t nt, int64_t src_stride, int64_t src_bstride, int64_t dst_stride,
+                                int64_t dst_bstride, int32_t nrows);
+
 // Adjoint register gather over a depth-first leaf list; max_shift bounds the
 // shifts of every leaf.
 template <typename Tacc>

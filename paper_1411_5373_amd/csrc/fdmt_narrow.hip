@@ -1,0 +1,245 @@
+// Register gathers over uint8 input or uint16 planes, with exact integer sums.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "fdmt_launch.h"
+
+namespace fdmt {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// The same sums as gather_pass_kernel and input_gather_kernel (2^k terms per
+// output, each a plane-l0 row at a shift, or an Option-1 chain of input
+// samples), over data whose every partial sum is an integer below 2^24: then
+// the sums are exact in any order and equal the tree-order FP32 or int32
+// results bit for bit. They are added into int32 lanes as they arrive.
+//
+// Layout: a wave covers 256 * CV consecutive samples like the other gathers,
+// but a lane owns S = 4 * CV consecutive samples, so a term is one wide load
+// per lane: W aligned words that cover the lane's bytes whatever their
+// misalignment, which is the same for every lane of a term (t is a multiple
+// of 4). Bytes take 16 bytes for 8 samples, uint16 20 bytes for 8 samples.
+template <bool FROM_INPUT, int CV>
+struct NarrowShape {
+  static constexpr int S = 4 * CV;  // samples per lane
+  // words per term: bytes: misalignment (<= 3) + chain (<= 4) + S;
+  // uint16: misalignment (0 or 2) + 2 S
+  static constexpr int W = FROM_INPUT ? (3 + 4 + S + 3) / 4 : (2 + 2 * S + 3) / 4;
+};
+
+template <int W>
+__device__ __forceinline__ void load_words(uint32_t (&w)[W], const char *q) {
+  if constexpr (W == 3) {
+    typedef uint32_t W3 __attribute__((ext_vector_type(3), aligned(4)));
+    const W3 x = *reinterpret_cast<const W3 *>(q);
+    w[0] = x[0];
+    w[1] = x[1];
+    w[2] = x[2];
+  } else {
+    typedef uint32_t W4 __attribute__((ext_vector_type(4), aligned(4)));
+    const W4 x = *reinterpret_cast<const W4 *>(q);
+    w[0] = x[0];
+    w[1] = x[1];
+    w[2] = x[2];
+    w[3] = x[3];
+    if constexpr (W == 5) w[4] = *reinterpret_cast<const uint32_t *>(q + 16);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T from_int(int32_t x) {
+  return static_cast<T>(x);
+}
+
+// Stores a lane's S samples (t .. t+S-1 of one row), clipped at nt.
+template <typename Tdst, int S>
+__device__ __forceinline__ void store_lane(Tdst *o, const int32_t (&acc)[S], int t, int nt) {
+  if (t + S <= nt) {
+    if constexpr (sizeof(Tdst) == 2) {
+      // 2 S bytes at an offset that is a multiple of 2 S: whole 16-, 8-byte words
+      typedef uint16_t H __attribute__((ext_vector_type(S), aligned(4)));
+      H h;
+#pragma unroll
+      for (int q = 0; q < S; ++q) h[q] = static_cast<uint16_t>(acc[q]);
+      *reinterpret_cast<H *>(o) = h;
+    } else {
+      typedef typename Vec4<Tdst>::type D4;
+#pragma unroll
+      for (int g = 0; g < S / 4; ++g) {
+        D4 d;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = from_int<Tdst>(acc[4 * g + q]);
+        *reinterpret_cast<D4 *>(o + 4 * g) = d;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (t + q < nt) o[q] = from_int<Tdst>(acc[q]);
+  }
+}
+
+template <bool FROM_INPUT, typename Tdst, int K, int CV, bool RAGGED>
+__global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
+    const void *__restrict__ src_v, Tdst *__restrict__ dst, const void *__restrict__ terms_v, int32_t nt_u,
+    int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
+    int32_t rows_per_wg, RaggedMap rg) {
+  typedef typename std::conditional<FROM_INPUT, uint8_t, uint16_t>::type Tsrc;
+  constexpr int N = 1 << K;
+  constexpr int S = NarrowShape<FROM_INPUT, CV>::S;
+  constexpr int W = NarrowShape<FROM_INPUT, CV>::W;
+  const int waves = kGatherThreads / 64;
+  const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int col_waves = waves / rows_per_wg;
+  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
+  const int g = xcd_local_order(blockIdx.x, groups);
+  const int r = g * rows_per_wg + wave / col_waves;
+  if (r >= nrows) return;
+  // the input's rows are Nt samples apart; a plane's by its (padded) stride
+  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, FROM_INPUT ? nt_u : src_stride_u, src_bstride, dst_stride_u,
+                                        dst_bstride);
+  const int nt = bs.nt;
+  const int64_t src_stride = FROM_INPUT ? nt : bs.src_stride;
+  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int t = tw + lane * S;
+  if (t >= nt) return;
+  const Tsrc *base = static_cast<const Tsrc *>(src_v) + bs.src_off;
+  // terms: (row or channel, shift, chain)
+  int row[N], shift[N], chain[N];
+  int reach = 0, longest = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if constexpr (FROM_INPUT) {
+      const int4 e = static_cast<const int4 *>(terms_v)[static_cast<int64_t>(r) * N + j];
+      row[j] = e.x;
+      shift[j] = e.y;
+      chain[j] = e.z;
+    } else {
+      const int2 e = static_cast<const int2 *>(terms_v)[static_cast<int64_t>(r) * N + j];
+      row[j] = e.x;
+      shift[j] = e.y;
+      chain[j] = 0;
+    }
+    reach = shift[j] + chain[j] > reach ? shift[j] + chain[j] : reach;
+    longest = chain[j] > longest ? chain[j] : longest;
+  }
+  int32_t acc[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = 0;
+  // Whole-word path: no sample of the wave before 0 (tw >= reach), its words
+  // inside the row (input: 8 samples of room after the wave's last; a plane
+  // row may be over-read by up to 4 bytes, into its padding or the workspace
+  // that follows, which is sized for 4-byte planes), a word-aligned buffer and
+  // chains of at most 4.
+  const bool words = (reinterpret_cast<uintptr_t>(base) & 3) == 0 && tw >= reach &&
+                     (FROM_INPUT ? tw + 256 * CV + 8 <= nt && longest <= 4 : tw + 256 * CV <= nt);
+  if (words) {
+    uint32_t w[N][W];
+    int mis[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const char *p = reinterpret_cast<const char *>(base + row[j] * src_stride + (t - shift[j] - chain[j]));
+      mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+      load_words<W>(w[j], p - mis[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if constexpr (FROM_INPUT) {
+        // chain element i (sample t - shift - i) starts mis + chain - i bytes in
+        for (int i = 0; i <= chain[j]; ++i) {
+          const int o = mis[j] + chain[j] - i;
+          const int k = o >> 2;
+#pragma unroll
+          for (int q4 = 0; q4 < CV; ++q4) {
+            const uint32_t lo = k ? w[j][q4 + 1] : w[j][q4];
+            const uint32_t hi = k ? w[j][q4 + 2] : w[j][q4 + 1];
+            const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[4 * q4 + q] += (x >> (8 * q)) & 0xffu;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) {
+          const uint32_t x = __builtin_amdgcn_alignbyte(w[j][m + 1], w[j][m], mis[j]);
+          acc[2 * m] += x & 0xffffu;
+          acc[2 * m + 1] += x >> 16;
+        }
+      }
+    }
+  } else {
+    // row edges: every sample checked against [0, nt)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tsrc *rp = base + row[j] * src_stride;
+      for (int i = 0; i <= chain[j]; ++i) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          const int ts = t + q - shift[j] - i;
+          if (ts >= 0 && ts < nt) acc[q] += rp[ts];
+        }
+      }
+    }
+  }
+  store_lane<Tdst, S>(dst + bs.dst_off + r * bs.dst_stride + t, acc, t, nt);
+}
+
+template <bool FROM_INPUT, typename Tdst>
+hipError_t launch_narrow(const GatherLaunch &g, const void *src, Tdst *dst, const void *terms, int32_t nt,
+                         int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                         int32_t nrows) {
+#define FDMT_NARROW(KK, CC, RR)                                                                                 \
+  hipLaunchKernelGGL((narrow_gather_kernel<FROM_INPUT, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0,     \
+                     g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows,   \
+                     g.rows_per_wg, g.rg)
+#define FDMT_NARROW_K(CC, RR)              \
+  switch (g.depth) {                       \
+    case 1: FDMT_NARROW(1, CC, RR); break; \
+    case 2: FDMT_NARROW(2, CC, RR); break; \
+    case 3: FDMT_NARROW(3, CC, RR); break; \
+    case 4: FDMT_NARROW(4, CC, RR); break; \
+    default: return hipErrorInvalidValue;  \
+  }
+  if (g.ragged) {
+    if (g.vecs == 2) { FDMT_NARROW_K(2, true) } else { FDMT_NARROW_K(1, true) }
+  } else {
+    if (g.vecs == 2) { FDMT_NARROW_K(2, false) } else { FDMT_NARROW_K(1, false) }
+  }
+#undef FDMT_NARROW_K
+#undef FDMT_NARROW
+  return hipGetLastError();
+}
+
+} // namespace
+
+template <typename Tdst>
+hipError_t launch_narrow_input_gather(const GatherLaunch &g, const uint8_t *src, Tdst *dst, const int4 *terms,
+                                      int32_t nt, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
+                                      int32_t nrows) {
+  if (g.vecs != 1 && g.vecs != 2) return hipErrorInvalidValue;
+  return launch_narrow<true, Tdst>(g, src, dst, terms, nt, nt, src_bstride, dst_stride, dst_bstride, nrows);
+}
+
+template <typename Tdst>
+hipError_t launch_narrow_gather(const GatherLaunch &g, const uint16_t *src, Tdst *dst, const int2 *terms,
+                                int32_t nt, int64_t src_stride, int64_t src_bstride, int64_t dst_stride,
+                                int64_t dst_bstride, int32_t nrows) {
+  if (g.vecs != 1 && g.vecs != 2) return hipErrorInvalidValue;
+  return launch_narrow<false, Tdst>(g, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride,
+                                    nrows);
+}
+
+#define FDMT_NARROW_INST(T)                                                                                   \
+  template hipError_t launch_narrow_input_gather<T>(const GatherLaunch &, const uint8_t *, T *, const int4 *, \
+                                                    int32_t, int64_t, int64_t, int64_t, int32_t);
+FDMT_NARROW_INST(uint16_t)
+FDMT_NARROW_INST(int32_t)
+FDMT_NARROW_INST(float)
+#undef FDMT_NARROW_INST
+template hipError_t launch_narrow_gather<uint16_t>(const GatherLaunch &, const uint16_t *, uint16_t *, const int2 *,
+                                                   int32_t, int64_t, int64_t, int64_t, int64_t, int32_t);
+
+} // namespace fdmt

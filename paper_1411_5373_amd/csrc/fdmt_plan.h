@@ -64,6 +64,7 @@ struct Plan {
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
   std::vector<uint8_t> narrow; // per forward pass: its output plane holds uint16 sums
+  std::vector<uint8_t> int_sums; // per forward pass: uint8 input or uint16 planes in, sums integers below 2^24
   std::vector<Step> fwd_steps, adj_steps;
   int64_t ws_rows = 0;         // rows of each workspace plane
 };
