@@ -114,6 +114,10 @@ typedef struct {
                                 pass: 1, 2, 4, 8 or 16 (0 = gather_rows). Channels of one
                                 sub-band read the same rows, so a workgroup of one whole
                                 sub-band reads them through one L1 */
+  double gamma;           /* delay law dt ~ f^gamma (Sec. 4.2, other functional forms: the
+                             power -2 of Eq. Cf2f0 becomes gamma); finite, nonzero
+                             (0 = default: -2, the cold-plasma law). Changes the tables
+                             and so the results */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

@@ -41,6 +41,9 @@ listed with its justification in the design notes):
          its continuous estimate of the same quantity).
   R-fp   1/f^2 is evaluated as 1.0/(f*f); C = (1/f1^2 - 1/f0^2)/(1/f2^2 - 1/f0^2)
          in that order, IEEE float64, no fused multiply-add.
+  R-law  another delay law dt ~ f^gamma (Sec. 4.2, other functional forms)
+         replaces the power -2 of Eq. (Cf2f0) by gamma and nothing else;
+         f^gamma is the C library's pow (gamma = -2 keeps 1.0/(f*f)).
 """
 from __future__ import annotations
 
@@ -65,10 +68,16 @@ def _inv_sq(f):
     return 1.0 / (f * f)
 
 
-def merge_coefficient(f0, f1, f2):
+def _law(f, gamma):
+    """f^gamma (reading R-law); the cold-plasma f^-2 as 1.0/(f*f)."""
+    return _inv_sq(f) if gamma == -2.0 else math.pow(f, gamma)
+
+
+def merge_coefficient(f0, f1, f2, gamma=-2.0):
     """Eq. (Cf2f0): C_{f2,f0} = (f1^-2 - f0^-2) / (f2^-2 - f0^-2), the fraction of
-    the sub-band delay spent between f0 and the border frequency f1."""
-    return (_inv_sq(f1) - _inv_sq(f0)) / (_inv_sq(f2) - _inv_sq(f0))
+    the sub-band delay spent between f0 and the border frequency f1; for the law
+    dt ~ f^gamma the power -2 becomes gamma (Sec. 4.2)."""
+    return (_law(f1, gamma) - _law(f0, gamma)) / (_law(f2, gamma) - _law(f0, gamma))
 
 
 def round_half_up(x):
@@ -89,25 +98,29 @@ class Tables:
     levels: int                 # log2(nf)
     rows: list                  # rows[l][j]: number of dt rows of sub-band j at iteration l
     split: list                 # split[l][j][dt] = (d_lo, s, d_hi) for l >= 1
+    gamma: float = -2.0         # delay law dt ~ f^gamma
 
     @property
     def leaf_rows(self):
         return self.rows[0]
 
 
-def build_tables(nf, nd, f_min, f_max):
+def build_tables(nf, nd, f_min, f_max, gamma=-2.0):
     """Per iteration l = 1..log2(Nf) and sub-band j (channels j*2^l .. (j+1)*2^l - 1,
     f0 = e[j*2^l], f1 = e[(2j+1)*2^(l-1)], f2 = e[(j+1)*2^l]):
         for each dt: t0 - t1 = d_lo = round(C_{f2,f0} * dt)   (lower half's delay)
                      s = d_lo                                  (upper half's start shift)
                      t1 - t2 = d_hi = dt - d_lo                (upper half's delay)
-    Row counts run top-down from Nd at the last iteration (reading R-rows)."""
+    Row counts run top-down from Nd at the last iteration (reading R-rows).
+    gamma: the delay law dt ~ f^gamma (reading R-law)."""
     if nf < 1 or nf & (nf - 1):
         raise ValueError("Nf must be a power of two")
     if nd < 1:
         raise ValueError("Nd must be >= 1")
     if not (0.0 < f_min < f_max):
         raise ValueError("need 0 < f_min < f_max")
+    if not math.isfinite(gamma) or gamma == 0.0:
+        raise ValueError("gamma must be finite and nonzero")
     levels = nf.bit_length() - 1
     e = channel_edges(nf, f_min, f_max)
     rows = [None] * (levels + 1)
@@ -121,7 +134,7 @@ def build_tables(nf, nd, f_min, f_max):
             f0 = e[j << l]
             f1 = e[(2 * j + 1) << (l - 1)]
             f2 = e[(j + 1) << l]
-            c = merge_coefficient(f0, f1, f2)
+            c = merge_coefficient(f0, f1, f2, gamma)
             triples = []
             for dt in range(rows[l][j]):
                 d_lo = round_half_up(dt * c)
@@ -130,7 +143,7 @@ def build_tables(nf, nd, f_min, f_max):
             last = triples[-1]
             rows[l - 1][2 * j] = last[0] + 1
             rows[l - 1][2 * j + 1] = last[2] + 1
-    return Tables(nf, nd, f_min, f_max, levels, rows, split)
+    return Tables(nf, nd, f_min, f_max, levels, rows, split, float(gamma))
 
 
 # ----------------------------------------------------------------------------
@@ -287,7 +300,7 @@ def brute_row(img, tables, dt):
     return out
 
 
-def brute_ideal(img, f_min, f_max, nd):
+def brute_ideal(img, f_min, f_max, nd, gamma=-2.0):
     """Brute-force dedispersion along the exact law (prior-art comparator, Sec. 3):
     each channel contributes I[k][t0 - round(dt * phi(centre_k))]."""
     img = np.asarray(img)
@@ -295,10 +308,10 @@ def brute_ideal(img, f_min, f_max, nd):
     e = channel_edges(nf, f_min, f_max)
     acc = _acc_dtype(img)
     out = np.zeros((nd, nt), dtype=acc)
-    den = _inv_sq(f_min) - _inv_sq(f_max)
+    den = _law(f_min, gamma) - _law(f_max, gamma)
     for k in range(nf):
         centre = 0.5 * (e[k] + e[k + 1])
-        phi = (_inv_sq(f_min) - _inv_sq(centre)) / den
+        phi = (_law(f_min, gamma) - _law(centre, gamma)) / den
         for dt in range(nd):
             sh = round_half_up(dt * phi)
             if sh < nt:

@@ -8,10 +8,11 @@ speed, so the tuner compares times alone. Forward and adjoint are tuned
 separately; the fields they share (the gather workgroup shape) are chosen to
 minimise their sum.
 
-Cache key: GPU architecture, Nf, Nd, band, input and accumulation dtypes and
-Nt rounded up to a power of two. The cache shipped with the package
-(tuning/<arch>.json) holds the entries its benchmark workloads use;
-FDMT_TUNE_CACHE names another file to read and update instead.
+Cache key: GPU architecture, Nf, Nd, band, the delay law's power when it is
+not -2, input and accumulation dtypes and Nt rounded up to a power of two.
+The cache shipped with the package (tuning/<arch>.json) holds the entries its
+benchmark workloads use; FDMT_TUNE_CACHE names another file to read and
+update instead.
 
 Command line (on a GPU):
   python -m paper_1411_5373_amd.autotune --nf 4096 --nt 65536 --nd 2048 \
@@ -78,8 +79,9 @@ def nt_bucket(nt):
     return b
 
 
-def cache_key(arch_name, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype):
-    return (f"{arch_name}/nf{nf}/nd{nd}/band{float(f_min):.6g}-{float(f_max):.6g}/"
+def cache_key(arch_name, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=-2.0):
+    law = "" if float(gamma) == -2.0 else f"/gamma{float(gamma):.6g}"
+    return (f"{arch_name}/nf{nf}/nd{nd}/band{float(f_min):.6g}-{float(f_max):.6g}{law}/"
             f"{_NAMES[in_dtype]}->{_NAMES[acc_dtype]}/nt{nt_bucket(nt)}")
 
 
@@ -95,10 +97,10 @@ def load_cache(arch_name):
         return json.load(f)
 
 
-def lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, arch_name=None):
+def lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, arch_name=None, gamma=-2.0):
     """Tuned schedule options for this workload, or None."""
     a = arch_name or arch()
-    entry = load_cache(a).get(cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype))
+    entry = load_cache(a).get(cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma))
     return None if entry is None else dict(entry["options"])
 
 
@@ -115,7 +117,7 @@ def _time(fn, reps):
 
 
 def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32, reps=5,
-         verbose=False):
+         verbose=False, gamma=-2.0):
     """Times every candidate; returns {"options", "forward_ms", "adjoint_ms", "tried"}."""
     dev = torch.device("cuda", torch.cuda.current_device())
     gen = torch.Generator(device=dev).manual_seed(1)
@@ -137,7 +139,7 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
         for cand in forward_candidates():
             opts = dict(cand, **shared)
             try:
-                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, **opts)
+                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
             except B.FDMTError:
                 continue  # this schedule does not fit the shape
             ws = p.workspace(1)
@@ -151,7 +153,7 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
         for cand in adjoint_candidates(rows):
             opts = dict(cand, **shared)
             try:
-                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, **opts)
+                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
             except B.FDMTError:
                 continue
             ws = p.workspace(1)
@@ -174,11 +176,11 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
     return best
 
 
-def store(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, result, arch_name=None):
+def store(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, result, arch_name=None, gamma=-2.0):
     a = arch_name or arch()
     path = cache_path(a)
     cache = load_cache(a)
-    cache[cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype)] = {
+    cache[cache_key(a, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma)] = {
         "options": result["options"], "forward_ms": result["forward_ms"],
         "adjoint_ms": result["adjoint_ms"], "tuned_at_nt": int(nt),
         "date": time.strftime("%Y-%m-%d")}
@@ -197,18 +199,20 @@ def main():
     ap.add_argument("--band", type=float, nargs=2, required=True)
     ap.add_argument("--in-dtype", choices=sorted(DTYPES), default="f32")
     ap.add_argument("--acc-dtype", choices=sorted(DTYPES), default="f32")
+    ap.add_argument("--gamma", type=float, default=-2.0, help="delay law dt ~ f^gamma")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--write", action="store_true", help="store the result in the cache")
     ap.add_argument("--out", help="also write the full result (every candidate's time) to this JSON file")
     args = ap.parse_args()
     ind, acc = DTYPES[args.in_dtype], DTYPES[args.acc_dtype]
-    res = tune(args.nf, args.nt, args.nd, *args.band, ind, acc, reps=args.reps, verbose=True)
+    res = tune(args.nf, args.nt, args.nd, *args.band, ind, acc, reps=args.reps, verbose=True, gamma=args.gamma)
     print(json.dumps({k: v for k, v in res.items() if k != "tried"}), flush=True)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(dict(res, workload=vars(args)), f, indent=1)
     if args.write:
-        print("stored in", store(args.nf, args.nt, args.nd, *args.band, ind, acc, res), flush=True)
+        print("stored in", store(args.nf, args.nt, args.nd, *args.band, ind, acc, res, gamma=args.gamma),
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -51,7 +51,8 @@ class _Options(ctypes.Structure):
                 ("first_kernel", ctypes.c_int32), ("later_kernel", ctypes.c_int32),
                 ("stream_tiles", ctypes.c_int32), ("gather_rows", ctypes.c_int32),
                 ("adjoint_levels", ctypes.c_int32), ("adjoint_last_levels", ctypes.c_int32),
-                ("gather_vecs", ctypes.c_int32), ("adjoint_last_rows", ctypes.c_int32)]
+                ("gather_vecs", ctypes.c_int32), ("adjoint_last_rows", ctypes.c_int32),
+                ("gamma", ctypes.c_double)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -141,14 +142,14 @@ def fdmt_last_error():
 def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0,
               first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
-              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0):
+              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
                    int(later_levels), int(tile), int(lds_kib), int(max_block_rows),
                    int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows),
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
-                   int(adjoint_last_rows))
+                   int(adjoint_last_rows), float(gamma))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -264,12 +265,14 @@ class Plan:
     shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
-                 host_only=False, unfused=False, tuned=False, wide_planes=False, **schedule):
-        """`schedule`: fdmt_options_t schedule fields (first_kernel, first_levels,
-        ...). tuned=True first takes the autotuner's stored options for this
+                 host_only=False, unfused=False, tuned=False, wide_planes=False, gamma=-2.0, **schedule):
+        """`gamma`: the delay law dt ~ f^gamma (-2: cold plasma). `schedule`:
+        fdmt_options_t schedule fields (first_kernel, first_levels, ...).
+        tuned=True first takes the autotuner's stored options for this
         workload, if any; explicit schedule fields override them."""
         self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
         self.f_min, self.f_max = float(f_min), float(f_max)
+        self.gamma = float(gamma)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
         flags = ((FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0) |
                  (FDMT_PLAN_WIDE_PLANES if wide_planes else 0))
@@ -277,13 +280,13 @@ class Plan:
         self.tuned = None
         if tuned and not host_only and not unfused:
             from . import autotune
-            self.tuned = autotune.lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype)
+            self.tuned = autotune.lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=self.gamma)
             if self.tuned:
                 schedule = dict(self.tuned, **schedule)
         self.options = dict(schedule)
         self.handle = None
         self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
-                                _TORCH_TO_CODE[acc_dtype], flags, **schedule)
+                                _TORCH_TO_CODE[acc_dtype], flags, gamma=self.gamma, **schedule)
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None

@@ -215,7 +215,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (!h) return fail(FDMT_E_NOMEM, "host allocation of the plan failed");
   fdmt::Plan &p = h->plan;
   try {
-    const std::string err = fdmt::build_tables(p.tab, nf, nd, f_min, f_max);
+    const std::string err = fdmt::build_tables(p.tab, nf, nd, f_min, f_max, o.gamma != 0.0 ? o.gamma : -2.0);
     if (!err.empty()) {
       delete h;
       return fail(FDMT_E_INVALID, err);

@@ -132,9 +132,10 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   // Whole-word path: no sample of the wave before 0 (tw >= reach), its words
   // inside the row (input: 8 samples of room after the wave's last; a plane
   // row may be over-read by up to 4 bytes, into its padding or the workspace
-  // that follows, which is sized for 4-byte planes), a word-aligned buffer and
-  // chains of at most 4.
-  const bool words = (reinterpret_cast<uintptr_t>(base) & 3) == 0 && tw >= reach &&
+  // that follows, which is sized for 4-byte planes), a word-aligned buffer (a
+  // beam's rows may start off a word: the words before them are the buffer's)
+  // and chains of at most 4.
+  const bool words = (reinterpret_cast<uintptr_t>(src_v) & 3) == 0 && tw >= reach &&
                      (FROM_INPUT ? tw + 256 * CV + 8 <= nt && longest <= 4 : tw + 256 * CV <= nt);
   if (words) {
     uint32_t w[N][W];

@@ -8,6 +8,9 @@
 // with C_{f2,f0} from Eq. (Cf2f0). Rows are counted top-down from the Nd
 // output rows: a child needs exactly the rows its parent reads, which is the
 // discrete counterpart of the dt_max(i, f0) estimate of Algorithm 1.
+//
+// Other delay laws dt ~ f^gamma (Sec. 4.2, other functional forms) change
+// only C: the power -2 of Eq. (Cf2f0) becomes gamma.
 #include "fdmt_tables.h"
 
 #include <cmath>
@@ -16,12 +19,13 @@ namespace fdmt {
 
 namespace {
 
-double inv_square(double f) { return 1.0 / (f * f); }
+// f^gamma; the cold-plasma law's f^-2 as 1 / (f * f).
+double law(double f, double gamma) { return gamma == -2.0 ? 1.0 / (f * f) : std::pow(f, gamma); }
 
 // Eq. (Cf2f0), evaluated exactly in this order.
-double merge_coefficient(double f0, double f1, double f2) {
-  const double num = inv_square(f1) - inv_square(f0);
-  const double den = inv_square(f2) - inv_square(f0);
+double merge_coefficient(double f0, double f1, double f2, double gamma) {
+  const double num = law(f1, gamma) - law(f0, gamma);
+  const double den = law(f2, gamma) - law(f0, gamma);
   return num / den;
 }
 
@@ -30,11 +34,12 @@ int32_t round_half_up(double x) { return static_cast<int32_t>(std::floor(x + 0.5
 
 } // namespace
 
-std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max) {
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma) {
   if (nf < 1 || (nf & (nf - 1)) != 0) return "Nf must be a power of two";
   if (nd < 1) return "Nd must be >= 1";
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
     return "need 0 < f_min < f_max (finite)";
+  if (!std::isfinite(gamma) || gamma == 0.0) return "the delay law's power must be finite and nonzero";
   int levels = 0;
   while ((1 << levels) < nf) ++levels;
 
@@ -44,6 +49,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max) 
   t.levels = levels;
   t.f_min = f_min;
   t.f_max = f_max;
+  t.gamma = gamma;
 
   const double df = (f_max - f_min) / nf;
   std::vector<double> edge(nf + 1);
@@ -67,7 +73,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max) 
       const double f0 = edge[static_cast<size_t>(j) << l];
       const double f1 = edge[static_cast<size_t>(2 * j + 1) << (l - 1)];
       const double f2 = edge[static_cast<size_t>(j + 1) << l];
-      const double c = merge_coefficient(f0, f1, f2);
+      const double c = merge_coefficient(f0, f1, f2, gamma);
       const int32_t n = t.rows[l][j];
       auto &lo = lo_of[l][j];
       auto &hi = hi_of[l][j];

@@ -25,6 +25,7 @@ struct AdjRow {
 struct Tables {
   int nf = 0, nd = 0, levels = 0;
   double f_min = 0, f_max = 0;
+  double gamma = -2.0;  // delay law dt ~ f^gamma
   // rows[l][j]: dt rows of sub-band j after iteration l (l = 0: channel j's
   // Option-1 partial sums; l = levels: the single output sub-band, nd rows).
   std::vector<std::vector<int32_t>> rows;
@@ -42,7 +43,8 @@ struct Tables {
   std::vector<int32_t> leaf_off, leaf_rows;
 };
 
-// Builds every table. Returns "" on success or a description of the problem.
-std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max);
+// Builds every table for the delay law dt ~ f^gamma (-2: cold plasma).
+// Returns "" on success or a description of the problem.
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma = -2.0);
 
 } // namespace fdmt

@@ -54,6 +54,29 @@ def test_tables_match_oracle(nf, nd, band):
             assert list(zip(d_lo, s, d_hi)) == ref.split[l][j], (l, j)
 
 
+@pytest.mark.parametrize("gamma", [-1.0, 1.0, 2.5, -4.0])
+@pytest.mark.parametrize("nf,nd,band", [(64, 64, (1.2, 1.6)), (1024, 700, (0.4, 0.8)), (4096, 2048, (1.2, 1.6))])
+def test_power_law_tables_match_oracle(gamma, nf, nd, band):
+    """Delay law dt ~ f^gamma: the library's tables equal the oracle's
+    (the same float64 expression and pow), and differ from the -2 law's."""
+    ref = build_tables(nf, nd, *band, gamma=gamma)
+    p = F.Plan(nf, 1000, nd, *band, host_only=True, gamma=gamma)
+    levels, rows = p.info()
+    assert rows == [sum(r) for r in ref.rows]
+    differs = False
+    default = build_tables(nf, nd, *band)
+    for l in range(1, levels + 1):
+        for j in range(nf >> l):
+            d_lo, s, d_hi, n = p.tables(l, j)
+            assert list(zip(d_lo, s, d_hi)) == ref.split[l][j], (l, j)
+            differs |= ref.split[l][j] != default.split[l][j]
+    assert differs
+    for bad in (float("inf"), float("nan")):
+        with pytest.raises(F.FDMTError) as e:
+            F.Plan(nf, 1000, nd, *band, host_only=True, gamma=bad)
+        assert e.value.status == B.FDMT_E_INVALID
+
+
 def test_random_bands_match_oracle():
     import numpy as np
     rng = np.random.default_rng(99)

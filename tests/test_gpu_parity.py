@@ -310,6 +310,28 @@ def test_schedules_bit_identical(sched, nf, nt, nd, band):
     assert torch.equal(pi.forward(xi), refi)
 
 
+@pytest.mark.parametrize("gamma", [-1.0, 2.0, -3.0])
+@pytest.mark.parametrize("sched", [dict(), dict(first_kernel=3, first_levels=3, later_levels=3, gather_vecs=4,
+                                                adjoint_levels=3, adjoint_last_levels=3, adjoint_last_rows=8)])
+def test_power_law_forward_and_adjoint(gamma, sched):
+    """Delay law dt ~ f^gamma (Sec. 4.2): the plan's tables drive every kernel,
+    so the forward (uint8 -> int32, uint8 -> FP32) equals the int64 oracle
+    built for that law and the FP32 adjoint its binary32 evaluation."""
+    nf, nt, nd, band = 256, 3001, 300, (1.2, 1.6)
+    print(f"power law gamma={gamma} {sched}", flush=True)
+    tab = build_tables(nf, nd, *band, gamma=gamma)
+    x = W.random_input((nf, nt), np.uint8, seed=int(7 * gamma) + 50)
+    ref = ofdmt(x.astype(np.int64), *band, nd, tab)
+    for acc in (torch.int32, torch.float32):
+        p = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=acc, gamma=gamma, **sched)
+        y = p.forward(_dev(x)).cpu().numpy()
+        np.testing.assert_array_equal(y.astype(np.int64), ref)
+    g = W.random_input((nd, nt), np.float32, seed=int(3 * gamma) + 60)
+    p = F.Plan(nf, nt, nd, *band, gamma=gamma, **sched)
+    xb = p.adjoint(_dev(g)).cpu().numpy()
+    np.testing.assert_array_equal(xb, oadj(g, *band, nf, tab, acc=np.float32))
+
+
 ADJOINT_SCHEDULES = [
     dict(adjoint_levels=1, adjoint_last_levels=1),
     dict(adjoint_levels=2, adjoint_last_levels=1, gather_rows=4),

@@ -132,6 +132,12 @@ def test_ragged_other_kernel_forms(sched, nf, nd, band):
     for x, yb, n in zip(xu, yu, LENGTHS):
         if n:
             np.testing.assert_array_equal(yb.astype(np.int64), ofdmt(x, *band, nd))
+    # uint8 -> FP32: integer sums below 2^24, exact
+    pf = F.Plan(nf, 4096, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.float32, **sched)
+    yf = _unpack(F.RaggedPlan(pf, LENGTHS).forward(_pack(xu, np.uint8)).cpu().numpy(), nd, LENGTHS)
+    for x, yb, n in zip(xu, yf, LENGTHS):
+        if n:
+            np.testing.assert_array_equal(yb.astype(np.int64), ofdmt(x, *band, nd))
     gs = _beam_inputs(nd, LENGTHS, np.float32, 9 * nf + nd)
     xb = _unpack(F.RaggedPlan(p, LENGTHS).adjoint(_pack(gs, np.float32)).cpu().numpy(), nf, LENGTHS)
     for g, xbb, n in zip(gs, xb, LENGTHS):

@@ -77,6 +77,66 @@ def test_path_follows_dispersion_law(nf, nd, band):
         assert np.max(np.abs(sig - dt * phi)) <= bound
 
 
+@pytest.mark.parametrize("gamma", [-1.0, 1.0, 2.0, -3.5])
+@pytest.mark.parametrize("nf,nd", [(16, 40), (256, 300), (1024, 1024)])
+@pytest.mark.parametrize("band", BANDS)
+def test_path_follows_power_law(gamma, nf, nd, band):
+    """Another delay law dt ~ f^gamma (Sec. 4.2, other functional forms): the
+    tables built with gamma keep every path within log2(Nf)/2 samples of
+    dt*phi_gamma(e_k), phi_gamma(f) = (f_min^g - f^g)/(f_min^g - f_max^g), and
+    the runs still tile [t0 - dt, t0]; the -2 law's phi misses them."""
+    f_min, f_max = band
+    t = build_tables(nf, nd, f_min, f_max, gamma=gamma)
+    e = np.array([f_min + k * (f_max - f_min) / nf for k in range(nf)])
+    phi = (f_min ** gamma - e ** gamma) / (f_min ** gamma - f_max ** gamma)
+    phi2 = (f_min ** -2 - e ** -2) / (f_min ** -2 - f_max ** -2)
+    bound = 0.5 * t.levels + 1e-9
+    worst2 = 0.0
+    for dt in list(range(0, nd, max(1, nd // 53))) + [nd - 1]:
+        p = np.array(path(t, dt))
+        sig, dlt = p[:, 0], p[:, 1]
+        assert sig[0] == 0
+        np.testing.assert_array_equal(sig[1:], sig[:-1] + dlt[:-1])
+        assert sig[-1] + dlt[-1] == dt
+        assert np.max(np.abs(sig - dt * phi)) <= bound
+        worst2 = max(worst2, np.max(np.abs(sig - dt * phi2)))
+    if nd >= 300:
+        assert worst2 > bound
+
+
+@pytest.mark.parametrize("nf,nd", [(8, 50), (512, 700)])
+def test_linear_law_splits_in_half(nf, nd):
+    """dt ~ f (gamma = 1): equal sub-bands take equal delays, so every merge
+    coefficient is 1/2 and d_lo is dt/2 rounded (either way at odd dt, where
+    dt*C sits within rounding of a half)."""
+    t = build_tables(nf, nd, 1.2, 1.6, gamma=1.0)
+    for l in range(1, t.levels + 1):
+        for trip in t.split[l]:
+            for dt, (d_lo, s, d_hi) in enumerate(trip):
+                assert d_lo in (dt // 2, (dt + 1) // 2) and s == d_lo and d_lo + d_hi == dt
+                if dt % 2 == 0:
+                    assert d_lo == dt // 2
+
+
+@pytest.mark.parametrize("gamma", [-1.0, 2.0])
+def test_power_law_pulses_recovered(gamma):
+    """Width-1 pulses placed along dt ~ f^gamma peak at their (dt, T) in the
+    transform built for that law and sum to Nf there by brute force along it."""
+    nf, nd, band = 256, 256, (1.2, 1.6)
+    rng = _rng(int(10 * gamma) + 99)
+    nt = nd + 200
+    tab = build_tables(nf, nd, *band, gamma=gamma)
+    for dt in [0, nd // 3, nd - 1]:
+        t_arr = int(rng.integers(nd, nt))
+        img = np.zeros((nf, nt), dtype=np.int64)
+        W.inject_pulses(img, band[0], band[1], [(dt, t_arr, 1.0)], gamma=gamma)
+        out = fdmt(img, band[0], band[1], nd, tab)
+        i, j = np.unravel_index(np.argmax(out), out.shape)
+        assert abs(i - dt) <= 2 and abs(j - t_arr) <= 2, (dt, t_arr, i, j)
+        assert out[i, j] >= 0.6 * nf
+        assert brute_ideal(img, band[0], band[1], nd, gamma=gamma)[dt, t_arr] == nf
+
+
 def test_work_below_paper_bound():
     """Sec. 4.1: additions <= 2*Nf*Nt + Nt*Nd*log2(Nf) (per unit Nt)."""
     for nf, nd in [(64, 64), (1024, 1024), (4096, 2048), (1024, 512)]:

@@ -55,9 +55,11 @@ WORKLOADS = {
 }
 
 
-def band_fraction(f, f_min, f_max):
-    """Fraction of the full-band delay reached at frequency f (dispersion law)."""
-    return (f_min ** -2 - np.asarray(f, dtype=np.float64) ** -2) / (f_min ** -2 - f_max ** -2)
+def band_fraction(f, f_min, f_max, gamma=-2.0):
+    """Fraction of the full-band delay reached at frequency f, for the delay law
+    dt ~ f^gamma (-2: cold-plasma dispersion)."""
+    f = np.asarray(f, dtype=np.float64)
+    return (f_min ** gamma - f ** gamma) / (f_min ** gamma - f_max ** gamma)
 
 
 def channel_centres(nf, f_min, f_max):
@@ -65,18 +67,18 @@ def channel_centres(nf, f_min, f_max):
     return f_min + (np.arange(nf, dtype=np.float64) + 0.5) * df
 
 
-def pulse_samples(nf, f_min, f_max, dt, t_arr):
+def pulse_samples(nf, f_min, f_max, dt, t_arr, gamma=-2.0):
     """Per-channel sample index of a width-1 pulse: round(T - dt*phi(centre_k))."""
-    frac = band_fraction(channel_centres(nf, f_min, f_max), f_min, f_max)
+    frac = band_fraction(channel_centres(nf, f_min, f_max), f_min, f_max, gamma)
     return np.rint(t_arr - dt * frac).astype(np.int64)
 
 
-def inject_pulses(img, f_min, f_max, pulses, scale=1.0):
+def inject_pulses(img, f_min, f_max, pulses, scale=1.0, gamma=-2.0):
     """Add each pulse (dt, T, amp) to img[nf][nt] in place (amp*scale per channel)."""
     nf, nt = img.shape
     rows = np.arange(nf)
     for dt, t_arr, amp in pulses:
-        ts = pulse_samples(nf, f_min, f_max, dt, t_arr)
+        ts = pulse_samples(nf, f_min, f_max, dt, t_arr, gamma)
         ok = (ts >= 0) & (ts < nt)
         np.add.at(img, (rows[ok], ts[ok]), img.dtype.type(amp * scale))
     return img
