@@ -179,6 +179,24 @@ def differentiable_c5(F, torch, W, reps=3):
             "schedule": plan.options}
 
 
+def boxcar_on_output(F, torch, y, max_log2=8, reps=10):
+    """Boxcar search (widths 1..2^max_log2) over the step's FP32 forward output
+    ([Nd][Nt]); its algorithmic bytes are one read of the plane."""
+    nd, nt = y.shape
+    ws = torch.empty(F.fdmt_boxcar_workspace_bytes(1, nd, nt, max_log2), dtype=torch.uint8, device=y.device)
+    F.boxcar_search(y, max_log2, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        F.boxcar_search(y, max_log2, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"widths": f"1..{1 << max_log2}", "plane": f"[{nd}][{nt}] FP32 forward output", "ms": round(ms, 4),
+            "alg_gb_s": round(nd * nt * 4 / ms / 1e6, 1)}
+
+
 def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, tuned=True)
     gen = torch.Generator(device="cuda").manual_seed(11)
@@ -356,6 +374,7 @@ def main():
         out["precision_forms"] = forms
         if "adjoint_f32" in acc:
             out["adjoint"]["accuracy_vs_oracle"] = acc["adjoint_f32"]
+    out["boxcar"] = boxcar_on_output(F, torch, y)
     del x, g, y, xb, ws, plan
     if not args.no_ragged:
         torch.cuda.empty_cache()

@@ -118,6 +118,13 @@ typedef struct {
                              power -2 of Eq. Cf2f0 becomes gamma); finite, nonzero
                              (0 = default: -2, the cold-plasma law). Changes the tables
                              and so the results */
+  int32_t d_min;          /* smallest total delay searched, in samples, >= 0 (Sec. 4.2,
+                             different range of dispersions): channel k's input is
+                             delayed by pre_k = round(d_min * phi(c_k)), phi the fraction
+                             of the band delay at its centre c_k, so output row dt
+                             follows delay d_min + dt. Needs the first pass to gather from
+                             the input (first_kernel 3, the default when d_min > 0) or
+                             the unfused schedule. Changes the results */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
@@ -252,6 +259,36 @@ fdmt_status_t fdmt_ragged_info(fdmt_ragged_t r, int32_t *nbeams, int64_t *total_
 
 /* Release the ragged plan's device buffer (must not be in use by queued work). NULL is a no-op. */
 fdmt_status_t fdmt_ragged_destroy(fdmt_ragged_t r);
+
+/* Boxcar search (Sec. 4.2, pulse profile: a profile shared by every frequency
+ * commutes with the transform, so boxcars of several widths run on its output
+ * instead of on the input, one transform for all widths).
+ * For every beam, row dt of plane[b] and width w = 2^j, j = 0..max_log2:
+ *   b_w[t] = y[t] + y[t-1] + ... + y[t-w+1], y = plane[b][dt], zero before t = 0,
+ * summed in FP32 as b_2w[t] = b_w[t] + b_w[t-w] from b_1 = y, and reports its
+ * largest value `peak`, the first t where it occurs, the mean and (population)
+ * standard deviation of b_w over t = 0..nt-1, accumulated in FP64, and
+ * snr = (peak - mean) / stdev (0 when stdev is 0). NaN samples are never a
+ * peak. */
+typedef struct {
+  float peak;
+  int32_t t;
+  float mean;
+  float stdev;
+  float snr;
+} fdmt_boxcar_t;
+
+/* Workspace (bytes) of fdmt_boxcar_search; 0 for invalid sizes. */
+size_t fdmt_boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2);
+
+/* plane : device, [batch][nd][nt] FP32 (an FDMT output), read only
+ * out   : device, [batch][max_log2 + 1][nd] results, fully overwritten
+ * ws    : device scratch of fdmt_boxcar_workspace_bytes()
+ * Sizes: batch, nd in [1, 65535], nt in [1, 2^31 - 1], max_log2 in [0, 10].
+ * Errors: FDMT_E_INVALID (NULL pointer, a size out of range),
+ * FDMT_E_WORKSPACE, FDMT_E_DEVICE. Enqueued on hip_stream; allocates nothing. */
+fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                                 fdmt_boxcar_t *out, void *ws, size_t ws_bytes, void *hip_stream);
 
 /* Static description of a status code. */
 const char *fdmt_status_string(fdmt_status_t s);

@@ -44,6 +44,14 @@ listed with its justification in the design notes):
   R-law  another delay law dt ~ f^gamma (Sec. 4.2, other functional forms)
          replaces the power -2 of Eq. (Cf2f0) by gamma and nothing else;
          f^gamma is the C library's pow (gamma = -2 keeps 1.0/(f*f)).
+  R-dmin a known smallest delay d_min (Sec. 4.2, different range of
+         dispersions) is applied as the frequency-dependent input shift the
+         paper names: channel k is delayed by pre_k = round_half_up(d_min *
+         phi(c_k)) samples (zero history), phi(f) = (f_min^g - f^g) /
+         (f_min^g - f_max^g) at the channel's centre c_k = (e_k + e_k+1)/2, so
+         the run a row adds in a channel is centred on the curve's passage
+         through it; row dt then follows total delay d_min + dt. The delay
+         tables themselves are unchanged.
 """
 from __future__ import annotations
 
@@ -99,20 +107,22 @@ class Tables:
     rows: list                  # rows[l][j]: number of dt rows of sub-band j at iteration l
     split: list                 # split[l][j][dt] = (d_lo, s, d_hi) for l >= 1
     gamma: float = -2.0         # delay law dt ~ f^gamma
+    pre: list = None            # per channel: the d_min pre-shift (reading R-dmin)
 
     @property
     def leaf_rows(self):
         return self.rows[0]
 
 
-def build_tables(nf, nd, f_min, f_max, gamma=-2.0):
+def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
     """Per iteration l = 1..log2(Nf) and sub-band j (channels j*2^l .. (j+1)*2^l - 1,
     f0 = e[j*2^l], f1 = e[(2j+1)*2^(l-1)], f2 = e[(j+1)*2^l]):
         for each dt: t0 - t1 = d_lo = round(C_{f2,f0} * dt)   (lower half's delay)
                      s = d_lo                                  (upper half's start shift)
                      t1 - t2 = d_hi = dt - d_lo                (upper half's delay)
     Row counts run top-down from Nd at the last iteration (reading R-rows).
-    gamma: the delay law dt ~ f^gamma (reading R-law)."""
+    gamma: the delay law dt ~ f^gamma (reading R-law). d_min: the smallest
+    delay searched (reading R-dmin), which sets the per-channel pre-shift."""
     if nf < 1 or nf & (nf - 1):
         raise ValueError("Nf must be a power of two")
     if nd < 1:
@@ -121,6 +131,8 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0):
         raise ValueError("need 0 < f_min < f_max")
     if not math.isfinite(gamma) or gamma == 0.0:
         raise ValueError("gamma must be finite and nonzero")
+    if d_min < 0:
+        raise ValueError("d_min must be >= 0")
     levels = nf.bit_length() - 1
     e = channel_edges(nf, f_min, f_max)
     rows = [None] * (levels + 1)
@@ -143,7 +155,14 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0):
             last = triples[-1]
             rows[l - 1][2 * j] = last[0] + 1
             rows[l - 1][2 * j + 1] = last[2] + 1
-    return Tables(nf, nd, f_min, f_max, levels, rows, split, float(gamma))
+    pre = [0] * nf
+    if d_min > 0:
+        den = _law(f_min, gamma) - _law(f_max, gamma)
+        for k in range(nf):
+            centre = 0.5 * (e[k] + e[k + 1])
+            phi = (_law(f_min, gamma) - _law(centre, gamma)) / den
+            pre[k] = round_half_up(float(d_min) * phi)
+    return Tables(nf, nd, f_min, f_max, levels, rows, split, float(gamma), pre)
 
 
 # ----------------------------------------------------------------------------
@@ -167,6 +186,13 @@ def initialize(img, tables, acc=None):
     nf, nt = img.shape
     acc = _acc_dtype(img, acc)
     x = img.astype(acc)
+    if any(tables.pre):
+        # reading R-dmin: channel k's input delayed by pre_k samples
+        xs = np.zeros_like(x)
+        for k, sh in enumerate(tables.pre):
+            if sh < nt:
+                xs[k, sh:] = x[k, : nt - sh]
+        x = xs
     planes = []
     for k in range(nf):
         n = tables.rows[0][k]
@@ -248,9 +274,11 @@ def fdmt_adjoint(grad, f_min, f_max, nf, tables=None, acc=None):
     out = np.zeros((nf, nt), dtype=acc)
     for k in range(nf):
         a_bar = planes[k]
+        sh = tables.pre[k]    # transpose of the R-dmin input delay
         for dt in range(tables.rows[0][k]):
-            for i in range(min(dt, nt - 1) + 1):
-                out[k, : nt - i] += a_bar[dt, i:]
+            for i in range(dt + 1):
+                if sh + i < nt:
+                    out[k, : nt - sh - i] += a_bar[dt, sh + i:]
     return out
 
 
@@ -261,7 +289,7 @@ def fdmt_adjoint(grad, f_min, f_max, nf, tables=None, acc=None):
 def path(tables, dt):
     """Descend the tables from output row dt to the channels. Returns per channel
     k the pair (sigma_k, delta_k): channel k contributes I[k][t0 - sigma_k - i]
-    for i = 0..delta_k."""
+    for i = 0..delta_k (sigma_k includes the channel's d_min pre-shift)."""
     nodes = [(0, dt)]
     for l in range(tables.levels, 0, -1):
         nxt = []
@@ -270,7 +298,7 @@ def path(tables, dt):
             nxt.append((sigma, d_lo))
             nxt.append((sigma + s, d_hi))
         nodes = nxt
-    return nodes
+    return [(sigma + pre, d) for (sigma, d), pre in zip(nodes, tables.pre)]
 
 
 def brute_point(img, tables, dt, t0):
@@ -317,3 +345,51 @@ def brute_ideal(img, f_min, f_max, nd, gamma=-2.0):
             if sh < nt:
                 out[dt, sh:] += img[k, : nt - sh].astype(acc)
     return out
+
+
+# ----------------------------------------------------------------------------
+# Boxcar search on the output (Sec. 4.2, pulse profile: a profile common to all
+# frequencies commutes with the transform, so several widths share one FDMT)
+# ----------------------------------------------------------------------------
+
+def boxcar_search(plane, max_log2, acc=None):
+    """For every row of plane[..., nd, nt] and width w = 2^j, j = 0..max_log2:
+    b_w[t] = y[t] + y[t-1] + ... + y[t-w+1] (y = 0 before t = 0), its largest
+    value and the first t where it occurs, its mean and population standard
+    deviation over t = 0..nt-1, and snr = (peak - mean) / stdev (0 if stdev is 0).
+
+    Default: b_w by that definition in float64. acc=np.float32: b_w in binary32
+    as the doubling tree b_2w[t] = b_w[t] + b_w[t-w] from b_1 = y, the exact
+    reference for a binary32 implementation of that tree. The statistics are
+    float64 in both modes. Returns a dict of arrays [..., max_log2 + 1, nd]."""
+    y = np.asarray(plane)
+    nt = y.shape[-1]
+    widths = [1 << j for j in range(max_log2 + 1)]
+    sums = []
+    if acc is None:
+        y64 = y.astype(np.float64)
+        for w in widths:
+            b = np.zeros_like(y64)
+            for i in range(min(w, nt)):
+                b[..., i:] += y64[..., : nt - i]
+            sums.append(b)
+    else:
+        b = y.astype(acc)
+        sums.append(b.copy())
+        for w in widths[:-1]:
+            nb = b.copy()
+            if w < nt:
+                nb[..., w:] = (b[..., w:] + b[..., : nt - w]).astype(acc)
+            b = nb
+            sums.append(b.copy())
+    out = {"peak": [], "t": [], "mean": [], "stdev": [], "snr": []}
+    for b in sums:
+        b64 = b.astype(np.float64)
+        t = np.argmax(b64, axis=-1)          # first maximum
+        peak = np.take_along_axis(b64, t[..., None], axis=-1)[..., 0]
+        mean = b64.sum(axis=-1) / nt
+        sd = np.sqrt(((b64 - mean[..., None]) ** 2).sum(axis=-1) / nt)
+        snr = np.where(sd > 0, (peak - mean) / np.where(sd > 0, sd, 1.0), 0.0)
+        for k, v in zip(("peak", "t", "mean", "stdev", "snr"), (peak, t, mean, sd, snr)):
+            out[k].append(v)
+    return {k: np.stack(v, axis=-2) for k, v in out.items()}

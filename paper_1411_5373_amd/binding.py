@@ -27,7 +27,8 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_plan_tables", "fdmt_plan_info", "fdmt_plan_destroy",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
-            "fdmt_ragged_destroy", "fdmt_status_string", "fdmt_last_error")
+            "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
+            "fdmt_status_string", "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
               "input_gather", "staged_gather", "adjoint_gather")
@@ -52,7 +53,7 @@ class _Options(ctypes.Structure):
                 ("stream_tiles", ctypes.c_int32), ("gather_rows", ctypes.c_int32),
                 ("adjoint_levels", ctypes.c_int32), ("adjoint_last_levels", ctypes.c_int32),
                 ("gather_vecs", ctypes.c_int32), ("adjoint_last_rows", ctypes.c_int32),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -114,6 +115,10 @@ def load():
     lib.fdmt_ragged_info.restype = ctypes.c_int
     lib.fdmt_ragged_destroy.argtypes = [vp]
     lib.fdmt_ragged_destroy.restype = ctypes.c_int
+    lib.fdmt_boxcar_workspace_bytes.argtypes = [i32, i32, i64, i32]
+    lib.fdmt_boxcar_workspace_bytes.restype = sz
+    lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
+    lib.fdmt_boxcar_search.restype = ctypes.c_int
     lib.fdmt_status_string.argtypes = [ctypes.c_int]
     lib.fdmt_status_string.restype = ctypes.c_char_p
     lib.fdmt_last_error.argtypes = []
@@ -142,14 +147,14 @@ def fdmt_last_error():
 def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0,
               first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
-              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0):
+              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
                    int(later_levels), int(tile), int(lds_kib), int(max_block_rows),
                    int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows),
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
-                   int(adjoint_last_rows), float(gamma))
+                   int(adjoint_last_rows), float(gamma), int(d_min))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -167,6 +172,15 @@ def fdmt_forward(plan, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
 def fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, batch, ws_ptr, ws_bytes, stream):
     _check(load().fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, int(batch), ws_ptr, int(ws_bytes),
                                stream), "fdmt_adjoint")
+
+
+def fdmt_boxcar_workspace_bytes(batch, nd, nt, max_log2):
+    return int(load().fdmt_boxcar_workspace_bytes(int(batch), int(nd), int(nt), int(max_log2)))
+
+
+def fdmt_boxcar_search(plane_ptr, batch, nd, nt, max_log2, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_boxcar_search(plane_ptr, int(batch), int(nd), int(nt), int(max_log2), out_ptr, ws_ptr,
+                                     int(ws_bytes), stream), "fdmt_boxcar_search")
 
 
 def fdmt_step_count(plan, adjoint=False):
@@ -265,14 +279,17 @@ class Plan:
     shaped [Nf][Nt] / [Nd][Nt], or with a leading batch dimension."""
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
-                 host_only=False, unfused=False, tuned=False, wide_planes=False, gamma=-2.0, **schedule):
-        """`gamma`: the delay law dt ~ f^gamma (-2: cold plasma). `schedule`:
+                 host_only=False, unfused=False, tuned=False, wide_planes=False, gamma=-2.0, d_min=0,
+                 **schedule):
+        """`gamma`: the delay law dt ~ f^gamma (-2: cold plasma). `d_min`: the
+        smallest delay searched (row dt is delay d_min + dt). `schedule`:
         fdmt_options_t schedule fields (first_kernel, first_levels, ...).
         tuned=True first takes the autotuner's stored options for this
         workload, if any; explicit schedule fields override them."""
         self.nf, self.nt, self.nd = int(nf), int(nt), int(nd)
         self.f_min, self.f_max = float(f_min), float(f_max)
         self.gamma = float(gamma)
+        self.d_min = int(d_min)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
         flags = ((FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0) |
                  (FDMT_PLAN_WIDE_PLANES if wide_planes else 0))
@@ -282,11 +299,14 @@ class Plan:
             from . import autotune
             self.tuned = autotune.lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=self.gamma)
             if self.tuned:
+                if self.d_min and self.tuned.get("first_kernel") in (1, 2):
+                    # the pre-shift needs the gather from the input
+                    self.tuned = dict(self.tuned, first_kernel=3)
                 schedule = dict(self.tuned, **schedule)
         self.options = dict(schedule)
         self.handle = None
         self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
-                                _TORCH_TO_CODE[acc_dtype], flags, gamma=self.gamma, **schedule)
+                                _TORCH_TO_CODE[acc_dtype], flags, gamma=self.gamma, d_min=self.d_min, **schedule)
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
@@ -440,3 +460,29 @@ class FDMTFunction(torch.autograd.Function):
 
 def fdmt(x, plan):
     return FDMTFunction.apply(x, plan)
+
+
+def boxcar_search(plane, max_log2=8, ws=None):
+    """Boxcar search over FDMT output planes ([Nd][Nt] or [B][Nd][Nt], FP32, on
+    the GPU): widths 2^0 .. 2^max_log2. Returns a dict of tensors shaped
+    [B][max_log2 + 1][Nd] (no B for a 2-D plane): peak, t (first time of the
+    peak), mean and stdev of each width's running sum, and snr =
+    (peak - mean) / stdev (0 where stdev is 0), all from fdmt_boxcar_search."""
+    if plane.dtype != torch.float32 or plane.device.type != "cuda":
+        raise TypeError("plane must be a float32 CUDA tensor")
+    squeeze = plane.dim() == 2
+    x = (plane.unsqueeze(0) if squeeze else plane).contiguous()
+    if x.dim() != 3:
+        raise ValueError("plane must be [Nd][Nt] or [B][Nd][Nt]")
+    b, nd, nt = x.shape
+    out = torch.empty((b, max_log2 + 1, nd, 5), dtype=torch.int32, device=x.device)
+    need = fdmt_boxcar_workspace_bytes(b, nd, nt, max_log2)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    fdmt_boxcar_search(ctypes.c_void_p(x.data_ptr()), b, nd, nt, max_log2, ctypes.c_void_p(out.data_ptr()),
+                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(x.device))
+    f = out.view(torch.float32)
+    res = {"peak": f[..., 0], "t": out[..., 1], "mean": f[..., 2], "stdev": f[..., 3], "snr": f[..., 4]}
+    if squeeze:
+        res = {k: v[0] for k, v in res.items()}
+    return res

@@ -27,7 +27,8 @@ HIP_FLAGS = [
 ]
 CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
-HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_gather.hip", "fdmt_narrow.hip", "fdmt_adjoint.hip", "fdmt_api.hip"]
+HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_gather.hip", "fdmt_narrow.hip", "fdmt_adjoint.hip", "fdmt_boxcar.hip",
+               "fdmt_api.hip"]
 CXX_SOURCES = ["fdmt_tables.cpp", "fdmt_schedule.cpp"]
 
 

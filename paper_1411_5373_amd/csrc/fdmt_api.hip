@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/fdmt.h"
+#include "fdmt_boxcar.h"
 #include "fdmt_plan.h"
 
 struct fdmt_plan_s {
@@ -56,6 +57,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   const size_t off_leaf_off = reserve(T.leaf_off.size() * sizeof(int32_t));
   const size_t off_leaf_rows = reserve(T.leaf_rows.size() * sizeof(int32_t));
+  const size_t off_pre = reserve(T.pre.size() * sizeof(int32_t));
   const size_t off_recs = reserve(p.fwd.recs.size() * sizeof(fdmt::Rec));
   const size_t off_heads = reserve(p.fwd.heads.size() * sizeof(int32_t));
   const size_t off_terms = reserve(p.fwd.terms.size() * sizeof(fdmt::Term));
@@ -75,6 +77,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   std::memcpy(host.data() + off_leaf_off, T.leaf_off.data(), T.leaf_off.size() * sizeof(int32_t));
   std::memcpy(host.data() + off_leaf_rows, T.leaf_rows.data(), T.leaf_rows.size() * sizeof(int32_t));
+  std::memcpy(host.data() + off_pre, T.pre.data(), T.pre.size() * sizeof(int32_t));
   if (!p.fwd.recs.empty())
     std::memcpy(host.data() + off_recs, p.fwd.recs.data(), p.fwd.recs.size() * sizeof(fdmt::Rec));
   if (!p.fwd.heads.empty())
@@ -114,6 +117,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   }
   p.dev.leaf_off = reinterpret_cast<const int32_t *>(base + off_leaf_off);
   p.dev.leaf_rows = reinterpret_cast<const int32_t *>(base + off_leaf_rows);
+  p.dev.pre = reinterpret_cast<const int32_t *>(base + off_pre);
   p.dev_recs = reinterpret_cast<const fdmt::Rec *>(base + off_recs);
   p.dev_heads = reinterpret_cast<const int32_t *>(base + off_heads);
   p.dev_terms = reinterpret_cast<const int2 *>(base + off_terms);
@@ -204,6 +208,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
   if (o.adjoint_last_rows < 0 || o.adjoint_last_rows > 16 || (o.adjoint_last_rows & (o.adjoint_last_rows - 1)))
     return fail(FDMT_E_INVALID, "adjoint_last_rows must be 1, 2, 4, 8 or 16");
+  if (o.d_min < 0) return fail(FDMT_E_INVALID, "d_min must be >= 0");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES))
@@ -215,7 +220,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (!h) return fail(FDMT_E_NOMEM, "host allocation of the plan failed");
   fdmt::Plan &p = h->plan;
   try {
-    const std::string err = fdmt::build_tables(p.tab, nf, nd, f_min, f_max, o.gamma != 0.0 ? o.gamma : -2.0);
+    const std::string err =
+        fdmt::build_tables(p.tab, nf, nd, f_min, f_max, o.gamma != 0.0 ? o.gamma : -2.0, o.d_min);
     if (!err.empty()) {
       delete h;
       return fail(FDMT_E_INVALID, err);
@@ -250,6 +256,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     static const fdmt::PassKind kinds[] = {fdmt::PassKind::Staged, fdmt::PassKind::Staged,
                                            fdmt::PassKind::Recursive, fdmt::PassKind::Register};
     if (o.first_kernel) sp.first_kind = kinds[o.first_kernel];
+    // the d_min pre-shift rides on the input terms of a gather from the input
+    else if (o.d_min > 0) sp.first_kind = fdmt::PassKind::Register;
     if (o.later_kernel) sp.later_kind = kinds[o.later_kernel];
     try {
       const std::string err = fdmt::build_schedule(p.fwd, p.tab, sp);
@@ -667,6 +675,34 @@ fdmt_status_t fdmt_ragged_destroy(fdmt_ragged_t r) {
   }
   delete r;
   return s;
+}
+
+namespace {
+
+bool boxcar_sizes_ok(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2) {
+  return batch >= 1 && batch <= 65535 && nd >= 1 && nd <= 65535 && nt >= 1 && nt <= INT32_MAX && max_log2 >= 0 &&
+         max_log2 <= fdmt::kBoxMaxLog2;
+}
+
+} // namespace
+
+size_t fdmt_boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2) {
+  return boxcar_sizes_ok(batch, nd, nt, max_log2) ? fdmt::boxcar_workspace_bytes(batch, nd, nt, max_log2) : 0;
+}
+
+fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                                 fdmt_boxcar_t *out, void *ws, size_t ws_bytes, void *hip_stream) {
+  if (!plane || !out || !ws) return fail(FDMT_E_INVALID, "plane, out or workspace is NULL");
+  if (!boxcar_sizes_ok(batch, nd, nt, max_log2))
+    return fail(FDMT_E_INVALID, "need batch, nd in [1, 65535], nt in [1, 2^31 - 1], max_log2 in [0, 10]");
+  const size_t need = fdmt::boxcar_workspace_bytes(batch, nd, nt, max_log2);
+  if (ws_bytes < need)
+    return fail(FDMT_E_WORKSPACE, "boxcar workspace needs " + std::to_string(need) + " bytes, got " +
+                                      std::to_string(ws_bytes));
+  const hipError_t e =
+      fdmt::launch_boxcar(plane, batch, nd, nt, max_log2, out, ws, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "boxcar search launch");
+  return FDMT_OK;
 }
 
 const char *fdmt_status_string(fdmt_status_t s) {

@@ -1,0 +1,30 @@
+// Boxcar search over FDMT output planes (device side, fdmt_boxcar.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/fdmt.h"
+
+namespace fdmt {
+
+constexpr int kBoxTile = 4096;   // samples of one row per workgroup
+constexpr int kBoxMaxLog2 = 10;  // widths up to 2^10 samples
+
+// Statistics of one width over one tile of one row.
+struct BoxPartial {
+  double sum, sumsq;  // of b_w over the tile's samples
+  float peak;         // largest b_w
+  int32_t t;          // first time of it
+};
+
+size_t boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2);
+
+// plane: device [batch][nd][nt] FP32; out: device [batch][max_log2 + 1][nd];
+// ws: boxcar_workspace_bytes() of device memory.
+hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                         fdmt_boxcar_t *out, void *ws, hipStream_t stream);
+
+} // namespace fdmt

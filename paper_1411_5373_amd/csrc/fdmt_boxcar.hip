@@ -1,0 +1,176 @@
+// Boxcar search over FDMT output planes: for every row (trial delay) and
+// width w = 2^j, the causal running sum b_w[t] = y[t] + ... + y[t - w + 1]
+// (zero before the record), its largest value with the first time it occurs,
+// and the mean and standard deviation of b_w over the record. A pulse
+// profile shared by all frequencies commutes with the transform (Sec. 4.2,
+// pulse profile), so one transform serves every width.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fdmt_boxcar.h"
+
+namespace fdmt {
+
+namespace {
+
+constexpr int kBoxThreads = 256;
+constexpr int kBoxPerThread = kBoxTile / kBoxThreads;
+constexpr int kBoxHaloMax = (1 << kBoxMaxLog2) - 1;
+
+// Peak order: larger value first, then earlier time.
+__device__ __forceinline__ bool better(float v, int t, float bv, int bt) { return v > bv || (v == bv && t < bt); }
+
+template <typename T>
+__device__ __forceinline__ T xor_lane(T x, int mask) {
+  return __shfl_xor(x, mask, 64);
+}
+
+// One workgroup: one row, one tile of kBoxTile samples plus the w_max - 1
+// samples before it. Width 2w is built in LDS from width w as
+// b_2w[t] = b_w[t] + b_w[t - w], which sums each window in a fixed tree; each
+// level's tile samples then add to the partial statistics of that width.
+__global__ __launch_bounds__(kBoxThreads) void boxcar_tile_kernel(const float *__restrict__ plane,
+                                                                  BoxPartial *__restrict__ part, int64_t nt,
+                                                                  int32_t nd, int32_t ntiles, int32_t max_log2) {
+  __shared__ float buf[kBoxTile + kBoxHaloMax];
+  __shared__ double red_sum[kBoxThreads / 64], red_sq[kBoxThreads / 64];
+  __shared__ float red_max[kBoxThreads / 64];
+  __shared__ int red_t[kBoxThreads / 64];
+  const int tile = blockIdx.x, row = blockIdx.y, b = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int halo = (1 << max_log2) - 1;
+  const int64_t t0 = static_cast<int64_t>(tile) * kBoxTile;  // first sample of the tile
+  const int64_t left = nt - t0;
+  const int nvalid = left < kBoxTile ? static_cast<int>(left) : kBoxTile;
+  const float *y = plane + (static_cast<int64_t>(b) * nd + row) * nt;
+  // local index i holds time t0 - halo + i
+  for (int i = tid; i < halo + nvalid; i += kBoxThreads) {
+    const int64_t t = t0 - halo + i;
+    buf[i] = t >= 0 ? y[t] : 0.0f;
+  }
+  __syncthreads();
+  for (int j = 0; j <= max_log2; ++j) {
+    if (j > 0) {
+      // width 2^j from width w = 2^(j-1); valid from local index 2^j - 1 on,
+      // which covers every index a later width or the statistics read
+      const int w = 1 << (j - 1);
+      const int first = (1 << j) - 1 + tid, end = halo + nvalid;
+      constexpr int kSlots = (kBoxTile + kBoxHaloMax + kBoxThreads - 1) / kBoxThreads;
+      float nv[kSlots];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = first + k * kBoxThreads;
+        if (i < end) nv[k] = buf[i] + buf[i - w];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = first + k * kBoxThreads;
+        if (i < end) buf[i] = nv[k];
+      }
+      __syncthreads();
+    }
+    double s = 0.0, q = 0.0;
+    float best = -__builtin_inff();
+    int best_t = INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < kBoxPerThread; ++k) {
+      const int i = tid + k * kBoxThreads;
+      if (i < nvalid) {
+        const float v = buf[halo + i];
+        s += static_cast<double>(v);
+        q += static_cast<double>(v) * static_cast<double>(v);
+        if (better(v, i, best, best_t)) {
+          best = v;
+          best_t = i;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      s += xor_lane(s, m);
+      q += xor_lane(q, m);
+      const float ov = xor_lane(best, m);
+      const int ot = xor_lane(best_t, m);
+      if (better(ov, ot, best, best_t)) {
+        best = ov;
+        best_t = ot;
+      }
+    }
+    if (lane == 0) {
+      red_sum[wave] = s;
+      red_sq[wave] = q;
+      red_max[wave] = best;
+      red_t[wave] = best_t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int v = 1; v < kBoxThreads / 64; ++v) {
+        s += red_sum[v];
+        q += red_sq[v];
+        if (better(red_max[v], red_t[v], best, best_t)) {
+          best = red_max[v];
+          best_t = red_t[v];
+        }
+      }
+      BoxPartial &p = part[((static_cast<int64_t>(b) * (max_log2 + 1) + j) * nd + row) * ntiles + tile];
+      p.sum = s;
+      p.sumsq = q;
+      p.peak = best;
+      p.t = static_cast<int32_t>(t0) + best_t;
+    }
+    __syncthreads();
+  }
+}
+
+// One thread per (beam, width, row): the tiles' partials in time order.
+__global__ __launch_bounds__(256) void boxcar_combine_kernel(const BoxPartial *__restrict__ part,
+                                                             fdmt_boxcar_t *__restrict__ out, int64_t nt,
+                                                             int32_t ntiles, int64_t count) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const BoxPartial *p = part + k * ntiles;
+  double s = 0.0, q = 0.0;
+  float best = -__builtin_inff();
+  int best_t = INT32_MAX;
+  for (int i = 0; i < ntiles; ++i) {
+    s += p[i].sum;
+    q += p[i].sumsq;
+    if (better(p[i].peak, p[i].t, best, best_t)) {
+      best = p[i].peak;
+      best_t = p[i].t;
+    }
+  }
+  const double mean = s / static_cast<double>(nt);
+  const double var = q / static_cast<double>(nt) - mean * mean;
+  const double sd = var > 0.0 ? sqrt(var) : 0.0;
+  fdmt_boxcar_t r;
+  r.peak = best;
+  r.t = best_t;
+  r.mean = static_cast<float>(mean);
+  r.stdev = static_cast<float>(sd);
+  r.snr = sd > 0.0 ? static_cast<float>((static_cast<double>(best) - mean) / sd) : 0.0f;
+  out[k] = r;
+}
+
+} // namespace
+
+size_t boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2) {
+  const int64_t ntiles = (nt + kBoxTile - 1) / kBoxTile;
+  return static_cast<size_t>(batch) * (max_log2 + 1) * nd * ntiles * sizeof(BoxPartial);
+}
+
+hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                         fdmt_boxcar_t *out, void *ws, hipStream_t stream) {
+  const int64_t ntiles = (nt + kBoxTile - 1) / kBoxTile;
+  BoxPartial *part = static_cast<BoxPartial *>(ws);
+  hipLaunchKernelGGL(boxcar_tile_kernel, dim3(static_cast<unsigned>(ntiles), nd, batch), dim3(kBoxThreads), 0,
+                     stream, plane, part, nt, nd, static_cast<int32_t>(ntiles), max_log2);
+  const int64_t count = static_cast<int64_t>(batch) * (max_log2 + 1) * nd;
+  hipLaunchKernelGGL(boxcar_combine_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, stream,
+                     part, out, nt, static_cast<int32_t>(ntiles), count);
+  return hipGetLastError();
+}
+
+} // namespace fdmt

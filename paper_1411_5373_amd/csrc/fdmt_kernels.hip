@@ -29,11 +29,13 @@ constexpr int kTile = kThreads * kPerThread;  // samples per workgroup
 template <typename Tin, typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void init_kernel(
     const Tin *__restrict__ in, Tacc *__restrict__ out, const int32_t *__restrict__ leaf_off,
-    const int32_t *__restrict__ leaf_rows, int64_t nt_u, int64_t in_bstride, int64_t out_stride_u,
-    int64_t out_bstride, RaggedMap rg) {
+    const int32_t *__restrict__ leaf_rows, const int32_t *__restrict__ pre, int64_t nt_u, int64_t in_bstride,
+    int64_t out_stride_u, int64_t out_bstride, RaggedMap rg) {
   const int k = blockIdx.x;
   const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), nt_u, in_bstride, out_stride_u, out_bstride);
   const int64_t nt = bs.nt, out_stride = bs.dst_stride;
+  // channel k's input delayed by its pre-shift: sample t reads x[t - pre]
+  const int64_t sh = pre[k];
   const Tin *x = in + bs.src_off + static_cast<int64_t>(k) * nt;
   Tacc *o = out + bs.dst_off + static_cast<int64_t>(leaf_off[k]) * out_stride;
   const int n = leaf_rows[k];
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void init_kernel(
     if (t >= nt) break;
     Tacc acc = 0;
     for (int d = 0; d < n; ++d) {
-      if (t - d >= 0) acc += widen<Tacc>(x[t - d]);
+      if (t - sh - d >= 0) acc += widen<Tacc>(x[t - sh - d]);
       o[d * out_stride + t] = acc;
     }
   }
@@ -106,11 +108,12 @@ __global__ __launch_bounds__(kThreads) void merge_adjoint_kernel(
 template <typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void init_adjoint_kernel(
     const Tacc *__restrict__ plane, Tacc *__restrict__ out, const int32_t *__restrict__ leaf_off,
-    const int32_t *__restrict__ leaf_rows, int64_t nt_u, int64_t plane_stride_u,
+    const int32_t *__restrict__ leaf_rows, const int32_t *__restrict__ pre, int64_t nt_u, int64_t plane_stride_u,
     int64_t plane_bstride, int64_t out_bstride, RaggedMap rg) {
   const int k = blockIdx.x;
   const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), plane_stride_u, plane_bstride, nt_u, out_bstride);
   const int64_t nt = bs.nt, plane_stride = bs.src_stride;
+  const int64_t sh = pre[k];  // transpose of the pre-shift: reads t + pre
   const Tacc *g = plane + bs.src_off + static_cast<int64_t>(leaf_off[k]) * plane_stride;
   Tacc *o = out + bs.dst_off + static_cast<int64_t>(k) * nt;
   const int n = leaf_rows[k];
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void init_adjoint_kernel(
     Tacc acc = 0;
     for (int d = 0; d < n; ++d)
       for (int j = 0; j <= d; ++j)
-        if (t + j < nt) acc += g[d * plane_stride + t + j];
+        if (t + sh + j < nt) acc += g[d * plane_stride + t + sh + j];
     o[t] = acc;
   }
 }
@@ -613,7 +616,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
       return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0, stream,
                            static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                           p.dev.leaf_off, p.dev.leaf_rows, nt, src.bstride, dst.stride, dst.bstride, rg);
+                           p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, nt, src.bstride, dst.stride, dst.bstride, rg);
         return hipSuccess;
       });
     case Step::Merge:
@@ -802,7 +805,7 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       return for_each_launch(p, rb, st, true, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         hipLaunchKernelGGL((init_adjoint_kernel<Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0,
                            stream, static_cast<const Tacc *>(src.ptr), static_cast<Tacc *>(dst.ptr),
-                           p.dev.leaf_off, p.dev.leaf_rows, nt, src.stride, src.bstride, dst.bstride, rg);
+                           p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, nt, src.stride, src.bstride, dst.bstride, rg);
         return hipSuccess;
       });
     default: return hipErrorInvalidValue;

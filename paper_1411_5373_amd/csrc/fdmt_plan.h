@@ -22,6 +22,7 @@ struct DeviceTables {
   const int4 *adj[32] = {};       // per iteration l >= 1: AdjRow per row of plane l - 1
   const int32_t *leaf_off = nullptr;
   const int32_t *leaf_rows = nullptr;
+  const int32_t *pre = nullptr;   // per channel: d_min pre-shift
 };
 
 // Where a step reads or writes: the caller's input/output or one of the two

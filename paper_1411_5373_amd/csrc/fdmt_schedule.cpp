@@ -327,6 +327,12 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
   {
     const bool first = from_input;
     const PassKind kind = first ? p.first_kind : p.later_kind;
+    // The d_min pre-shift enters through the input terms of a register pass
+    // (and the initialisation kernels); passes that stage input rows in LDS do
+    // not apply it.
+    if (first && kind != PassKind::Register)
+      for (int32_t x : t.pre)
+        if (x != 0) return "the d_min pre-shift needs the first pass to gather from the input";
     if (kind == PassKind::Staged) {
       const int k = std::min(k_req, L - l0);
       if (k > 5) return "at most 5 iterations per staged pass";
@@ -438,7 +444,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
           for (const Term &x : cur) {
             const int ch = channel_of[x.row];
             const int d = x.row - t.leaf_off[ch];
-            s.iterms.push_back(InTerm{ch, x.shift, d, 0});
+            s.iterms.push_back(InTerm{ch, x.shift + t.pre[ch], d, 0});
             ps.staged_rows += d + 1;
           }
         } else {
@@ -612,18 +618,20 @@ std::string build_adjoint_schedule(AdjSchedule &s, const Tables &t, int levels_p
     for (int r = 0; r < ps.nrows; ++r) {
       AdjWalker w{t, l_hi, per_row[r]};
       if (ps.lagged) {
-        // channel r: the subtree of each partial-sum row d once, at lag 0,
-        // its first leaf carrying the d + 1 lags it is added at
+        // channel r: the subtree of each partial-sum row d once, at lag 0
+        // (plus the channel's pre-shift), its first leaf carrying the d + 1
+        // lags it is added at
         for (int d = 0; d < t.leaf_rows[r]; ++d) {
           const size_t first = per_row[r].size();
-          w.visit(0, t.leaf_off[r] + d, 0, 1, 0);
+          w.visit(0, t.leaf_off[r] + d, t.pre[r], 1, 0);
           per_row[r][first].lags = (d + 1) | static_cast<int32_t>(per_row[r].size() - first) << 3;
         }
       } else if (ps.to_input) {
-        // channel r: partial-sum rows d at lags i, in (d, i) order; each starts
-        // a new child of the root (branch depth 0)
+        // channel r: partial-sum rows d at lags i (plus the channel's
+        // pre-shift), in (d, i) order; each starts a new child of the root
+        // (branch depth 0)
         for (int d = 0; d < t.leaf_rows[r]; ++d)
-          for (int i = 0; i <= d; ++i) w.visit(0, t.leaf_off[r] + d, i, 1, 0);
+          for (int i = 0; i <= d; ++i) w.visit(0, t.leaf_off[r] + d, t.pre[r] + i, 1, 0);
       } else {
         w.visit(ps.l_lo, r, 0, 0, 0);
       }

@@ -11,6 +11,13 @@
 //
 // Other delay laws dt ~ f^gamma (Sec. 4.2, other functional forms) change
 // only C: the power -2 of Eq. (Cf2f0) becomes gamma.
+//
+// A known smallest delay d_min (Sec. 4.2, different range of dispersions) is
+// a frequency-dependent shift of the input: channel k is delayed by
+// pre_k = round(d_min * phi(c_k)) samples, phi(f) = (f_min^g - f^g) /
+// (f_min^g - f_max^g) the fraction of the band delay reached at its centre
+// c_k, after which output row dt follows total delay d_min + dt (the run a
+// row adds in channel k is then centred on the curve's passage through it).
 #include "fdmt_tables.h"
 
 #include <cmath>
@@ -34,12 +41,13 @@ int32_t round_half_up(double x) { return static_cast<int32_t>(std::floor(x + 0.5
 
 } // namespace
 
-std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma) {
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma, int d_min) {
   if (nf < 1 || (nf & (nf - 1)) != 0) return "Nf must be a power of two";
   if (nd < 1) return "Nd must be >= 1";
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
     return "need 0 < f_min < f_max (finite)";
   if (!std::isfinite(gamma) || gamma == 0.0) return "the delay law's power must be finite and nonzero";
+  if (d_min < 0) return "d_min must be >= 0";
   int levels = 0;
   while ((1 << levels) < nf) ++levels;
 
@@ -50,6 +58,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   t.f_min = f_min;
   t.f_max = f_max;
   t.gamma = gamma;
+  t.d_min = d_min;
 
   const double df = (f_max - f_min) / nf;
   std::vector<double> edge(nf + 1);
@@ -148,6 +157,16 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   for (int k = 0; k < nf; ++k) {
     t.leaf_off[k] = static_cast<int32_t>(t.row_off[0][k]);
     t.leaf_rows[k] = t.rows[0][k];
+  }
+  t.pre.assign(nf, 0);
+  if (d_min > 0) {
+    const double den = law(f_min, gamma) - law(f_max, gamma);
+    for (int k = 0; k < nf; ++k) {
+      const double centre = 0.5 * (edge[k] + edge[k + 1]);
+      const double phi = (law(f_min, gamma) - law(centre, gamma)) / den;
+      t.pre[k] = round_half_up(static_cast<double>(d_min) * phi);
+      if (t.pre[k] < 0 || t.pre[k] > d_min) return "pre-shift outside [0, d_min]";
+    }
   }
   return "";
 }

@@ -26,6 +26,7 @@ struct Tables {
   int nf = 0, nd = 0, levels = 0;
   double f_min = 0, f_max = 0;
   double gamma = -2.0;  // delay law dt ~ f^gamma
+  int32_t d_min = 0;    // smallest total delay searched; row dt is delay d_min + dt
   // rows[l][j]: dt rows of sub-band j after iteration l (l = 0: channel j's
   // Option-1 partial sums; l = levels: the single output sub-band, nd rows).
   std::vector<std::vector<int32_t>> rows;
@@ -41,10 +42,15 @@ struct Tables {
   std::vector<std::vector<AdjRow>> adj;
   // per channel: first row of its partial sums in plane 0 and their count
   std::vector<int32_t> leaf_off, leaf_rows;
+  // per channel: the d_min pre-shift, the samples its input is delayed by
+  // before the transform (all 0 when d_min = 0)
+  std::vector<int32_t> pre;
 };
 
-// Builds every table for the delay law dt ~ f^gamma (-2: cold plasma).
-// Returns "" on success or a description of the problem.
-std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma = -2.0);
+// Builds every table for the delay law dt ~ f^gamma (-2: cold plasma) and the
+// pre-shift for delays from d_min on. Returns "" on success or a description
+// of the problem.
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma = -2.0,
+                         int d_min = 0);
 
 } // namespace fdmt

@@ -77,6 +77,39 @@ def test_power_law_tables_match_oracle(gamma, nf, nd, band):
         assert e.value.status == B.FDMT_E_INVALID
 
 
+def test_dmin_plan_rules():
+    """d_min >= 0; the pre-shift needs the first pass to gather from the
+    input, which a d_min plan picks by default; LDS first passes are refused."""
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=-1)
+    assert e.value.status == B.FDMT_E_INVALID
+    p = F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=500)
+    assert p.steps()[0]["kind"] == B.STEP_KINDS[6]      # gather from the input
+    for fk in (1, 2):
+        with pytest.raises(F.FDMTError) as e:
+            F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=500, first_kernel=fk)
+        assert e.value.status == B.FDMT_E_UNSUPPORTED and "d_min" in F.fdmt_last_error()
+    F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=500, unfused=True)
+    F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=0, first_kernel=2)
+
+
+def test_boxcar_argument_errors_before_launch():
+    """fdmt_boxcar_search validates pointers, sizes and the workspace before
+    it touches the device."""
+    lib = B.load()
+    x, o, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    need = F.fdmt_boxcar_workspace_bytes(2, 8, 10000, 5)
+    assert need == 2 * 6 * 8 * 3 * 24
+    for args in [(1, 0, 100, 3), (0, 4, 100, 3), (1, 4, 0, 3), (1, 4, 100, 11), (1, 4, 100, -1),
+                 (1, 70000, 100, 3)]:
+        assert F.fdmt_boxcar_workspace_bytes(*args) == 0
+        assert lib.fdmt_boxcar_search(x, *args, o, ws, 1 << 30, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_boxcar_search(None, 2, 8, 10000, 5, o, ws, need, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_boxcar_search(x, 2, 8, 10000, 5, o, None, need, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_boxcar_search(x, 2, 8, 10000, 5, o, ws, need - 1, None) == B.FDMT_E_WORKSPACE
+    assert "workspace" in F.fdmt_last_error()
+
+
 def test_random_bands_match_oracle():
     import numpy as np
     rng = np.random.default_rng(99)

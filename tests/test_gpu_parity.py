@@ -332,6 +332,28 @@ def test_power_law_forward_and_adjoint(gamma, sched):
     np.testing.assert_array_equal(xb, oadj(g, *band, nf, tab, acc=np.float32))
 
 
+@pytest.mark.parametrize("nf,nt,nd,band,d_min", [(256, 3001, 300, (1.2, 1.6), 700), (64, 1030, 100, (0.4, 0.8), 2500),
+                                                 (2, 500, 1999, (0.4, 0.8), 333), (1024, 4000, 256, (1.2, 1.6), 1500)])
+@pytest.mark.parametrize("sched", [dict(), dict(first_levels=3, later_levels=3, gather_vecs=4, adjoint_levels=3,
+                                                adjoint_last_levels=3, adjoint_last_rows=8), dict(unfused=True)])
+def test_dmin_forward_and_adjoint(nf, nt, nd, band, d_min, sched):
+    """The d_min pre-shift (Sec. 4.2, different range of dispersions) rides on
+    the input terms and the initialisation kernels: uint8 forward exact against
+    the int64 oracle with the same pre-shift, FP32 adjoint bit-exact against its
+    binary32 evaluation."""
+    print(f"d_min {d_min} nf={nf} nt={nt} nd={nd} {sched}", flush=True)
+    tab = build_tables(nf, nd, *band, d_min=d_min)
+    assert any(tab.pre)
+    x = W.random_input((nf, nt), np.uint8, seed=d_min + nf)
+    p = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, d_min=d_min, **sched)
+    y = p.forward(_dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(y.astype(np.int64), ofdmt(x.astype(np.int64), *band, nd, tab))
+    g = W.random_input((nd, nt), np.float32, seed=d_min + nd)
+    pf = F.Plan(nf, nt, nd, *band, d_min=d_min, **sched)
+    xb = pf.adjoint(_dev(g)).cpu().numpy()
+    np.testing.assert_array_equal(xb, oadj(g, *band, nf, tab, acc=np.float32))
+
+
 ADJOINT_SCHEDULES = [
     dict(adjoint_levels=1, adjoint_last_levels=1),
     dict(adjoint_levels=2, adjoint_last_levels=1, gather_rows=4),

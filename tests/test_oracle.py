@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import read_golden
-from oracle import (brute_ideal, brute_point, brute_row, build_tables, fdmt,
+from oracle import (boxcar_search, brute_ideal, brute_point, brute_row, build_tables, fdmt,
                     fdmt_adjoint, path)
 import workloads as W
 
@@ -384,3 +384,138 @@ def test_binary32_mode_within_rounding_bound():
     ref_a = fdmt_adjoint(g.astype(np.float64), 0.4, 0.8, 128)
     got_a = fdmt_adjoint(g, 0.4, 0.8, 128, acc=np.float32)
     assert np.all(np.abs(got_a - ref_a) <= adjoint_bound(g, 0.4, 0.8, 128))
+
+
+# ---------------------------------------------------------------- boxcar search
+
+def test_boxcar_impulse_closed_form():
+    """One impulse A at (row r, t0) of a zero plane: b_w is A on
+    [t0, t0 + w - 1] and 0 elsewhere, so the peak is A first at t0, the mean
+    A*n/Nt and the variance A^2*n/Nt - mean^2, n = min(w, Nt - t0); other rows
+    are all zero (stdev 0, snr 0)."""
+    nd, nt, t0, amp, m = 3, 50, 40, 3.0, 5
+    y = np.zeros((nd, nt))
+    y[1, t0] = amp
+    res = boxcar_search(y, m)
+    for j in range(m + 1):
+        n = min(1 << j, nt - t0)
+        mean = amp * n / nt
+        assert res["peak"][j, 1] == amp and res["t"][j, 1] == t0
+        assert math.isclose(res["mean"][j, 1], mean, rel_tol=1e-12)
+        assert math.isclose(res["stdev"][j, 1], math.sqrt(amp * amp * n / nt - mean * mean), rel_tol=1e-12)
+        assert res["peak"][j, 0] == 0 and res["t"][j, 0] == 0 and res["stdev"][j, 0] == 0 and res["snr"][j, 0] == 0
+
+
+def test_boxcar_constant_row_closed_form():
+    """A constant c: b_w[t] = c * min(t + 1, w), so the peak c*min(w, Nt) first
+    reached at t = min(w, Nt) - 1, and the mean c/Nt * sum_t min(t + 1, w)."""
+    c, nt, m = 2.0, 37, 6
+    res = boxcar_search(np.full((1, nt), c), m)
+    for j in range(m + 1):
+        w = 1 << j
+        assert res["peak"][j, 0] == c * min(w, nt) and res["t"][j, 0] == min(w, nt) - 1
+        ramp = [c * min(t + 1, w) for t in range(nt)]
+        assert math.isclose(res["mean"][j, 0], sum(ramp) / nt, rel_tol=1e-12)
+
+
+def test_boxcar_commutes_with_transform():
+    """Sec. 4.2: a pulse profile shared by all frequencies commutes with the
+    FDMT. The oracle's width-w boxcar of the transform equals the transform of
+    the input boxcar-filtered per channel (causal, zero history), exactly on
+    integers; and the binary32 tree equals it on small integers."""
+    nf, nt, nd, band, m = 16, 300, 24, (1.2, 1.6), 4
+    x = _rng(5).integers(0, 20, size=(nf, nt)).astype(np.int64)
+    y = fdmt(x, *band, nd)
+    res = boxcar_search(y, m)
+    res32 = boxcar_search(y.astype(np.float32), m, acc=np.float32)
+    for j in range(m + 1):
+        w = 1 << j
+        xw = np.zeros_like(x)
+        for i in range(w):
+            xw[:, i:] += x[:, : nt - i]
+        yw = fdmt(xw, *band, nd)
+        np.testing.assert_array_equal(res["peak"][j], yw.max(axis=1))
+        np.testing.assert_array_equal(res["t"][j], yw.argmax(axis=1))
+        np.testing.assert_allclose(res["mean"][j], yw.mean(axis=1), rtol=1e-12)
+        np.testing.assert_allclose(res["stdev"][j], yw.std(axis=1), rtol=1e-12)
+        for k in ("peak", "t"):
+            np.testing.assert_array_equal(res32[k][j], res[k][j])
+
+
+def test_boxcar_binary32_tree_within_rounding():
+    """On Gaussian data the binary32 tree's b_w differs from the float64
+    definition by at most j rounding steps of its magnitude (the tree adds
+    each window in j levels), so the peaks agree to ~j * 2^-24 relative."""
+    y = _rng(6).standard_normal((4, 500)).astype(np.float32)
+    m = 6
+    r64 = boxcar_search(y, m)
+    r32 = boxcar_search(y, m, acc=np.float32)
+    for j in range(m + 1):
+        bound = (j + 1) * 2.0 ** -24 * (1 << j) * np.abs(y).max()
+        assert np.all(np.abs(r32["peak"][j] - r64["peak"][j]) <= bound)
+
+
+# ---------------------------------------------------------------- d_min pre-shift
+
+@pytest.mark.parametrize("nf,nd,d_min", [(16, 40, 100), (256, 128, 700), (1024, 256, 3000)])
+@pytest.mark.parametrize("band", [(1.2, 1.6), (0.4, 0.8)])
+def test_dmin_path_follows_law_from_dmin(nf, nd, d_min, band):
+    """Sec. 4.2 (different range of dispersions): with the pre-shift, row dt
+    follows total delay d_min + dt. The run channel k adds, [sigma_k,
+    sigma_k + delta_k], is centred within (log2(Nf) + 1)/2 samples (+ the
+    law's curvature over half a channel) of where the curve of delay
+    d_min + dt crosses the channel, (d_min + dt) * (phi(e_k) + phi(e_k+1))/2:
+    the path's own bound plus the pre-shift's rounding."""
+    f_min, f_max = band
+    t = build_tables(nf, nd, f_min, f_max, d_min=d_min)
+    e = np.array([f_min + k * (f_max - f_min) / nf for k in range(nf + 1)])
+    phi = (f_min ** -2 - e ** -2) / (f_min ** -2 - f_max ** -2)
+    mid = 0.5 * (phi[:-1] + phi[1:])
+    phic = (f_min ** -2 - (0.5 * (e[:-1] + e[1:])) ** -2) / (f_min ** -2 - f_max ** -2)
+    assert 0 <= min(t.pre) and max(t.pre) <= d_min
+    curv = d_min * np.max(np.abs(phic - mid))
+    bound = 0.5 * (t.levels + 1) + curv + 1e-9
+    for dt in list(range(0, nd, max(1, nd // 31))) + [nd - 1]:
+        p = np.array(path(t, dt))
+        centre = p[:, 0] + 0.5 * p[:, 1]
+        assert np.max(np.abs(centre - (d_min + dt) * mid)) <= bound
+
+
+def test_dmin_zero_is_the_plain_transform():
+    x = _rng(8).integers(0, 50, size=(32, 200)).astype(np.int64)
+    t0 = build_tables(32, 40, 1.2, 1.6)
+    t1 = build_tables(32, 40, 1.2, 1.6, d_min=0)
+    assert t1.pre == [0] * 32
+    np.testing.assert_array_equal(fdmt(x, 1.2, 1.6, 40, t0), fdmt(x, 1.2, 1.6, 40, t1))
+
+
+@pytest.mark.parametrize("d_min", [57, 400])
+def test_dmin_recursion_matches_path_and_adjoint(d_min):
+    """With a pre-shift the recursion still equals brute-force summation
+    along each row's (shifted) path, and the adjoint is its exact transpose
+    (<A x, g> = <x, A^T g> on integers)."""
+    nf, nt, nd, band = 64, 500, 50, (1.2, 1.6)
+    rng = _rng(d_min)
+    t = build_tables(nf, nd, *band, d_min=d_min)
+    x = rng.integers(0, 30, size=(nf, nt)).astype(np.int64)
+    y = fdmt(x, *band, nd, t)
+    for dt in [0, 17, nd - 1]:
+        np.testing.assert_array_equal(y[dt], brute_row(x, t, dt))
+    g = rng.integers(-5, 6, size=(nd, nt)).astype(np.int64)
+    assert int((y * g).sum()) == int((x * fdmt_adjoint(g, *band, nf, t)).sum())
+
+
+def test_dmin_pulse_recovered_at_offset_row():
+    """A width-1 pulse of total delay D = d_min + dt0 peaks at row dt0 of the
+    pre-shifted transform (within 2 samples, >= 60% of the pulse)."""
+    nf, nd, band, d_min = 256, 128, (1.2, 1.6), 900
+    nt = d_min + nd + 300
+    t = build_tables(nf, nd, *band, d_min=d_min)
+    for dt0 in [0, 40, nd - 1]:
+        t_arr = nt - 100
+        img = np.zeros((nf, nt), dtype=np.int64)
+        W.inject_pulses(img, band[0], band[1], [(d_min + dt0, t_arr, 1.0)])
+        out = fdmt(img, *band, nd, t)
+        i, j = np.unravel_index(np.argmax(out), out.shape)
+        assert abs(i - dt0) <= 2 and abs(j - t_arr) <= 2, (dt0, i, j)
+        assert out[i, j] >= 0.6 * nf
