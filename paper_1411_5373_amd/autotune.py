@@ -116,21 +116,42 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def ragged_lengths(beams, lo, hi, seed):
+    """Beam lengths log-uniform in [lo, hi] (a survey's mix of record lengths)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [int(n) for n in np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=beams)))]
+
+
 def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32, reps=5,
-         verbose=False, gamma=-2.0):
-    """Times every candidate; returns {"options", "forward_ms", "adjoint_ms", "tried"}."""
+         verbose=False, gamma=-2.0, lengths=None):
+    """Times every candidate; returns {"options", "forward_ms", "adjoint_ms", "tried"}.
+    With `lengths`, candidates are timed as a ragged batch of beams of those
+    lengths (RaggedPlan; nt is then the longest beam)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     gen = torch.Generator(device=dev).manual_seed(1)
+    if lengths is not None:
+        nt = max(lengths)
+    shape_in, shape_out = ((nf * sum(lengths),), (nd * sum(lengths),)) if lengths else ((nf, nt), (nd, nt))
     if in_dtype in (torch.uint8, torch.int32):
-        x = torch.randint(0, 256, (nf, nt), device=dev, dtype=torch.int32, generator=gen).to(in_dtype)
+        x = torch.randint(0, 256, shape_in, device=dev, dtype=torch.int32, generator=gen).to(in_dtype)
     else:
-        x = torch.randn(nf, nt, device=dev, generator=gen).to(in_dtype)
+        x = torch.randn(shape_in, device=dev, generator=gen).to(in_dtype)
     if acc_dtype == torch.int32:
-        g = torch.randint(-8, 8, (nd, nt), device=dev, dtype=torch.int32, generator=gen)
+        g = torch.randint(-8, 8, shape_out, device=dev, dtype=torch.int32, generator=gen)
     else:
-        g = torch.randn(nd, nt, device=dev, generator=gen)
-    y = torch.empty(nd, nt, device=dev, dtype=acc_dtype)
-    xb = torch.empty(nf, nt, device=dev, dtype=acc_dtype)
+        g = torch.randn(shape_out, device=dev, generator=gen)
+    y = torch.empty(shape_out, device=dev, dtype=acc_dtype)
+    xb = torch.empty(shape_in, device=dev, dtype=acc_dtype)
+
+    def runner(p, adjoint):
+        if lengths:
+            r = B.RaggedPlan(p, lengths)
+            ws = r.workspace()
+            return (lambda: r.adjoint(g, out=xb, ws=ws)) if adjoint else (lambda: r.forward(x, out=y, ws=ws))
+        ws = p.workspace(1)
+        return (lambda: p.adjoint(g, out=xb, ws=ws)) if adjoint else (lambda: p.forward(x, out=y, ws=ws))
+
     tried = []
     best = {}
     for rows, vecs in [(r, v) for r in GATHER_ROWS for v in GATHER_VECS]:
@@ -140,30 +161,30 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
             opts = dict(cand, **shared)
             try:
                 p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
+                fn = runner(p, False)
             except B.FDMTError:
-                continue  # this schedule does not fit the shape
-            ws = p.workspace(1)
-            ms = _time(lambda: p.forward(x, out=y, ws=ws), reps)
+                continue  # this schedule does not fit the shape (or the ragged form)
+            ms = _time(fn, reps)
             tried.append({"direction": "forward", "options": opts, "ms": round(ms, 4)})
             if verbose:
                 print(f"forward {opts}: {ms:.4f} ms", flush=True)
             if fwd_best is None or ms < fwd_best[0]:
                 fwd_best = (ms, cand)
-            del p, ws
+            del p, fn
         for cand in adjoint_candidates(rows):
             opts = dict(cand, **shared)
             try:
                 p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
+                fn = runner(p, True)
             except B.FDMTError:
                 continue
-            ws = p.workspace(1)
-            ms = _time(lambda: p.adjoint(g, out=xb, ws=ws), reps)
+            ms = _time(fn, reps)
             tried.append({"direction": "adjoint", "options": opts, "ms": round(ms, 4)})
             if verbose:
                 print(f"adjoint {opts}: {ms:.4f} ms", flush=True)
             if adj_best is None or ms < adj_best[0]:
                 adj_best = (ms, cand)
-            del p, ws
+            del p, fn
         if fwd_best is None or adj_best is None:
             continue
         total = fwd_best[0] + adj_best[0]
@@ -194,24 +215,30 @@ def store(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, result, arch_name=None,
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--nf", type=int, required=True)
-    ap.add_argument("--nt", type=int, required=True)
+    ap.add_argument("--nt", type=int, default=0, help="samples (not used with --ragged)")
     ap.add_argument("--nd", type=int, required=True)
     ap.add_argument("--band", type=float, nargs=2, required=True)
     ap.add_argument("--in-dtype", choices=sorted(DTYPES), default="f32")
     ap.add_argument("--acc-dtype", choices=sorted(DTYPES), default="f32")
     ap.add_argument("--gamma", type=float, default=-2.0, help="delay law dt ~ f^gamma")
+    ap.add_argument("--ragged", type=int, nargs=4, metavar=("BEAMS", "LO", "HI", "SEED"),
+                    help="time a ragged batch of BEAMS beams, lengths log-uniform in [LO, HI] "
+                         "(the entry is stored under Nt = the longest beam)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--write", action="store_true", help="store the result in the cache")
     ap.add_argument("--out", help="also write the full result (every candidate's time) to this JSON file")
     args = ap.parse_args()
     ind, acc = DTYPES[args.in_dtype], DTYPES[args.acc_dtype]
-    res = tune(args.nf, args.nt, args.nd, *args.band, ind, acc, reps=args.reps, verbose=True, gamma=args.gamma)
+    lengths = ragged_lengths(*args.ragged) if args.ragged else None
+    nt = max(lengths) if lengths else args.nt
+    res = tune(args.nf, nt, args.nd, *args.band, ind, acc, reps=args.reps, verbose=True, gamma=args.gamma,
+               lengths=lengths)
     print(json.dumps({k: v for k, v in res.items() if k != "tried"}), flush=True)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(dict(res, workload=vars(args)), f, indent=1)
     if args.write:
-        print("stored in", store(args.nf, args.nt, args.nd, *args.band, ind, acc, res, gamma=args.gamma),
+        print("stored in", store(args.nf, nt, args.nd, *args.band, ind, acc, res, gamma=args.gamma),
               flush=True)
 
 

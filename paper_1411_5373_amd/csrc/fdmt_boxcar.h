@@ -10,7 +10,7 @@
 
 namespace fdmt {
 
-constexpr int kBoxTile = 4096;   // samples of one row per workgroup
+constexpr int kBoxTile = 2048;   // samples of one row per workgroup
 constexpr int kBoxMaxLog2 = 10;  // widths up to 2^10 samples
 
 // Statistics of one width over one tile of one row.

@@ -14,9 +14,8 @@ namespace fdmt {
 
 namespace {
 
-constexpr int kBoxThreads = 256;
+constexpr int kBoxThreads = 64;  // one wave: its LDS steps need no workgroup barrier to wait on other waves
 constexpr int kBoxPerThread = kBoxTile / kBoxThreads;
-constexpr int kBoxHaloMax = (1 << kBoxMaxLog2) - 1;
 
 // Peak order: larger value first, then earlier time.
 __device__ __forceinline__ bool better(float v, int t, float bv, int bt) { return v > bv || (v == bv && t < bt); }
@@ -26,48 +25,61 @@ __device__ __forceinline__ T xor_lane(T x, int mask) {
   return __shfl_xor(x, mask, 64);
 }
 
-// One workgroup: one row, one tile of kBoxTile samples plus the w_max - 1
-// samples before it. Width 2w is built in LDS from width w as
+// One workgroup (one wave): one row, one tile of kBoxTile samples plus the
+// w_max - 1 samples before it. Width 2w is built in LDS from width w as
 // b_2w[t] = b_w[t] + b_w[t - w], which sums each window in a fixed tree; each
 // level's tile samples then add to the partial statistics of that width.
 __global__ __launch_bounds__(kBoxThreads) void boxcar_tile_kernel(const float *__restrict__ plane,
                                                                   BoxPartial *__restrict__ part, int64_t nt,
                                                                   int32_t nd, int32_t ntiles, int32_t max_log2) {
-  __shared__ float buf[kBoxTile + kBoxHaloMax];
-  __shared__ double red_sum[kBoxThreads / 64], red_sq[kBoxThreads / 64];
-  __shared__ float red_max[kBoxThreads / 64];
-  __shared__ int red_t[kBoxThreads / 64];
+  extern __shared__ float buf[];  // kBoxTile + 2^max_log2 - 1 samples
   const int tile = blockIdx.x, row = blockIdx.y, b = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int tid = threadIdx.x;
   const int halo = (1 << max_log2) - 1;
   const int64_t t0 = static_cast<int64_t>(tile) * kBoxTile;  // first sample of the tile
   const int64_t left = nt - t0;
   const int nvalid = left < kBoxTile ? static_cast<int>(left) : kBoxTile;
   const float *y = plane + (static_cast<int64_t>(b) * nd + row) * nt;
-  // local index i holds time t0 - halo + i
-  for (int i = tid; i < halo + nvalid; i += kBoxThreads) {
-    const int64_t t = t0 - halo + i;
-    buf[i] = t >= 0 ? y[t] : 0.0f;
+  // local index i holds time t0 - halo + i; every load is issued before the
+  // first store to LDS
+  {
+    constexpr int kLoads = (kBoxTile + (1 << kBoxMaxLog2) - 1 + kBoxThreads - 1) / kBoxThreads;
+    float v[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int i = tid + k * kBoxThreads;
+      const int64_t t = t0 - halo + i;
+      v[k] = i < halo + nvalid && t >= 0 ? y[t] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int i = tid + k * kBoxThreads;
+      if (i < halo + nvalid) buf[i] = v[k];
+    }
   }
   __syncthreads();
   for (int j = 0; j <= max_log2; ++j) {
     if (j > 0) {
       // width 2^j from width w = 2^(j-1); valid from local index 2^j - 1 on,
       // which covers every index a later width or the statistics read
+      // In place, from the top index down, kGroup * 64 indices at a time: a
+      // group reads all its old values before writing, and every index it
+      // reads lies at or below its own top, which later groups never write.
+      constexpr int kGroup = 8;
       const int w = 1 << (j - 1);
-      const int first = (1 << j) - 1 + tid, end = halo + nvalid;
-      constexpr int kSlots = (kBoxTile + kBoxHaloMax + kBoxThreads - 1) / kBoxThreads;
-      float nv[kSlots];
+      const int first = (1 << j) - 1;
+      for (int top = halo + nvalid - 1; top >= first; top -= kGroup * kBoxThreads) {
+        float nv[kGroup];
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        const int i = first + k * kBoxThreads;
-        if (i < end) nv[k] = buf[i] + buf[i - w];
-      }
-      __syncthreads();
+        for (int g = 0; g < kGroup; ++g) {
+          const int i = top - g * kBoxThreads - tid;
+          if (i >= first) nv[g] = buf[i] + buf[i - w];
+        }
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        const int i = first + k * kBoxThreads;
-        if (i < end) buf[i] = nv[k];
+        for (int g = 0; g < kGroup; ++g) {
+          const int i = top - g * kBoxThreads - tid;
+          if (i >= first) buf[i] = nv[g];
+        }
       }
       __syncthreads();
     }
@@ -98,29 +110,13 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_tile_kernel(const float *_
         best_t = ot;
       }
     }
-    if (lane == 0) {
-      red_sum[wave] = s;
-      red_sq[wave] = q;
-      red_max[wave] = best;
-      red_t[wave] = best_t;
-    }
-    __syncthreads();
     if (tid == 0) {
-      for (int v = 1; v < kBoxThreads / 64; ++v) {
-        s += red_sum[v];
-        q += red_sq[v];
-        if (better(red_max[v], red_t[v], best, best_t)) {
-          best = red_max[v];
-          best_t = red_t[v];
-        }
-      }
       BoxPartial &p = part[((static_cast<int64_t>(b) * (max_log2 + 1) + j) * nd + row) * ntiles + tile];
       p.sum = s;
       p.sumsq = q;
       p.peak = best;
       p.t = static_cast<int32_t>(t0) + best_t;
     }
-    __syncthreads();
   }
 }
 
@@ -165,7 +161,8 @@ hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t 
                          fdmt_boxcar_t *out, void *ws, hipStream_t stream) {
   const int64_t ntiles = (nt + kBoxTile - 1) / kBoxTile;
   BoxPartial *part = static_cast<BoxPartial *>(ws);
-  hipLaunchKernelGGL(boxcar_tile_kernel, dim3(static_cast<unsigned>(ntiles), nd, batch), dim3(kBoxThreads), 0,
+  const size_t lds = (kBoxTile + (1 << max_log2) - 1) * sizeof(float);
+  hipLaunchKernelGGL(boxcar_tile_kernel, dim3(static_cast<unsigned>(ntiles), nd, batch), dim3(kBoxThreads), lds,
                      stream, plane, part, nt, nd, static_cast<int32_t>(ntiles), max_log2);
   const int64_t count = static_cast<int64_t>(batch) * (max_log2 + 1) * nd;
   hipLaunchKernelGGL(boxcar_combine_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, stream,

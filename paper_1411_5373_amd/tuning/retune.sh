@@ -12,8 +12,9 @@ $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype f16 --acc-dtype f32
 $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
 $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype u8 --acc-dtype i32
 $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype i32 --acc-dtype i32
-# ragged beams (base plan Nt = the longest beam, 32511), Nf=1024, Nd=512
-$T --nf 1024 --nt 32768 --nd 512 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
+# ragged beams: 256 beams, Nt log-uniform in [2048, 32768] (the benchmark's
+# draw), Nf=1024, Nd=512, timed as one ragged batch; stored under Nt = 32511
+$T --nf 1024 --nd 512 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32 --ragged 256 2048 32768 14115376
 # Nf=1024, Nt=8192, Nd=1024 and the 0.4-0.8 GHz batch-16 form
 $T --nf 1024 --nt 8192 --nd 1024 --band 1.2 1.6 --in-dtype f32 --acc-dtype f32
 $T --nf 1024 --nt 16384 --nd 1024 --band 0.4 0.8 --in-dtype f32 --acc-dtype f32

@@ -99,7 +99,7 @@ def test_boxcar_argument_errors_before_launch():
     lib = B.load()
     x, o, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
     need = F.fdmt_boxcar_workspace_bytes(2, 8, 10000, 5)
-    assert need == 2 * 6 * 8 * 3 * 24
+    assert need == 2 * 6 * 8 * 5 * 24      # beams * widths * rows * 2048-sample tiles * partial
     for args in [(1, 0, 100, 3), (0, 4, 100, 3), (1, 4, 0, 3), (1, 4, 100, 11), (1, 4, 100, -1),
                  (1, 70000, 100, 3)]:
         assert F.fdmt_boxcar_workspace_bytes(*args) == 0

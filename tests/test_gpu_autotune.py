@@ -35,3 +35,19 @@ def test_tuned_schedule_round_trip(tmp_path, monkeypatch, in_dtype):
     g = torch.randn(300, 2900, device=DEV, generator=gen)
     pa = F.Plan(256, 2900, 300, 1.2, 1.6, tuned=False, **{k: v for k, v in res["options"].items()})
     assert torch.equal(pa.adjoint(g), F.Plan(256, 2900, 300, 1.2, 1.6, unfused=True).adjoint(g))
+
+
+def test_ragged_tuning(tmp_path, monkeypatch):
+    """Tuning a ragged batch times RaggedPlan candidates (staged passes, which
+    the ragged form refuses, are skipped) and stores under the longest beam."""
+    monkeypatch.setenv("FDMT_TUNE_CACHE", str(tmp_path / "cache.json"))
+    lengths = A.ragged_lengths(6, 200, 3000, 5)
+    res = A.tune(64, 0, 64, 1.2, 1.6, reps=1, lengths=lengths)
+    assert res["forward_ms"] > 0 and res["adjoint_ms"] > 0
+    A.store(64, max(lengths), 64, 1.2, 1.6, torch.float32, torch.float32, res)
+    p = F.Plan(64, max(lengths), 64, 1.2, 1.6, tuned=True)
+    assert p.tuned == res["options"]
+    r = F.RaggedPlan(p, lengths)
+    x = torch.randn(64 * sum(lengths), device=DEV, generator=torch.Generator(DEV).manual_seed(4))
+    ref = F.RaggedPlan(F.Plan(64, max(lengths), 64, 1.2, 1.6, unfused=True), lengths)
+    assert torch.equal(r.forward(x), ref.forward(x))
