@@ -718,8 +718,9 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
           const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
-            // uint16 out: a lane's 8 samples are one 16-byte store. 4-byte
-            // planes keep the 4-sample runs, whose stores are whole lines.
+            // uint16 out: the integer-sum kernel (a lane's 8 samples are one
+            // 16-byte store). 4-byte planes: the 4-sample-run kernel, which
+            // timed faster there than the integer-sum kernel's wide loads.
             if (narrow_out)
               return launch_narrow_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32, src.stride,
                                                     src.bstride, dst.stride, dst.bstride, ps.nblocks);

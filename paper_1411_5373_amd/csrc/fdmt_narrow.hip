@@ -105,7 +105,10 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   const int64_t src_stride = FROM_INPUT ? nt : bs.src_stride;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * S;
-  if (t >= nt) return;
+  // Lanes past the record's end return early, except where the outputs pass
+  // through LDS: there every lane stores 4 samples of another lane's range.
+  constexpr bool kTranspose = sizeof(Tdst) == 4 && CV == 2;
+  if (!kTranspose && t >= nt) return;
   const Tsrc *base = static_cast<const Tsrc *>(src_v) + bs.src_off;
   // terms: (row or channel, shift, chain)
   int row[N], shift[N], chain[N];
@@ -185,7 +188,37 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
       }
     }
   }
-  store_lane<Tdst, S>(dst + bs.dst_off + r * bs.dst_stride + t, acc, t, nt);
+  Tdst *orow = dst + bs.dst_off + r * bs.dst_stride;
+  if constexpr (kTranspose) {
+    // 4-byte outputs: a lane's 8 consecutive samples would be two 16-byte
+    // stores that each cover every other 16 bytes of the wave's span. Pass
+    // them through LDS so each store instruction writes 256 consecutive
+    // samples (4 per lane, whole lines). One wave's LDS accesses are ordered,
+    // so no barrier is needed.
+    typedef Tdst T4 __attribute__((ext_vector_type(4)));
+    __shared__ T4 xbuf[kGatherThreads / 64][128];
+    T4 *xb = xbuf[wave];
+    T4 lo, hi;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lo[q] = from_int<Tdst>(acc[q]);
+      hi[q] = from_int<Tdst>(acc[4 + q]);
+    }
+    xb[2 * lane] = lo;
+    xb[2 * lane + 1] = hi;
+#pragma unroll
+    for (int run = 0; run < 2; ++run) {
+      const T4 d = xb[64 * run + lane];
+      const int tc = tw + 256 * run + 4 * lane;
+      if (tc + 4 <= nt) {
+        *reinterpret_cast<typename Vec4<Tdst>::type *>(orow + tc) = d;
+      } else {
+        for (int q = 0; q < 4 && tc + q < nt; ++q) orow[tc + q] = d[q];
+      }
+    }
+  } else {
+    store_lane<Tdst, S>(orow + t, acc, t, nt);
+  }
 }
 
 template <bool FROM_INPUT, typename Tdst>
