@@ -125,6 +125,10 @@ typedef struct {
                              follows delay d_min + dt. Needs the first pass to gather from
                              the input (first_kernel 3, the default when d_min > 0) or
                              the unfused schedule. Changes the results */
+  uint32_t adjoint_tile_major; /* bit i set: adjoint gather pass i (launch order) runs each row
+                                  group's time tiles back to back on one XCD instead of all
+                                  groups of a tile together; suits passes whose leaves sit at
+                                  large shifts (0 = default: none) */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

@@ -41,7 +41,7 @@ GATHER_ROWS_DEFAULT = 8  # the library's gather_rows when the option is 0
 # Fields that shape only the forward or only the adjoint schedule.
 FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
                   "max_block_rows", "stream_tiles")
-ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows")
+ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows", "adjoint_tile_major")
 SHARED_FIELDS = ("gather_rows", "gather_vecs")
 
 
@@ -57,14 +57,46 @@ def forward_candidates():
     return out
 
 
+# Adjoint passes that run each row group's tiles back to back: none, the
+# first and last (leaves at the largest shifts; one sub-band per workgroup),
+# or all.
+TILE_MAJOR_MASKS = ("none", "ends", "all")
+
+
 def adjoint_candidates(gather_rows=GATHER_ROWS_DEFAULT):
-    """Adjoint pass depths, and channels per workgroup of the last pass: the
-    shared gather shape, or a larger one (a whole sub-band per workgroup)."""
+    """Adjoint pass depths, channels per workgroup of the last pass (the shared
+    gather shape, or a whole sub-band per workgroup) and work order."""
     last_rows = [0] + [r for r in (8, 16) if r > gather_rows]
-    return [dict(adjoint_levels=a, adjoint_last_levels=b, adjoint_last_rows=r)
-            for a in (1, 2, 3) for b in (1, 2, 3) for r in last_rows]
+    return [dict(adjoint_levels=a, adjoint_last_levels=b, adjoint_last_rows=r, adjoint_tile_major=m)
+            for a in (1, 2, 3) for b in (1, 2, 3) for r in last_rows for m in TILE_MAJOR_MASKS]
 
 
+def tile_major_mask(name, passes):
+    """Bitmask over `passes` adjoint passes for a TILE_MAJOR_MASKS name."""
+    if name == "none" or passes == 0:
+        return 0
+    if name == "all":
+        return (1 << passes) - 1
+    return 1 | (1 << (passes - 1))
+
+
+def adjoint_gather_passes(plan):
+    """Number of adjoint gather passes of a plan."""
+    return sum(1 for s in plan.steps(adjoint=True) if s["kind"] == B.STEP_KINDS[8])
+
+
+def resolve_order(cand, make_plan):
+    """Replaces a candidate's work-order name by its bitmask. `make_plan(**opts)`
+    builds a plan from schedule options; returns the options, or None when the
+    name selects no pass."""
+    cand = dict(cand)
+    order = cand.pop("adjoint_tile_major", "none")
+    if order != "none":
+        mask = tile_major_mask(order, adjoint_gather_passes(make_plan(**cand)))
+        if mask == 0:
+            return None
+        cand["adjoint_tile_major"] = mask
+    return cand
 
 
 def arch():
@@ -172,9 +204,15 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
                 fwd_best = (ms, cand)
             del p, fn
         for cand in adjoint_candidates(rows):
-            opts = dict(cand, **shared)
             try:
-                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
+                def make(**o):
+                    return B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma,
+                                  **o, **shared)
+                cand = resolve_order(cand, make)
+                if cand is None:
+                    continue
+                opts = dict(cand, **shared)
+                p = make(**cand)
                 fn = runner(p, True)
             except B.FDMTError:
                 continue

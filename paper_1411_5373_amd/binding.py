@@ -53,7 +53,8 @@ class _Options(ctypes.Structure):
                 ("stream_tiles", ctypes.c_int32), ("gather_rows", ctypes.c_int32),
                 ("adjoint_levels", ctypes.c_int32), ("adjoint_last_levels", ctypes.c_int32),
                 ("gather_vecs", ctypes.c_int32), ("adjoint_last_rows", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32)]
+                ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32),
+                ("adjoint_tile_major", ctypes.c_uint32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -147,14 +148,15 @@ def fdmt_last_error():
 def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, flags=0,
               first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
-              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0):
+              adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0,
+              adjoint_tile_major=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
                    int(later_levels), int(tile), int(lds_kib), int(max_block_rows),
                    int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows),
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
-                   int(adjoint_last_rows), float(gamma), int(d_min))
+                   int(adjoint_last_rows), float(gamma), int(d_min), int(adjoint_tile_major))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value

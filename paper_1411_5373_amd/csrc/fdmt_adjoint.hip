@@ -163,17 +163,19 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
     const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u, int32_t max_shift,
     int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
-    int32_t rows_per_wg, RaggedMap rg) {
+    int32_t rows_per_wg, int32_t tiles_fastest, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   constexpr int kSpan = adjoint_wave_span(CV, LAG);
   const int waves = kGatherThreads / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int g = xcd_local_order(blockIdx.x, groups);
+  const int2 item = gather_item<RAGGED>(groups, tiles_fastest != 0);
+  const int g = item.x;
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
-  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
+  BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
+  if (!RAGGED) bs.tile = item.y;
   const int nt = bs.nt;
   const int t_wave = (bs.tile * col_waves + wave % col_waves) * kSpan;
   const int t = t_wave + lane * 4;
@@ -225,7 +227,7 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
 #define FDMT_ADJ(KK, CC, RR, LL)                                                                         \
   hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL>), g.grid, dim3(kGatherThreads), 0, g.stream, \
                      src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,      \
-                     dst_bstride, nrows, g.rows_per_wg, g.rg)
+                     dst_bstride, nrows, g.rows_per_wg, g.tiles_fastest, g.rg)
 #define FDMT_ADJ_K(CC, RR)                                    \
   if (g.lagged) {                                             \
     switch (g.depth) {                                        \

@@ -239,6 +239,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (o.gather_rows) p.gather_rows = o.gather_rows;
   if (o.gather_vecs) p.gather_vecs = o.gather_vecs;
   p.adjoint_last_rows = o.adjoint_last_rows;
+  p.adjoint_tile_major = o.adjoint_tile_major;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
   if (!(o.flags & FDMT_PLAN_UNFUSED)) {
     fdmt::ScheduleParams sp;

@@ -74,6 +74,29 @@ __device__ __forceinline__ int xcd_local_order(int id, int n) {
 
 
 
+// Work item (row group, time tile) of a register-gather launch over
+// groups x tiles workgroups. By default (and always for ragged launches,
+// whose tile comes from their map: blockIdx.y, returned as -1 here) row
+// groups are spread over the XCDs as above and all groups of a tile run
+// together, so rows that share terms meet in L2. With `tiles_fastest`, a
+// uniform launch deals the whole grid so that each XCD runs a contiguous
+// range of row groups with every group's time tiles back to back: a term row
+// read at a large shift straddles neighbouring tiles, and the second tile
+// finds it in that XCD's L2.
+template <bool RAGGED>
+__device__ __forceinline__ int2 gather_item(int groups, bool tiles_fastest) {
+  if (RAGGED || !tiles_fastest) {
+    return make_int2(xcd_local_order(blockIdx.x, groups), RAGGED ? -1 : static_cast<int>(blockIdx.y));
+  } else {
+    const int tiles = gridDim.y;
+    const int64_t n = static_cast<int64_t>(groups) * tiles;
+    const int64_t id = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;  // dispatch order
+    const int64_t q = n >> 3, r = n & 7, x = id & 7, slot = id >> 3;
+    const int64_t item = x * q + (x < r ? x : r) + slot;
+    return make_int2(static_cast<int>(item / tiles), static_cast<int>(item % tiles));
+  }
+}
+
 // Block records and headers are read-only for the whole launch and the same
 // for every lane of a wave: reading them through the constant address space
 // makes them scalar loads.

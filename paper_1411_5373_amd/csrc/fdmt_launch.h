@@ -19,6 +19,7 @@ struct GatherLaunch {
   bool ragged;
   int depth, vecs, rows_per_wg;
   bool lagged = false;  // adjoint: lagged leaf list (subtrees listed once)
+  int tiles_fastest = 0;  // adjoint: run each row group's time tiles back to back (uniform launches)
 };
 
 // Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,

@@ -95,12 +95,14 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int g = xcd_local_order(blockIdx.x, groups);
+  const int2 item = gather_item<RAGGED>(groups, false);
+  const int g = item.x;
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
   // the input's rows are Nt samples apart; a plane's by its (padded) stride
-  const BeamSpan bs = beam_span<RAGGED>(rg, nt_u, FROM_INPUT ? nt_u : src_stride_u, src_bstride, dst_stride_u,
+  BeamSpan bs = beam_span<RAGGED>(rg, nt_u, FROM_INPUT ? nt_u : src_stride_u, src_bstride, dst_stride_u,
                                         dst_bstride);
+  if (!RAGGED) bs.tile = item.y;
   const int nt = bs.nt;
   const int64_t src_stride = FROM_INPUT ? nt : bs.src_stride;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave

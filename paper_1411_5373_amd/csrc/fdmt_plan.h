@@ -62,6 +62,7 @@ struct Plan {
   int gather_rows = 8;         // output rows per register-gather workgroup
   int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1, 2 or 4)
   int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: gather_rows)
+  uint32_t adjoint_tile_major = 0;  // bit i: adjoint pass i runs each row group's tiles back to back
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
   std::vector<uint8_t> narrow; // per forward pass: its output plane holds uint16 sums

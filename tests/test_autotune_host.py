@@ -36,10 +36,23 @@ def test_candidates_build_host_plans(nf, nd, band):
     built = 0
     for rows in A.GATHER_ROWS:
         for cand in A.forward_candidates() + A.adjoint_candidates(rows):
+            def make(**o):
+                return F.Plan(nf, 8192, nd, *band, host_only=True, gather_rows=rows,
+                              gather_vecs=A.GATHER_VECS[-1], **o)
             try:
-                F.Plan(nf, 8192, nd, *band, host_only=True, gather_rows=rows, gather_vecs=A.GATHER_VECS[-1],
-                       **cand)
-                built += 1
+                opts = A.resolve_order(cand, make)
+                if opts is not None:
+                    make(**opts)
+                    built += 1
             except F.FDMTError as e:
                 assert e.status == 2, str(e)
     assert built > 0
+
+
+def test_tile_major_masks():
+    """Work-order names map to masks over the adjoint passes in launch order."""
+    assert [A.tile_major_mask(n, 4) for n in A.TILE_MAJOR_MASKS] == [0, 0b1001, 0b1111]
+    assert A.tile_major_mask("ends", 1) == 1 and A.tile_major_mask("all", 0) == 0
+    opts = A.resolve_order(dict(adjoint_levels=3, adjoint_last_levels=3, adjoint_tile_major="ends"),
+                           lambda **o: F.Plan(4096, 8192, 2048, 1.2, 1.6, host_only=True, **o))
+    assert opts["adjoint_tile_major"] == 0b1001  # 12 iterations in 4 passes of 3

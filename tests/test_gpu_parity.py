@@ -367,6 +367,9 @@ ADJOINT_SCHEDULES = [
     dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=4, gather_vecs=4, adjoint_last_rows=8),
     dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=2, adjoint_last_rows=16),
     dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=8, gather_vecs=4, adjoint_last_rows=1),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_vecs=2, adjoint_last_rows=16, adjoint_tile_major=0b1001),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=4, adjoint_tile_major=0xFFFFFFFF),
+    dict(adjoint_levels=1, adjoint_last_levels=2, gather_vecs=1, adjoint_tile_major=0b10),
 ]
 
 
