@@ -52,6 +52,14 @@ listed with its justification in the design notes):
          the run a row adds in a channel is centred on the curve's passage
          through it; row dt then follows total delay d_min + dt. The delay
          tables themselves are unchanged.
+  R-nf   Nf need not be a power of two (Sec. 4.2, the case Nf != 2^k): the
+         iterations still pair sub-bands 2j and 2j+1, sub-band j of iteration
+         l holding channels j*2^l .. min((j+1)*2^l, Nf) - 1, so there are
+         ceil(log2 Nf) iterations. A sub-band with no channels has no rows; a
+         sub-band whose upper half has no channels is its lower half as it is
+         (a copy node); every other merge is between sub-bands of possibly
+         unequal width, split at the border frequency f1 between them, with
+         f2 the upper edge of the sub-band's last channel.
 """
 from __future__ import annotations
 
@@ -103,9 +111,11 @@ class Tables:
     nd: int
     f_min: float
     f_max: float
-    levels: int                 # log2(nf)
+    levels: int                 # ceil(log2(nf))
     rows: list                  # rows[l][j]: number of dt rows of sub-band j at iteration l
-    split: list                 # split[l][j][dt] = (d_lo, s, d_hi) for l >= 1
+                                # (2^(levels-l) sub-bands; 0 rows for one with no channels)
+    split: list                 # split[l][j][dt] = (d_lo, s, d_hi) for l >= 1; d_hi is None
+                                # in a copy node (reading R-nf)
     gamma: float = -2.0         # delay law dt ~ f^gamma
     pre: list = None            # per channel: the d_min pre-shift (reading R-dmin)
 
@@ -122,9 +132,11 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
                      t1 - t2 = d_hi = dt - d_lo                (upper half's delay)
     Row counts run top-down from Nd at the last iteration (reading R-rows).
     gamma: the delay law dt ~ f^gamma (reading R-law). d_min: the smallest
-    delay searched (reading R-dmin), which sets the per-channel pre-shift."""
-    if nf < 1 or nf & (nf - 1):
-        raise ValueError("Nf must be a power of two")
+    delay searched (reading R-dmin), which sets the per-channel pre-shift.
+    Any Nf >= 1 (reading R-nf): sub-band j of iteration l holds channels
+    j*2^l .. min((j+1)*2^l, Nf) - 1; f2 is the upper edge of its last channel."""
+    if nf < 1:
+        raise ValueError("Nf must be >= 1")
     if nd < 1:
         raise ValueError("Nd must be >= 1")
     if not (0.0 < f_min < f_max):
@@ -133,19 +145,31 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
         raise ValueError("gamma must be finite and nonzero")
     if d_min < 0:
         raise ValueError("d_min must be >= 0")
-    levels = nf.bit_length() - 1
+    levels = (nf - 1).bit_length()
     e = channel_edges(nf, f_min, f_max)
+
+    def channels(l, j):
+        return max(0, min((j + 1) << l, nf) - (j << l))
+
     rows = [None] * (levels + 1)
     split = [None] * (levels + 1)
     rows[levels] = [nd]
     for l in range(levels, 0, -1):
-        nsub = nf >> l
+        nsub = 1 << (levels - l)
         rows[l - 1] = [0] * (2 * nsub)
         split[l] = []
         for j in range(nsub):
+            if channels(l, j) == 0:
+                split[l].append([])       # no channels, no rows
+                continue
+            if channels(l - 1, 2 * j + 1) == 0:
+                # copy node: the sub-band is its lower half (reading R-nf)
+                split[l].append([(dt, 0, None) for dt in range(rows[l][j])])
+                rows[l - 1][2 * j] = rows[l][j]
+                continue
             f0 = e[j << l]
             f1 = e[(2 * j + 1) << (l - 1)]
-            f2 = e[(j + 1) << l]
+            f2 = e[min((j + 1) << l, nf)]
             c = merge_coefficient(f0, f1, f2, gamma)
             triples = []
             for dt in range(rows[l][j]):
@@ -194,7 +218,10 @@ def initialize(img, tables, acc=None):
                 xs[k, sh:] = x[k, : nt - sh]
         x = xs
     planes = []
-    for k in range(nf):
+    for k in range(len(tables.rows[0])):
+        if k >= nf:
+            planes.append(np.zeros((0, nt), dtype=acc))  # no channel here (reading R-nf)
+            continue
         n = tables.rows[0][k]
         a = np.zeros((n, nt), dtype=acc)
         a[0] = x[k]
@@ -211,14 +238,17 @@ def iterate(planes, tables, nt):
     for each dt, for each t0:
         A_{f0}^{f2}(t0, dt) = A_{f0}^{f1}(t0, d_lo) + A_{f1}^{f2}(t0 - s, d_hi)   (t0 >= s)
         A_{f0}^{f2}(t0, dt) = A_{f0}^{f1}(t0, d_lo)                             (t0 <  s)
-    where the second line is the alternative (copy) rule for t1 = t0 - s < 0."""
+    where the second line is the alternative (copy) rule for t1 = t0 - s < 0.
+    A copy node (reading R-nf) is its lower half: A_{f0}^{f2}(t0, dt) = A_{f0}^{f1}(t0, dt)."""
     for l in range(1, tables.levels + 1):
         merged = []
-        for j in range(tables.nf >> l):
+        for j in range(len(planes) // 2):
             lower, upper = planes[2 * j], planes[2 * j + 1]
             out = np.empty((tables.rows[l][j], nt), dtype=lower.dtype)
             for dt, (d_lo, s, d_hi) in enumerate(tables.split[l][j]):
-                if s < nt:
+                if d_hi is None:
+                    out[dt] = lower[d_lo]
+                elif s < nt:
                     out[dt, s:] = lower[d_lo, s:] + upper[d_hi, : nt - s]
                     out[dt, :s] = lower[d_lo, :s]
                 else:
@@ -267,7 +297,7 @@ def fdmt_adjoint(grad, f_min, f_max, nf, tables=None, acc=None):
             hi_bar = np.zeros((tables.rows[l - 1][2 * j + 1], nt), dtype=acc)
             for dt, (d_lo, s, d_hi) in enumerate(tables.split[l][j]):
                 lo_bar[d_lo] += g[dt]
-                if s < nt:
+                if d_hi is not None and s < nt:
                     hi_bar[d_hi, : nt - s] += g[dt, s:]
             split_planes += [lo_bar, hi_bar]
         planes = split_planes
@@ -293,12 +323,17 @@ def path(tables, dt):
     nodes = [(0, dt)]
     for l in range(tables.levels, 0, -1):
         nxt = []
-        for j, (sigma, d) in enumerate(nodes):
+        for j, node in enumerate(nodes):
+            if node is None:              # no channels below (reading R-nf)
+                nxt += [None, None]
+                continue
+            sigma, d = node
             d_lo, s, d_hi = tables.split[l][j][d]
             nxt.append((sigma, d_lo))
-            nxt.append((sigma + s, d_hi))
+            nxt.append(None if d_hi is None else (sigma + s, d_hi))
         nodes = nxt
-    return [(sigma + pre, d) for (sigma, d), pre in zip(nodes, tables.pre)]
+    assert all(n is not None for n in nodes[:tables.nf]) and all(n is None for n in nodes[tables.nf:])
+    return [(sigma + pre, d) for (sigma, d), pre in zip(nodes[:tables.nf], tables.pre)]
 
 
 def brute_point(img, tables, dt, t0):

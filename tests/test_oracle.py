@@ -22,7 +22,7 @@ def _rng(seed):
 
 # ---------------------------------------------------------------- worked examples
 
-@pytest.mark.parametrize("name", ["tiny_nf2_nd3.txt", "tiny_nf4_nd4.txt"])
+@pytest.mark.parametrize("name", ["tiny_nf2_nd3.txt", "tiny_nf4_nd4.txt", "tiny_nf3_nd4.txt"])
 def test_hand_derived_examples(name):
     """Hand-derived outputs of one and two iterations (fixtures cite the
     addition rule, Eq. Cf2f0 and Option-1 init); pins direction of shifts,
@@ -33,16 +33,28 @@ def test_hand_derived_examples(name):
 
 # ---------------------------------------------------------------- delay tables
 
-@pytest.mark.parametrize("nf,nd", [(2, 3), (8, 8), (64, 64), (256, 100), (1024, 1024), (4096, 2048)])
+@pytest.mark.parametrize("nf,nd", [(2, 3), (8, 8), (64, 64), (256, 100), (1024, 1024), (4096, 2048),
+                                   (3, 4), (6, 20), (100, 90), (1000, 1024)])
 @pytest.mark.parametrize("band", BANDS)
 def test_table_invariants(nf, nd, band):
     """Each split is a partition of the delay (d_lo + d_hi = dt, s = d_lo), the
-    maps are monotone with unit steps, and every child row exists."""
+    maps are monotone with unit steps, and every child row exists. With Nf not
+    a power of two (Sec. 4.2), sub-band j of iteration l has rows exactly when
+    it holds a channel, and one whose upper half holds none passes its rows
+    straight down."""
     t = build_tables(nf, nd, *band)
-    assert t.rows[t.levels] == [nd]
+    assert t.rows[t.levels] == [nd] and t.levels == math.ceil(math.log2(nf))
     for l in range(1, t.levels + 1):
         for j, trip in enumerate(t.split[l]):
             assert len(trip) == t.rows[l][j]
+            assert (t.rows[l][j] > 0) == (j << l < nf)
+            if trip and trip[0][2] is None:  # upper half without channels
+                assert (2 * j + 1) << (l - 1) >= nf and t.rows[l - 1][2 * j + 1] == 0
+                assert [x[0] for x in trip] == list(range(len(trip))) and t.rows[l - 1][2 * j] == len(trip)
+                continue
+            if not trip:
+                continue
+            assert (2 * j + 1) << (l - 1) < nf
             prev = None
             for dt, (d_lo, s, d_hi) in enumerate(trip):
                 assert 0 <= d_lo <= dt and s == d_lo and d_lo + d_hi == dt
@@ -54,7 +66,8 @@ def test_table_invariants(nf, nd, band):
             assert trip[-1][2] + 1 == t.rows[l - 1][2 * j + 1]
 
 
-@pytest.mark.parametrize("nf,nd", [(16, 40), (64, 64), (1024, 1024), (4096, 2048)])
+@pytest.mark.parametrize("nf,nd", [(16, 40), (64, 64), (1024, 1024), (4096, 2048), (12, 40), (1000, 1024),
+                                   (336, 500)])
 @pytest.mark.parametrize("band", BANDS)
 def test_path_follows_dispersion_law(nf, nd, band):
     """Closed-form bound from Eq. (DtD): along every output path the start shift
@@ -78,7 +91,7 @@ def test_path_follows_dispersion_law(nf, nd, band):
 
 
 @pytest.mark.parametrize("gamma", [-1.0, 1.0, 2.0, -3.5])
-@pytest.mark.parametrize("nf,nd", [(16, 40), (256, 300), (1024, 1024)])
+@pytest.mark.parametrize("nf,nd", [(16, 40), (256, 300), (1024, 1024), (100, 300)])
 @pytest.mark.parametrize("band", BANDS)
 def test_path_follows_power_law(gamma, nf, nd, band):
     """Another delay law dt ~ f^gamma (Sec. 4.2, other functional forms): the
@@ -147,7 +160,8 @@ def test_work_below_paper_bound():
 
 # ---------------------------------------------------------------- recursion
 
-@pytest.mark.parametrize("nf,nt,nd", [(1, 20, 7), (2, 16, 5), (8, 40, 12), (16, 64, 30), (32, 50, 64)])
+@pytest.mark.parametrize("nf,nt,nd", [(1, 20, 7), (2, 16, 5), (8, 40, 12), (16, 64, 30), (32, 50, 64),
+                                      (3, 20, 9), (7, 30, 20), (20, 50, 40)])
 @pytest.mark.parametrize("band", BANDS)
 def test_recursion_equals_path_brute_force(nf, nt, nd, band):
     """Bottom-up recursion == top-down path summation, exact in int64, including
@@ -161,14 +175,14 @@ def test_recursion_equals_path_brute_force(nf, nt, nd, band):
         assert out[dt, t0] == brute_point(img, t, dt, t0)
 
 
-@pytest.mark.parametrize("nf,nd", [(8, 8), (64, 64), (256, 300)])
+@pytest.mark.parametrize("nf,nd", [(8, 8), (64, 64), (256, 300), (5, 9), (100, 64)])
 def test_zero_delay_row_is_channel_sum(nf, nd):
     """At dt = 0 the curve is vertical: row 0 = sum over frequencies of I[f][t0]."""
     img = _rng(nf).integers(0, 256, size=(nf, 300))
     np.testing.assert_array_equal(fdmt(img, 1.2, 1.6, nd)[0], img.sum(axis=0))
 
 
-@pytest.mark.parametrize("nf,nd", [(4, 9), (64, 64), (128, 200)])
+@pytest.mark.parametrize("nf,nd", [(4, 9), (64, 64), (128, 200), (3, 7), (100, 120), (257, 64)])
 def test_all_ones_closed_form(nf, nd):
     """A complete path (t0 >= dt) through all-ones data adds Nf + dt samples
     (Nf channel runs whose lengths add to dt + Nf); no term is dropped or doubled."""
@@ -271,7 +285,8 @@ def test_c1_pulse_recovered():
     assert out[i, j] >= 0.6 * w.nf * amp
 
 
-@pytest.mark.parametrize("nf,nd,band", [(256, 256, (1.2, 1.6)), (256, 512, (0.4, 0.8)), (1024, 300, (1.2, 1.6))])
+@pytest.mark.parametrize("nf,nd,band", [(256, 256, (1.2, 1.6)), (256, 512, (0.4, 0.8)), (1024, 300, (1.2, 1.6)),
+                                        (1000, 512, (1.2, 1.6)), (336, 300, (0.4, 0.8))])
 def test_noiseless_pulses_recovered(nf, nd, band):
     """Noiseless width-1 pulses at several delays: the transform's peak sits within
     2 samples of the truth in both axes (2*Nd/Nf in delay when Nd > Nf, where each
@@ -295,7 +310,8 @@ def test_noiseless_pulses_recovered(nf, nd, band):
 
 # ---------------------------------------------------------------- adjoint
 
-@pytest.mark.parametrize("nf,nt,nd", [(1, 30, 9), (8, 40, 16), (32, 64, 64), (64, 50, 90)])
+@pytest.mark.parametrize("nf,nt,nd", [(1, 30, 9), (8, 40, 16), (32, 64, 64), (64, 50, 90), (3, 30, 9), (12, 40, 30),
+                                      (100, 50, 64)])
 @pytest.mark.parametrize("band", [(1.2, 1.6), (0.4, 0.8)])
 def test_adjoint_dot_product_exact(nf, nt, nd, band):
     """<A x, y> = <x, A^T y>, exact in int64."""
@@ -457,7 +473,7 @@ def test_boxcar_binary32_tree_within_rounding():
 
 # ---------------------------------------------------------------- d_min pre-shift
 
-@pytest.mark.parametrize("nf,nd,d_min", [(16, 40, 100), (256, 128, 700), (1024, 256, 3000)])
+@pytest.mark.parametrize("nf,nd,d_min", [(16, 40, 100), (256, 128, 700), (1024, 256, 3000), (100, 64, 300)])
 @pytest.mark.parametrize("band", [(1.2, 1.6), (0.4, 0.8)])
 def test_dmin_path_follows_law_from_dmin(nf, nd, d_min, band):
     """Sec. 4.2 (different range of dispersions): with the pre-shift, row dt
