@@ -18,7 +18,13 @@
  *   - Option-1 initialisation: A_f(t, d) = sum_{i=0}^{d} I[f][t-i];
  *   - samples before t = 0 are zero (the alternative addition rule for t1 < 0),
  *     so outputs with t0 < dt are sums over the part of the path inside the record;
- *   - the rows each sub-band needs are derived top-down from Nd.
+ *   - the rows each sub-band needs are derived top-down from Nd;
+ *   - Nf need not be a power of two (Sec. 4.2, the case Nf != 2^k): iteration
+ *     l pairs sub-bands 2j and 2j+1 of the previous one, sub-band j holding
+ *     channels j*2^l .. min((j+1)*2^l, Nf) - 1, for ceil(log2 Nf) iterations;
+ *     halves of unequal width meet at their border frequency, f2 being the
+ *     upper edge of the sub-band's last channel, and a sub-band whose upper
+ *     half holds no channel is its lower half unchanged.
  *
  * Layout: all device arrays are dense, row-major, time fastest:
  *   forward input   [batch][Nf][Nt]   of the plan's input dtype
@@ -57,7 +63,7 @@ typedef struct fdmt_ragged_s *fdmt_ragged_t;
 typedef enum {
   FDMT_OK = 0,
   FDMT_E_INVALID = 1,     /* null pointer, size out of range, f_min >= f_max, f_min <= 0, ... */
-  FDMT_E_UNSUPPORTED = 2, /* Nf not a power of two, unsupported dtype pair, host-only plan */
+  FDMT_E_UNSUPPORTED = 2, /* unsupported dtype pair or schedule, host-only plan */
   FDMT_E_NOMEM = 3,       /* host or device allocation failed inside fdmt_plan() */
   FDMT_E_DEVICE = 4,      /* a HIP call or kernel launch failed */
   FDMT_E_WORKSPACE = 5    /* workspace null or smaller than fdmt_workspace_bytes() */
@@ -134,7 +140,8 @@ typedef struct {
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
  * sub-band needs are fixed before any data is seen) and the kernel schedule, then upload
  * the tables to the current HIP device.
- *   nf     channels, a power of two, 1 <= nf <= 65536
+ *   nf     channels, 1 <= nf <= 65536 (not a power of two: the initialisation
+ *          runs as its own step and every fused pass starts from its plane)
  *   nt     samples per beam, 1 <= nt <= 2^31 - 1
  *   nd     delay trials (output rows), 1 <= nd <= 65536
  *   f_min, f_max  band edges in any one unit, 0 < f_min < f_max
@@ -201,14 +208,18 @@ fdmt_status_t fdmt_run_step(fdmt_plan_t p, int32_t adjoint, int32_t step, const 
 /* Host copy of one sub-band's delay table (for inspection and table tests).
  * level 0: sub = channel, *n_rows = rows of its Option-1 partial sums, no
  *          triples are written.
- * level l in 1..log2(Nf): sub = sub-band index; for each row dt < *n_rows,
- *          d_lo[dt] = t0 - t1, s[dt] = shift of the upper half, d_hi[dt] = t1 - t2,
- *          written only if cap >= *n_rows (pointers may be NULL when cap = 0). */
+ * level l in 1..levels: sub = sub-band index (0 .. 2^(levels-l) - 1); for
+ *          each row dt < *n_rows, d_lo[dt] = t0 - t1, s[dt] = shift of the
+ *          upper half, d_hi[dt] = t1 - t2, written only if cap >= *n_rows
+ *          (pointers may be NULL when cap = 0). A sub-band without channels
+ *          has no rows; one whose upper half has none reports (dt, 0, -1).
+ * FDMT_E_INVALID for a level or sub-band out of range. */
 fdmt_status_t fdmt_plan_tables(fdmt_plan_t p, int32_t level, int32_t sub, int32_t *d_lo,
                                int32_t *s, int32_t *d_hi, int32_t cap, int32_t *n_rows);
 
-/* Plan shape: *levels = log2(Nf); rows_per_level[l] (l = 0..levels, if not NULL
- * and cap > levels) = total rows of iteration l's planes. */
+/* Plan shape: *levels = ceil(log2(Nf)); rows_per_level[l] (l = 0..levels, if
+ * not NULL and cap > levels) = total rows of iteration l's planes, including
+ * the single zero row kept for each sub-band position without channels. */
 fdmt_status_t fdmt_plan_info(fdmt_plan_t p, int32_t *levels, int64_t *rows_per_level, int32_t cap);
 
 /* Release the plan and its device tables (must not be in use by queued work). NULL is a no-op. */

@@ -185,7 +185,6 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   fdmt_options_t o{FDMT_F32, FDMT_F32, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (opt) o = *opt;
   if (nf < 1 || nf > 65536) return fail(FDMT_E_INVALID, "Nf must be in [1, 65536]");
-  if ((nf & (nf - 1)) != 0) return fail(FDMT_E_UNSUPPORTED, "Nf must be a power of two");
   if (nt < 1 || nt > INT32_MAX) return fail(FDMT_E_INVALID, "Nt must be in [1, 2^31 - 1]");
   if (nd < 1 || nd > 65536) return fail(FDMT_E_INVALID, "Nd must be in [1, 65536]");
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
@@ -391,7 +390,7 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
   switch (st.kind) {
     case fdmt::Step::Init:
       info->level_first = info->level_last = 0;
-      info->work_items = T.nf;
+      info->work_items = T.slots;
       info->bytes_read = static_cast<int64_t>(T.nf) * nt * in_b;
       info->bytes_written = T.total[0] * nt * 4;
       info->staged_bytes = info->bytes_read;
@@ -487,8 +486,11 @@ fdmt_status_t fdmt_plan_tables(fdmt_plan_t p, int32_t level, int32_t sub, int32_
   if (!p || !n_rows) return fail(FDMT_E_INVALID, "plan or n_rows is NULL");
   const fdmt::Tables &T = p->plan.tab;
   if (level < 0 || level > T.levels) return fail(FDMT_E_INVALID, "level out of range");
-  if (sub < 0 || sub >= (T.nf >> level)) return fail(FDMT_E_INVALID, "sub-band out of range");
-  const int32_t n = T.rows[level][sub];
+  if (sub < 0 || sub >= (T.slots >> level)) return fail(FDMT_E_INVALID, "sub-band out of range");
+  // positions without channels keep one zero row internally; reported as none
+  const bool empty = (static_cast<int64_t>(sub) << level) >= T.nf;
+  const bool copy = level > 0 && (static_cast<int64_t>(2 * sub + 1) << (level - 1)) >= T.nf;
+  const int32_t n = empty ? 0 : T.rows[level][sub];
   *n_rows = n;
   if (level == 0 || cap <= 0) return FDMT_OK;
   if (cap < n) return fail(FDMT_E_INVALID, "cap smaller than the row count");
@@ -496,8 +498,8 @@ fdmt_status_t fdmt_plan_tables(fdmt_plan_t p, int32_t level, int32_t sub, int32_
   const int64_t base = T.row_off[level][sub];
   for (int32_t dt = 0; dt < n; ++dt) {
     d_lo[dt] = T.d_lo[level][base + dt];
-    s[dt] = T.shift[level][base + dt];
-    d_hi[dt] = T.d_hi[level][base + dt];
+    s[dt] = copy ? 0 : T.shift[level][base + dt];
+    d_hi[dt] = copy ? -1 : T.d_hi[level][base + dt];
   }
   return FDMT_OK;
 }

@@ -25,7 +25,9 @@ constexpr int kTile = kThreads * kPerThread;  // samples per workgroup
 
 // ---------------------------------------------------------------------------
 // Option-1 initialisation (Sec. 4): row d of channel k holds
-// sum_{i=0}^{d} I[k][t - i], zero before t = 0. Grid: (channel, time tile, beam).
+// sum_{i=0}^{d} I[k][t - i], zero before t = 0. Grid: (channel position, time
+// tile, beam); a position without a channel has its input delayed past every
+// record and writes its row as zeros.
 template <typename Tin, typename Tacc, bool RAGGED>
 __global__ __launch_bounds__(kThreads) void init_kernel(
     const Tin *__restrict__ in, Tacc *__restrict__ out, const int32_t *__restrict__ leaf_off,
@@ -614,7 +616,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
   switch (st.kind) {
     case Step::Init:
       return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-        hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.nf, gy, gz), dim3(kThreads), 0, stream,
+        hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.slots, gy, gz), dim3(kThreads), 0, stream,
                            static_cast<const Tin *>(src.ptr), static_cast<Tacc *>(dst.ptr),
                            p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, nt, src.bstride, dst.stride, dst.bstride, rg);
         return hipSuccess;

@@ -351,7 +351,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
       ps.psum_offset = static_cast<int64_t>(s.psums.size());
       int max_stage = 0, max_rows = 0;
       int64_t leaf_max = 0, psum_max = 0;
-      for (int sub = 0; sub < (t.nf >> ps.l1); ++sub) {
+      for (int sub = 0; sub < (t.slots >> ps.l1); ++sub) {
         const int n = t.rows[ps.l1][sub];
         int r0 = 0;
         while (r0 < n) {
@@ -470,7 +470,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
     ps.head_offset = static_cast<int64_t>(s.heads.size());
     ps.rows_in = first ? t.nf : t.total[l0];
     ps.rows_out = t.total[ps.l1];
-    for (int sub = 0; sub < (t.nf >> ps.l1); ++sub) {
+    for (int sub = 0; sub < (t.slots >> ps.l1); ++sub) {
       const int n = t.rows[ps.l1][sub];
       int r0 = 0;
       while (r0 < n) {
@@ -512,6 +512,9 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
   const int L = t.levels;
   if (L == 0) return "";
   if (p.tile < 1 || p.first_levels < 1 || p.later_levels < 1) return "bad schedule parameters";
+  // Channel positions without a channel are zero rows of plane 0, which the
+  // initialisation writes; the passes start from there.
+  if (t.slots != t.nf) s.init_separate = true;
   int l0 = 0;
   while (l0 < L) {
     const bool first = l0 == 0 && !s.init_separate;

@@ -12,6 +12,14 @@
 // Other delay laws dt ~ f^gamma (Sec. 4.2, other functional forms) change
 // only C: the power -2 of Eq. (Cf2f0) becomes gamma.
 //
+// Nf need not be a power of two (Sec. 4.2, the case Nf != 2^k): the tree
+// keeps 2^ceil(log2 Nf) channel positions, and the positions past the last
+// channel are zero-width bands at its upper edge with no data. A merge whose
+// upper half is such a band has C = 1 exactly, so its rows are the lower
+// half's rows plus a zero: the lower half passes through unchanged. Every
+// other merge splits a band of unequal halves at their border, f2 being the
+// upper edge of its last channel. Bands without a channel have one row.
+//
 // A known smallest delay d_min (Sec. 4.2, different range of dispersions) is
 // a frequency-dependent shift of the input: channel k is delayed by
 // pre_k = round(d_min * phi(c_k)) samples, phi(f) = (f_min^g - f^g) /
@@ -42,7 +50,7 @@ int32_t round_half_up(double x) { return static_cast<int32_t>(std::floor(x + 0.5
 } // namespace
 
 std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma, int d_min) {
-  if (nf < 1 || (nf & (nf - 1)) != 0) return "Nf must be a power of two";
+  if (nf < 1) return "Nf must be >= 1";
   if (nd < 1) return "Nd must be >= 1";
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
     return "need 0 < f_min < f_max (finite)";
@@ -50,19 +58,21 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   if (d_min < 0) return "d_min must be >= 0";
   int levels = 0;
   while ((1 << levels) < nf) ++levels;
+  const int slots = 1 << levels;
 
   t = Tables();
   t.nf = nf;
   t.nd = nd;
   t.levels = levels;
+  t.slots = slots;
   t.f_min = f_min;
   t.f_max = f_max;
   t.gamma = gamma;
   t.d_min = d_min;
 
   const double df = (f_max - f_min) / nf;
-  std::vector<double> edge(nf + 1);
-  for (int k = 0; k <= nf; ++k) edge[k] = f_min + static_cast<double>(k) * df;
+  std::vector<double> edge(slots + 1);
+  for (int k = 0; k <= slots; ++k) edge[k] = f_min + static_cast<double>(k <= nf ? k : nf) * df;
 
   t.rows.assign(levels + 1, {});
   t.d_lo.assign(levels + 1, {});
@@ -74,7 +84,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   // of iteration l - 1.
   std::vector<std::vector<std::vector<int32_t>>> lo_of(levels + 1), hi_of(levels + 1);
   for (int l = levels; l >= 1; --l) {
-    const int nsub = nf >> l;
+    const int nsub = slots >> l;
     t.rows[l - 1].assign(2 * nsub, 0);
     lo_of[l].resize(nsub);
     hi_of[l].resize(nsub);
@@ -82,7 +92,8 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
       const double f0 = edge[static_cast<size_t>(j) << l];
       const double f1 = edge[static_cast<size_t>(2 * j + 1) << (l - 1)];
       const double f2 = edge[static_cast<size_t>(j + 1) << l];
-      const double c = merge_coefficient(f0, f1, f2, gamma);
+      // a band with no channel (f0 = f2) has only row 0, which any C maps to 0
+      const double c = f2 == f0 ? 0.0 : merge_coefficient(f0, f1, f2, gamma);
       const int32_t n = t.rows[l][j];
       auto &lo = lo_of[l][j];
       auto &hi = hi_of[l][j];
@@ -117,7 +128,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   t.merge.assign(levels + 1, {});
   t.adj.assign(levels + 1, {});
   for (int l = 1; l <= levels; ++l) {
-    const int nsub = nf >> l;
+    const int nsub = slots >> l;
     auto &m = t.merge[l];
     m.resize(t.total[l]);
     t.d_lo[l].resize(t.total[l]);
@@ -152,13 +163,14 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
       if (x.count == 0) return "child row with no parent";
   }
 
-  t.leaf_off.resize(nf);
-  t.leaf_rows.resize(nf);
-  for (int k = 0; k < nf; ++k) {
+  t.leaf_off.resize(slots);
+  t.leaf_rows.resize(slots);
+  for (int k = 0; k < slots; ++k) {
     t.leaf_off[k] = static_cast<int32_t>(t.row_off[0][k]);
     t.leaf_rows[k] = t.rows[0][k];
   }
-  t.pre.assign(nf, 0);
+  t.pre.assign(slots, kNoChannelPre);
+  for (int k = 0; k < nf; ++k) t.pre[k] = 0;
   if (d_min > 0) {
     const double den = law(f_min, gamma) - law(f_max, gamma);
     for (int k = 0; k < nf; ++k) {

@@ -22,8 +22,13 @@ struct AdjRow {
   int32_t first, count, upper, pad;
 };
 
+// Pre-shift of a channel position that holds no channel (Nf not a power of
+// two): its input lies past the end of every record, so it reads as zero.
+constexpr int32_t kNoChannelPre = INT32_MAX;
+
 struct Tables {
   int nf = 0, nd = 0, levels = 0;
+  int slots = 0;  // 2^levels channel positions; positions nf .. slots-1 hold no channel
   double f_min = 0, f_max = 0;
   double gamma = -2.0;  // delay law dt ~ f^gamma
   int32_t d_min = 0;    // smallest total delay searched; row dt is delay d_min + dt
@@ -40,10 +45,11 @@ struct Tables {
   std::vector<std::vector<MergeRow>> merge;
   // per iteration l >= 1: one AdjRow per row of plane l - 1
   std::vector<std::vector<AdjRow>> adj;
-  // per channel: first row of its partial sums in plane 0 and their count
+  // per channel position: first row of its partial sums in plane 0 and their count
   std::vector<int32_t> leaf_off, leaf_rows;
-  // per channel: the d_min pre-shift, the samples its input is delayed by
-  // before the transform (all 0 when d_min = 0)
+  // per channel position: the d_min pre-shift, the samples its input is
+  // delayed by before the transform (all 0 when d_min = 0; kNoChannelPre
+  // where there is no channel)
   std::vector<int32_t> pre;
 };
 

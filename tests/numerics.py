@@ -33,8 +33,9 @@ def adjoint_bound(grad, f_min, f_max, nf):
     for l in range(1, t.levels + 1):
         for trip in t.split[l]:
             for col in (0, 2):
-                vals = [x[col] for x in trip]
-                cmax = max(cmax, max(vals.count(v) for v in set(vals)))
+                vals = [x[col] for x in trip if x[col] is not None]  # a copy row has no upper half
+                if vals:
+                    cmax = max(cmax, max(vals.count(v) for v in set(vals)))
     nmax = max(t.rows[0])
     depth = t.levels * (cmax - 1) + nmax * (nmax + 1) // 2
     return _gamma(depth) * fdmt_adjoint(np.abs(grad), f_min, f_max, nf, t)

@@ -36,6 +36,9 @@ SHAPES = [  # nf, nt, nd, band
     (512, 2048, 96, (0.4, 0.8)),     # Nd << Nf
     (2, 500, 1999, (0.4, 0.8)),      # Nd >> Nf: ~1000 partial sums per channel
     (8, 3000, 2500, (1.0, 3.0)),
+    (3, 100, 7, (1.0, 2.0)),         # Nf not a power of two (Sec. 4.2)
+    (100, 3001, 300, (1.2, 1.6)),
+    (1000, 2000, 512, (0.4, 0.8)),
 ]
 
 

@@ -31,6 +31,7 @@ SHAPES = [  # nf, nd, band
     (256, 128, (1.2, 1.6)),
     (2, 500, (0.4, 0.8)),
     (1024, 512, (1.2, 1.6)),
+    (100, 128, (1.2, 1.6)),          # Nf not a power of two
 ]
 
 
