@@ -52,6 +52,10 @@ listed with its justification in the design notes):
          the run a row adds in a channel is centred on the curve's passage
          through it; row dt then follows total delay d_min + dt. The delay
          tables themselves are unchanged.
+  R-fft  Algorithm 2 (FFT-FDMT) prints its initialisation with I(f, t + i);
+         it is read as Algorithm 1's (reading R-init), since both algorithms
+         compute the same transform. Its time axis is zero-padded to
+         Nt + Nd - 1 samples, the least padding after which no path wraps.
   R-nf   Nf need not be a power of two (Sec. 4.2, the case Nf != 2^k): the
          iterations still pair sub-bands 2j and 2j+1, sub-band j of iteration
          l holding channels j*2^l .. min((j+1)*2^l, Nf) - 1, so there are
@@ -380,6 +384,55 @@ def brute_ideal(img, f_min, f_max, nd, gamma=-2.0):
             if sh < nt:
                 out[dt, sh:] += img[k, : nt - sh].astype(acc)
     return out
+
+
+# ----------------------------------------------------------------------------
+# FFT-FDMT (Algorithm 2): the same iterations with the time axis Fourier
+# transformed, where a shift by s becomes a product with the shift vector
+# V(w, s), the transform of a unit impulse at s.
+# ----------------------------------------------------------------------------
+
+def fft_length(nt, nd):
+    """Zero padding (Algorithm 2 comments): shifts become cyclic, so the time
+    axis is padded with at least Nd - 1 zeros; a path's samples lie in
+    [t0 - dt, t0] with dt <= Nd - 1, so nothing wraps onto the record."""
+    return nt + nd - 1
+
+
+def shift_vector(n, s):
+    """V(w, s) = F(delta_s)(w) for w = 0..n//2 (real-input half spectrum)."""
+    w = np.arange(n // 2 + 1)
+    return np.exp(-2j * np.pi * ((w * s) % n) / n)
+
+
+def fdmt_fft(img, f_min, f_max, nd, tables=None, n=None):
+    """Algorithm 2 in complex128: the Option-1 rows of every channel (reading
+    R-init, and R-dmin's pre-shift), zero-padded to n samples and Fourier
+    transformed along time; every iteration adds B_lo(w, d_lo) + B_hi(w, d_hi) *
+    V(w, s) (a copy node, reading R-nf, keeps B_lo); the last plane is
+    transformed back and cut to the record. With n >= fft_length(nt, nd) it
+    equals fdmt() up to rounding; a shorter n wraps the tail of the record
+    onto its start."""
+    img = np.asarray(img)
+    nf, nt = img.shape
+    if tables is None:
+        tables = build_tables(nf, nd, f_min, f_max)
+    n = fft_length(nt, nd) if n is None else n
+    planes = []
+    for a in initialize(img.astype(np.float64), tables):
+        padded = np.zeros((a.shape[0], n))
+        padded[:, :nt] = a
+        planes.append(np.fft.rfft(padded, axis=1))
+    for l in range(1, tables.levels + 1):
+        merged = []
+        for j in range(len(planes) // 2):
+            lower, upper = planes[2 * j], planes[2 * j + 1]
+            out = np.empty((tables.rows[l][j], n // 2 + 1), dtype=np.complex128)
+            for dt, (d_lo, s, d_hi) in enumerate(tables.split[l][j]):
+                out[dt] = lower[d_lo] if d_hi is None else lower[d_lo] + upper[d_hi] * shift_vector(n, s)
+            merged.append(out)
+        planes = merged
+    return np.fft.irfft(planes[0], n=n, axis=1)[:, :nt]
 
 
 # ----------------------------------------------------------------------------

@@ -10,7 +10,7 @@ import pytest
 
 from conftest import read_golden
 from oracle import (boxcar_search, brute_ideal, brute_point, brute_row, build_tables, fdmt,
-                    fdmt_adjoint, path)
+                    fdmt_adjoint, fdmt_fft, fft_length, path)
 import workloads as W
 
 BANDS = [(1.2, 1.6), (0.4, 0.8), (1.0, 2.0)]
@@ -535,3 +535,42 @@ def test_dmin_pulse_recovered_at_offset_row():
         i, j = np.unravel_index(np.argmax(out), out.shape)
         assert abs(i - dt0) <= 2 and abs(j - t_arr) <= 2, (dt0, i, j)
         assert out[i, j] >= 0.6 * nf
+
+
+# ---------------------------------------------------------------- FFT-FDMT (Algorithm 2)
+
+@pytest.mark.parametrize("nf,nt,nd,band,kw", [
+    (1, 40, 9, (1.2, 1.6), {}), (8, 100, 12, (1.2, 1.6), {}), (32, 50, 64, (0.4, 0.8), {}),
+    (64, 300, 100, (1.2, 1.6), {}), (12, 200, 40, (1.0, 2.0), {}), (100, 256, 90, (1.2, 1.6), {}),
+    (64, 300, 64, (1.2, 1.6), dict(d_min=150)), (64, 300, 64, (0.4, 0.8), dict(gamma=1.0))])
+def test_fft_fdmt_equals_shift_fdmt(nf, nt, nd, band, kw):
+    """Algorithm 2 computes the transform of Algorithm 1: on integer data its
+    complex128 result rounds to the exact int64 result (errors far below 1/2),
+    including partial paths, Nf != 2^k, the d_min pre-shift and other laws."""
+    x = _rng(nf + nt).integers(0, 256, size=(nf, nt))
+    t = build_tables(nf, nd, *band, **kw)
+    y = fdmt_fft(x, *band, nd, t)
+    ref = fdmt(x, *band, nd, t)
+    assert np.max(np.abs(y - ref)) < 1e-6 * max(1, np.max(np.abs(ref)))
+    np.testing.assert_array_equal(np.rint(y).astype(np.int64), ref)
+
+
+def test_fft_fdmt_without_padding_wraps():
+    """Zero padding (Algorithm 2 comments): the shifts are cyclic, so with no
+    padding an output reads the end of the record in place of the zeros before
+    it; the result is then the path sums with time taken modulo Nt (the
+    Option-1 runs themselves start at t = 0)."""
+    nf, nt, nd, band = 16, 64, 40, (1.2, 1.6)
+    x = _rng(3).integers(0, 100, size=(nf, nt))
+    t = build_tables(nf, nd, *band)
+    y = np.rint(fdmt_fft(x, *band, nd, t, n=nt)).astype(np.int64)
+    assert not np.array_equal(y, fdmt(x, *band, nd, t))
+    for dt in (0, 7, nd - 1):
+        for t0 in (0, 5, 30, nt - 1):
+            total = 0
+            for k, (sigma, delta) in enumerate(path(t, dt)):
+                tc = (t0 - sigma) % nt
+                total += sum(int(x[k, tc - i]) for i in range(delta + 1) if tc - i >= 0)
+            assert y[dt, t0] == total, (dt, t0)
+    np.testing.assert_array_equal(np.rint(fdmt_fft(x, *band, nd, t, n=fft_length(nt, nd))).astype(np.int64),
+                                  fdmt(x, *band, nd, t))
