@@ -220,6 +220,27 @@ def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0)}
 
 
+def fft_fdmt(F, torch, w, shift_ms, reps=5):
+    """FFT-FDMT (Algorithm 2) forward of the FP32-input form: time per call
+    against the shift-based forward of the same input."""
+    plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, fft=True)
+    x = torch.randn(w.nf, w.nt, device="cuda", generator=torch.Generator(device="cuda").manual_seed(12))
+    y = torch.empty(w.nd, w.nt, device="cuda")
+    ws = plan.fft_workspace()
+    plan.forward_fft(x, out=y, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.forward_fft(x, out=y, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0),
+            "shift_forward_ms": shift_ms, "slowdown_vs_shift": round(ms / shift_ms, 2),
+            "workspace_gb": round(ws.numel() / 1e9, 2)}
+
+
 def ragged_c4(F, torch, W, reps=5):
     """The ragged workload: 256 beams, Nf=1024, Nd=512, Nt log-uniform in
     [2048, 32768], FP32 in and out. Times the ragged forward and adjoint (one
@@ -372,6 +393,8 @@ def main():
             if name in acc:
                 form["accuracy_vs_oracle"] = acc[name]
         out["precision_forms"] = forms
+        out["fft_fdmt"] = fft_fdmt(F, torch, w, forms["f32_in_f32_acc"]["ms"])
+        torch.cuda.empty_cache()
         if "adjoint_f32" in acc:
             out["adjoint"]["accuracy_vs_oracle"] = acc["adjoint_f32"]
     out["boxcar"] = boxcar_on_output(F, torch, y)

@@ -91,6 +91,11 @@ typedef enum {
                                       planes between two cache gathers as uint16 while
                                       every sum on them is below 2^16 (exact integers,
                                       same results, half the bytes) */
+#define FDMT_PLAN_FFT 0x8u         /* also build the FFT-FDMT state (Sec. 5, Algorithm 2)
+                                      for fdmt_forward_fft(): FP32 accumulation only, the
+                                      padded FFT length (the smallest 2^a 3^b 5^c >=
+                                      Nt + Nd - 1) at most 2^24; allocates its shift-vector
+                                      table and hipFFT plans with the plan */
 
 /* Options of a plan. Zero in any schedule field selects the built-in default;
  * schedule fields change only the kernel schedule, never the results. */
@@ -193,6 +198,21 @@ typedef struct {
   int32_t in_elem_bytes; /* bytes per element of what the step reads (input or plane) */
   int32_t out_elem_bytes;/* bytes per element of what the step writes */
 } fdmt_step_info_t;
+
+/* FFT-FDMT (Sec. 5, Algorithm 2): the same transform as fdmt_forward(), with
+ * the time axis Fourier transformed so that every shift is a product with a
+ * shift vector exp(-2 pi i w s / n). The Option-1 rows are zero-padded to n
+ * samples (n >= Nt + Nd - 1, so no path wraps), transformed by hipFFT, merged
+ * per frequency bin over all iterations, transformed back and scaled by 1/n.
+ * Results equal fdmt_forward()'s up to FP32 rounding of the transforms (not
+ * bit for bit). The plan must have been created with FDMT_PLAN_FFT; beams run
+ * one after another through the workspace, whose size does not depend on
+ * batch. Calls on one plan must not overlap (the hipFFT plans hold one work
+ * area). Arguments and layouts as for fdmt_forward().
+ * FDMT_E_INVALID for a plan without the FFT state. */
+size_t fdmt_fft_workspace_bytes(fdmt_plan_t p, int32_t batch);
+fdmt_status_t fdmt_forward_fft(fdmt_plan_t p, const void *in, void *out, int32_t batch, void *ws,
+                               size_t ws_bytes, void *hip_stream);
 
 /* Number of steps of the forward (adjoint = 0) or adjoint (adjoint = 1)
  * transform; -1 if p is NULL. */

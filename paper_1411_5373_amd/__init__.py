@@ -5,7 +5,7 @@ only marshals tensors and streams into its C ABI.
 """
 from .binding import (EXPORTED, FDMTError, FDMTFunction, Plan, RaggedPlan, boxcar_search, fdmt,
                       fdmt_adjoint, fdmt_boxcar_search, fdmt_boxcar_workspace_bytes,
-                      fdmt_forward, fdmt_last_error, fdmt_plan, fdmt_plan_destroy, fdmt_plan_info,
+                      fdmt_fft_workspace_bytes, fdmt_forward, fdmt_forward_fft, fdmt_last_error, fdmt_plan, fdmt_plan_destroy, fdmt_plan_info,
                       fdmt_plan_tables, fdmt_ragged_adjoint, fdmt_ragged_destroy,
                       fdmt_ragged_forward, fdmt_ragged_info, fdmt_ragged_plan,
                       fdmt_ragged_run_step, fdmt_ragged_workspace_bytes, fdmt_run_step,

@@ -21,6 +21,7 @@ FDMT_F32, FDMT_F16, FDMT_U8, FDMT_I32 = range(4)
 FDMT_PLAN_HOST_ONLY = 0x1
 FDMT_PLAN_UNFUSED = 0x2
 FDMT_PLAN_WIDE_PLANES = 0x4
+FDMT_PLAN_FFT = 0x8
 
 EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_step_count", "fdmt_step_info", "fdmt_run_step",
@@ -28,7 +29,7 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
-            "fdmt_status_string", "fdmt_last_error")
+            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_status_string", "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
               "input_gather", "staged_gather", "adjoint_gather")
@@ -116,6 +117,10 @@ def load():
     lib.fdmt_ragged_info.restype = ctypes.c_int
     lib.fdmt_ragged_destroy.argtypes = [vp]
     lib.fdmt_ragged_destroy.restype = ctypes.c_int
+    lib.fdmt_fft_workspace_bytes.argtypes = [vp, i32]
+    lib.fdmt_fft_workspace_bytes.restype = sz
+    lib.fdmt_forward_fft.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.fdmt_forward_fft.restype = ctypes.c_int
     lib.fdmt_boxcar_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.fdmt_boxcar_workspace_bytes.restype = sz
     lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
@@ -174,6 +179,15 @@ def fdmt_forward(plan, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
 def fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, batch, ws_ptr, ws_bytes, stream):
     _check(load().fdmt_adjoint(plan, grad_out_ptr, grad_in_ptr, int(batch), ws_ptr, int(ws_bytes),
                                stream), "fdmt_adjoint")
+
+
+def fdmt_fft_workspace_bytes(plan, batch=1):
+    return int(load().fdmt_fft_workspace_bytes(plan, int(batch)))
+
+
+def fdmt_forward_fft(plan, in_ptr, out_ptr, batch, ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_forward_fft(plan, in_ptr, out_ptr, int(batch), ws_ptr, int(ws_bytes), stream),
+           "fdmt_forward_fft")
 
 
 def fdmt_boxcar_workspace_bytes(batch, nd, nt, max_log2):
@@ -282,9 +296,10 @@ class Plan:
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
                  host_only=False, unfused=False, tuned=False, wide_planes=False, gamma=-2.0, d_min=0,
-                 **schedule):
+                 fft=False, **schedule):
         """`gamma`: the delay law dt ~ f^gamma (-2: cold plasma). `d_min`: the
-        smallest delay searched (row dt is delay d_min + dt). `schedule`:
+        smallest delay searched (row dt is delay d_min + dt). `fft`: also build
+        the FFT-FDMT state for forward_fft(). `schedule`:
         fdmt_options_t schedule fields (first_kernel, first_levels, ...).
         tuned=True first takes the autotuner's stored options for this
         workload, if any; explicit schedule fields override them."""
@@ -294,7 +309,7 @@ class Plan:
         self.d_min = int(d_min)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
         flags = ((FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0) |
-                 (FDMT_PLAN_WIDE_PLANES if wide_planes else 0))
+                 (FDMT_PLAN_WIDE_PLANES if wide_planes else 0) | (FDMT_PLAN_FFT if fft else 0))
         self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
         self.tuned = None
         if tuned and not host_only and not unfused:
@@ -349,6 +364,14 @@ class Plan:
 
     def adjoint(self, g, out=None, ws=None):
         return self._run(fdmt_adjoint, g, out, self.nd, self.nf, self.acc_dtype, self.acc_dtype, ws)
+
+    def fft_workspace(self):
+        return torch.empty(max(fdmt_fft_workspace_bytes(self.handle), 1), dtype=torch.uint8, device=self.device)
+
+    def forward_fft(self, x, out=None, ws=None):
+        """FFT-FDMT (Algorithm 2) of x; the plan needs fft=True."""
+        return self._run(fdmt_forward_fft, x, out, self.nf, self.nd, self.in_dtype, self.acc_dtype,
+                         self.fft_workspace() if ws is None else ws)
 
     def steps(self, adjoint=False):
         """Per-kernel description of the forward (or adjoint) launch sequence."""

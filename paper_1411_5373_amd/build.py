@@ -28,7 +28,8 @@ HIP_FLAGS = [
 CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_gather.hip", "fdmt_narrow.hip", "fdmt_adjoint.hip", "fdmt_boxcar.hip",
-               "fdmt_api.hip"]
+               "fdmt_fft.hip", "fdmt_api.hip"]
+LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]  # FFT-FDMT's transforms
 CXX_SOURCES = ["fdmt_tables.cpp", "fdmt_schedule.cpp"]
 
 
@@ -53,7 +54,7 @@ def build(verbose: bool = False) -> str:
         list(pool.map(lambda cmd: _run(cmd, verbose), jobs))
     objs = [cmd[-1] for cmd in jobs]
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

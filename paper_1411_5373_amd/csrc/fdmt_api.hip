@@ -9,6 +9,7 @@
 
 #include "../../include/fdmt.h"
 #include "fdmt_boxcar.h"
+#include "fdmt_fft.h"
 #include "fdmt_plan.h"
 
 struct fdmt_plan_s {
@@ -210,8 +211,10 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (o.d_min < 0) return fail(FDMT_E_INVALID, "d_min must be >= 0");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
-  if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES))
+  if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES | FDMT_PLAN_FFT))
     return fail(FDMT_E_INVALID, "unknown option flag");
+  if ((o.flags & FDMT_PLAN_FFT) && o.acc_dtype != FDMT_F32)
+    return fail(FDMT_E_UNSUPPORTED, "FFT-FDMT accumulates in FP32 only");
   if (!pair_supported(o.in_dtype, o.acc_dtype))
     return fail(FDMT_E_UNSUPPORTED, "unsupported (input, accumulation) dtype pair");
 
@@ -327,15 +330,50 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     delete h;
     return fail(FDMT_E_UNSUPPORTED, "Nt too long for the time tile (more than 65535 tiles)");
   }
+  if ((o.flags & FDMT_PLAN_FFT) && fdmt::fft_length(nt, nd) > fdmt::kFftMaxLength) {
+    delete h;
+    return fail(FDMT_E_UNSUPPORTED, "FFT-FDMT length Nt + Nd - 1 above 2^24 samples");
+  }
   if (!(o.flags & FDMT_PLAN_HOST_ONLY)) {
-    const fdmt_status_t s = upload(p);
+    fdmt_status_t s = upload(p);
+    if (s == FDMT_OK && (o.flags & FDMT_PLAN_FFT)) {
+      const std::string err = fdmt::fft_create(p);
+      if (!err.empty()) s = fail(FDMT_E_DEVICE, "FFT-FDMT: " + err);
+    }
     if (s != FDMT_OK) {
+      fdmt::fft_destroy(p);
       if (p.dbuf) (void)hipFree(p.dbuf);
       delete h;
       return s;
     }
   }
   *out = h;
+  return FDMT_OK;
+}
+
+size_t fdmt_fft_workspace_bytes(fdmt_plan_t p, int32_t batch) {
+  if (!p || batch < 1) return 0;
+  return fdmt::fft_workspace_bytes(p->plan);
+}
+
+fdmt_status_t fdmt_forward_fft(fdmt_plan_t p, const void *in, void *out, int32_t batch, void *ws,
+                               size_t ws_bytes, void *hip_stream) {
+  if (!p) return fail(FDMT_E_INVALID, "plan is NULL");
+  if (!p->plan.fft) return fail(FDMT_E_INVALID, "plan was built without FDMT_PLAN_FFT");
+  if (!in || !out) return fail(FDMT_E_INVALID, "input or output pointer is NULL");
+  if (in == out) return fail(FDMT_E_INVALID, "input and output alias");
+  if (batch < 1 || batch > 65535) return fail(FDMT_E_INVALID, "batch must be in [1, 65535]");
+  const size_t need = fdmt::fft_workspace_bytes(p->plan);
+  if (!ws || ws_bytes < need)
+    return fail(FDMT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
+                                      std::to_string(ws ? ws_bytes : 0));
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(FDMT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev != p->plan.device) return fail(FDMT_E_INVALID, "current device differs from the plan's device");
+  const std::string err = fdmt::launch_forward_fft(p->plan, in, out, batch, ws, static_cast<hipStream_t>(hip_stream));
+  if (!err.empty()) return fail(FDMT_E_DEVICE, "fdmt_forward_fft: " + err);
   return FDMT_OK;
 }
 
@@ -516,6 +554,7 @@ fdmt_status_t fdmt_plan_info(fdmt_plan_t p, int32_t *levels, int64_t *rows_per_l
 fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p) {
   if (!p) return FDMT_OK;
   fdmt_status_t s = FDMT_OK;
+  fdmt::fft_destroy(p->plan);
   if (p->plan.dbuf) {
     hipError_t e = hipFree(p->plan.dbuf);
     if (e != hipSuccess) s = device_fail(e, "hipFree of delay tables");

@@ -952,6 +952,30 @@ hipError_t run_step(const Plan &p, bool adjoint, int i, const void *in, void *ou
   }
 }
 
+hipError_t launch_init_f32(const Plan &p, const void *in, float *plane0, int64_t stride, hipStream_t stream) {
+  const dim3 grid(static_cast<unsigned>(p.tab.slots), static_cast<unsigned>((p.nt + kTile - 1) / kTile), 1);
+  const int64_t in_bstride = p.tab.nf * p.nt, out_bstride = p.tab.total[0] * stride;
+  switch (p.in_dtype) {
+    case FDMT_F32:
+      hipLaunchKernelGGL((init_kernel<float, float, false>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const float *>(in), plane0, p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, p.nt,
+                         in_bstride, stride, out_bstride, RaggedMap{});
+      break;
+    case FDMT_F16:
+      hipLaunchKernelGGL((init_kernel<_Float16, float, false>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const _Float16 *>(in), plane0, p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, p.nt,
+                         in_bstride, stride, out_bstride, RaggedMap{});
+      break;
+    case FDMT_U8:
+      hipLaunchKernelGGL((init_kernel<uint8_t, float, false>), grid, dim3(kThreads), 0, stream,
+                         static_cast<const uint8_t *>(in), plane0, p.dev.leaf_off, p.dev.leaf_rows, p.dev.pre, p.nt,
+                         in_bstride, stride, out_bstride, RaggedMap{});
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
                           hipStream_t stream, const RaggedBatch *rb) {
   for (size_t i = 0; i < p.fwd_steps.size(); ++i) {

@@ -25,6 +25,8 @@ struct DeviceTables {
   const int32_t *pre = nullptr;   // per channel: d_min pre-shift
 };
 
+struct FftPlan;  // FFT-FDMT state (fdmt_fft.hip)
+
 // Where a step reads or writes: the caller's input/output or one of the two
 // workspace planes.
 enum class Buf { In, Out, Ws0, Ws1 };
@@ -69,6 +71,7 @@ struct Plan {
   std::vector<uint8_t> int_sums; // per forward pass: uint8 input or uint16 planes in, sums integers below 2^24
   std::vector<Step> fwd_steps, adj_steps;
   int64_t ws_rows = 0;         // rows of each workspace plane
+  FftPlan *fft = nullptr;      // FFT-FDMT state (FDMT_PLAN_FFT plans only)
 };
 
 // Beams of different lengths packed back to back: beam b's [rows][Nt_b]
@@ -103,6 +106,9 @@ int step_tile(const Plan &p, bool adjoint, int step);
 // Output rows per workgroup of adjoint register-gather pass `pass`.
 int adjoint_rows(const Plan &p, int pass);
 size_t workspace_bytes(const Plan &p, int batch);
+// Option-1 rows of every channel position of one beam into FP32 rows of
+// `stride` elements (samples t < nt; the rest of each row is untouched).
+hipError_t launch_init_f32(const Plan &p, const void *in, float *plane0, int64_t stride, hipStream_t stream);
 // Sets the dynamic-LDS limit of the fused kernels the plan uses.
 hipError_t prepare_kernels(const Plan &p);
 

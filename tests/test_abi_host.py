@@ -337,3 +337,22 @@ def test_uint16_planes_start_at_the_input_gather():
     ins = [s["in_elem_bytes"] for s in q.steps()]
     assert outs[0] == 2 and ins[1:] == outs[:-1]
     assert outs == sorted(outs)  # narrow planes form one run from the input
+
+
+def test_fft_plan_rules():
+    """FFT-FDMT plans: FP32 accumulation only, a length limit, and the entry
+    point refuses a plan built without the FFT state before touching the device."""
+    import torch
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, fft=True, in_dtype=torch.int32, acc_dtype=torch.int32)
+    assert e.value.status == B.FDMT_E_UNSUPPORTED and "FFT" in F.fdmt_last_error()
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(1, 16_770_000, 65536, 1.2, 1.6, host_only=True, fft=True)
+    assert e.value.status == B.FDMT_E_UNSUPPORTED
+    p = F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, fft=True)
+    assert F.fdmt_fft_workspace_bytes(p.handle) == 0           # no FFT state without a device
+    lib = B.load()
+    x, o, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.fdmt_forward_fft(p.handle, x, o, 1, ws, 1 << 30, None) == B.FDMT_E_INVALID
+    assert "FDMT_PLAN_FFT" in F.fdmt_last_error()
+    assert lib.fdmt_forward_fft(None, x, o, 1, ws, 1 << 30, None) == B.FDMT_E_INVALID
