@@ -4,6 +4,10 @@
 // then adds, at every frequency bin w of the time axis,
 //   B_out(w) = B_lo(w) + B_hi(w) * V(w, s),  V(w, s) = exp(-2 pi i w s / n),
 // the transform of a unit impulse at s, so all additions stay within one bin.
+// Iterations run kFftLevels at a time: an output row of plane l1 is the sum of
+// its 2^k terms of plane l0 (the rows the recursion reaches, each with its
+// accumulated shift sigma), each times V(w, sigma), which is the recursion
+// with its shifts composed (V(w, a) V(w, b) = V(w, a + b)).
 // The last plane is transformed back (complex to real), scaled by 1/n and cut
 // to the record. The padding makes the cyclic shifts of the transform equal
 // the zero-history shifts of the direct algorithm: a path reads samples in
@@ -24,6 +28,10 @@
 namespace fdmt {
 
 struct FftPlan {
+  struct Pass {
+    int l0, l1;           // consumes plane l0, produces plane l1
+    int64_t term_offset;  // first (row, shift) term of this pass, 2^(l1-l0) per output row
+  };
   int64_t n = 0;        // FFT length: the record plus its zero padding
   int64_t rpitch = 0;   // reals per time-domain row
   int64_t nbins = 0;    // n / 2 + 1 complex bins of a real row's transform
@@ -31,12 +39,15 @@ struct FftPlan {
   int64_t rows0 = 0;    // rows of plane 0 (Option-1 rows of every channel position)
   hipfftHandle r2c = nullptr, c2r = nullptr;
   float2 *twiddle = nullptr;  // V(1, k) = exp(-2 pi i k / n), k < n
+  int2 *terms = nullptr;      // every pass's terms
+  std::vector<Pass> passes;
 };
 
 namespace {
 
 constexpr int kFftThreads = 256;
 constexpr int kBinsPerThread = 4;
+constexpr int kFftLevels = 3;  // iterations per frequency-domain pass
 
 const char *fft_error(hipfftResult r) {
   switch (r) {
@@ -56,38 +67,50 @@ __global__ __launch_bounds__(kFftThreads) void pad_tail_kernel(float *__restrict
   for (int64_t t = from + threadIdx.x; t < pitch; t += kFftThreads) row[t] = 0.0f;
 }
 
-// One iteration in the frequency domain. Grid: (row of plane l, bin tile).
-// A thread takes kBinsPerThread consecutive bins w; the shift vector's index
-// w * s mod n is formed once and then stepped by s (s < n).
-__global__ __launch_bounds__(kFftThreads) void fft_merge_kernel(const float2 *__restrict__ prev,
-                                                                float2 *__restrict__ next,
-                                                                const int4 *__restrict__ rows,
-                                                                const float2 *__restrict__ tw, int64_t n,
-                                                                int64_t cpitch, int64_t nbins) {
+// k iterations in the frequency domain. Grid: (row of plane l1, bin tile).
+// A thread takes kBinsPerThread consecutive bins w0 .. w0+3. For each term it
+// looks up V(w0, sigma) once (index w0 * sigma mod n, through a float64
+// quotient corrected by one step) and reaches the next bins by multiplying
+// with V(1, sigma), the same for every thread: one scattered table read per
+// term instead of four.
+template <int K>
+__global__ __launch_bounds__(kFftThreads) void fft_gather_kernel(const float2 *__restrict__ prev,
+                                                                 float2 *__restrict__ next,
+                                                                 const int2 *__restrict__ terms,
+                                                                 const float2 *__restrict__ tw, int64_t n,
+                                                                 double inv_n, int64_t cpitch, int64_t nbins) {
+  constexpr int N = 1 << K;
   const int64_t r = blockIdx.x;
   const int64_t w0 = (static_cast<int64_t>(blockIdx.y) * kFftThreads + threadIdx.x) * kBinsPerThread;
   if (w0 >= nbins) return;
-  const int4 m = rows[r];  // {lower row, upper row, shift, sub-band}
-  const float4 *lo = reinterpret_cast<const float4 *>(prev + m.x * cpitch + w0);
-  const float4 *hi = reinterpret_cast<const float4 *>(prev + m.y * cpitch + w0);
-  // the row pitch is a multiple of 64 bins, so all four bins lie in the row
-  const float4 a0 = lo[0], a1 = lo[1], b0 = hi[0], b1 = hi[1];
-  const float2 av[4] = {{a0.x, a0.y}, {a0.z, a0.w}, {a1.x, a1.y}, {a1.z, a1.w}};
-  const float2 bv[4] = {{b0.x, b0.y}, {b0.z, b0.w}, {b1.x, b1.y}, {b1.z, b1.w}};
-  const int64_t s = m.z;
-  int64_t k = (w0 * s) % n;
-  float2 o[4];
+  const int2 *tm = terms + r * N;
+  float2 acc[kBinsPerThread];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float2 v = tw[k];
-    o[q].x = av[q].x + (bv[q].x * v.x - bv[q].y * v.y);
-    o[q].y = av[q].y + (bv[q].x * v.y + bv[q].y * v.x);
-    k += s;
+  for (int q = 0; q < kBinsPerThread; ++q) acc[q] = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int2 e = tm[j];  // {plane-l0 row, accumulated shift}
+    // the row pitch is a multiple of 64 bins, so all four bins lie in the row
+    const float4 *src = reinterpret_cast<const float4 *>(prev + e.x * cpitch + w0);
+    const float4 b0 = src[0], b1 = src[1];
+    const float2 bv[4] = {{b0.x, b0.y}, {b0.z, b0.w}, {b1.x, b1.y}, {b1.z, b1.w}};
+    const int64_t s = e.y;
+    const int64_t x = w0 * s;
+    int64_t k = x - static_cast<int64_t>(static_cast<double>(x) * inv_n) * n;
+    if (k < 0) k += n;
     if (k >= n) k -= n;
+    float2 v = tw[k];
+    const float2 step = tw[s];
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) {
+      acc[q].x += bv[q].x * v.x - bv[q].y * v.y;
+      acc[q].y += bv[q].x * v.y + bv[q].y * v.x;
+      v = make_float2(v.x * step.x - v.y * step.y, v.x * step.y + v.y * step.x);
+    }
   }
   float4 *out = reinterpret_cast<float4 *>(next + r * cpitch + w0);
-  out[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
-  out[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+  out[0] = make_float4(acc[0].x, acc[0].y, acc[1].x, acc[1].y);
+  out[1] = make_float4(acc[2].x, acc[2].y, acc[3].x, acc[3].y);
 }
 
 // out[r][t] = real[r][t] / n for t < nt (the inverse transform is unscaled).
@@ -144,6 +167,37 @@ std::string fft_create(Plan &p) {
     f->c2r = nullptr;
     return std::string("inverse FFT plan: ") + fft_error(r);
   }
+  // Terms of each pass: walking the merge rows down from every output row of
+  // plane l1 to plane l0, the upper half of each merge adding its shift.
+  std::vector<int2> terms, cur, nxt;
+  for (int l0 = 0; l0 < T.levels; l0 += kFftLevels) {
+    const int l1 = std::min(l0 + kFftLevels, T.levels);
+    f->passes.push_back({l0, l1, static_cast<int64_t>(terms.size())});
+    for (int64_t row = 0; row < T.total[l1]; ++row) {
+      cur.assign(1, make_int2(static_cast<int>(row), 0));
+      for (int l = l1; l > l0; --l) {
+        nxt.clear();
+        for (const int2 &x : cur) {
+          const MergeRow &m = T.merge[l][x.x];
+          nxt.push_back(make_int2(m.lo, x.y));
+          nxt.push_back(make_int2(m.hi, x.y + m.s));
+        }
+        cur.swap(nxt);
+      }
+      for (const int2 &x : cur)
+        if (x.x < 0 || x.x >= T.total[l0] || x.y < 0 || x.y >= f->n) return "frequency-domain term out of range";
+      terms.insert(terms.end(), cur.begin(), cur.end());
+    }
+  }
+  if (!terms.empty()) {
+    e = hipMalloc(&f->terms, terms.size() * sizeof(int2));
+    if (e != hipSuccess) {
+      f->terms = nullptr;
+      return std::string("hipMalloc of the frequency-domain terms: ") + hipGetErrorString(e);
+    }
+    e = hipMemcpy(f->terms, terms.data(), terms.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return std::string("hipMemcpy of the frequency-domain terms: ") + hipGetErrorString(e);
+  }
   return "";
 }
 
@@ -153,6 +207,7 @@ void fft_destroy(Plan &p) {
   if (f->r2c) hipfftDestroy(f->r2c);
   if (f->c2r) hipfftDestroy(f->c2r);
   if (f->twiddle) (void)hipFree(f->twiddle);
+  if (f->terms) (void)hipFree(f->terms);
   delete f;
   p.fft = nullptr;
 }
@@ -193,14 +248,30 @@ std::string launch_forward_fft(const Plan &p, const void *in, void *out, int bat
     }
     hipfftResult r = hipfftExecR2C(f->r2c, real, reinterpret_cast<hipfftComplex *>(spec[0]));
     if (r != HIPFFT_SUCCESS) return std::string("forward FFT: ") + fft_error(r);
-    for (int l = 1; l <= T.levels; ++l) {
-      hipLaunchKernelGGL(fft_merge_kernel, dim3(static_cast<unsigned>(T.total[l]), bin_tiles), dim3(kFftThreads), 0,
-                         stream, spec[(l - 1) & 1], spec[l & 1], p.dev.merge[l], f->twiddle, f->n, f->cpitch,
-                         f->nbins);
+    const double inv_n = 1.0 / static_cast<double>(f->n);
+    int cur = 0;
+    for (const FftPlan::Pass &ps : f->passes) {
+      const dim3 grid(static_cast<unsigned>(T.total[ps.l1]), bin_tiles);
+      const int2 *tm = f->terms + ps.term_offset;
+      switch (ps.l1 - ps.l0) {
+        case 1:
+          hipLaunchKernelGGL(fft_gather_kernel<1>, grid, dim3(kFftThreads), 0, stream, spec[cur], spec[cur ^ 1], tm,
+                             f->twiddle, f->n, inv_n, f->cpitch, f->nbins);
+          break;
+        case 2:
+          hipLaunchKernelGGL(fft_gather_kernel<2>, grid, dim3(kFftThreads), 0, stream, spec[cur], spec[cur ^ 1], tm,
+                             f->twiddle, f->n, inv_n, f->cpitch, f->nbins);
+          break;
+        default:
+          hipLaunchKernelGGL(fft_gather_kernel<kFftLevels>, grid, dim3(kFftThreads), 0, stream, spec[cur],
+                             spec[cur ^ 1], tm, f->twiddle, f->n, inv_n, f->cpitch, f->nbins);
+          break;
+      }
       e = hipGetLastError();
-      if (e != hipSuccess) return std::string("frequency-domain iteration: ") + hipGetErrorString(e);
+      if (e != hipSuccess) return std::string("frequency-domain pass: ") + hipGetErrorString(e);
+      cur ^= 1;
     }
-    r = hipfftExecC2R(f->c2r, reinterpret_cast<hipfftComplex *>(spec[T.levels & 1]), real);
+    r = hipfftExecC2R(f->c2r, reinterpret_cast<hipfftComplex *>(spec[cur]), real);
     if (r != HIPFFT_SUCCESS) return std::string("inverse FFT: ") + fft_error(r);
     const unsigned gx = static_cast<unsigned>((p.nt + kFftThreads - 1) / kFftThreads);
     const unsigned gy = static_cast<unsigned>(std::min<int64_t>(T.nd, 65535));
