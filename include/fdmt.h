@@ -145,8 +145,9 @@ typedef struct {
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
  * sub-band needs are fixed before any data is seen) and the kernel schedule, then upload
  * the tables to the current HIP device.
- *   nf     channels, 1 <= nf <= 65536 (not a power of two: the initialisation
- *          runs as its own step and every fused pass starts from its plane)
+ *   nf     channels, 1 <= nf <= 65536 (not a power of two: the forward first
+ *          copies the input into the workspace with zero rows up to the next
+ *          power of two, and every schedule runs on that copy)
  *   nt     samples per beam, 1 <= nt <= 2^31 - 1
  *   nd     delay trials (output rows), 1 <= nd <= 65536
  *   f_min, f_max  band edges in any one unit, 0 < f_min < f_max
@@ -186,7 +187,9 @@ typedef struct {
                             init, 5 iterations as a gather through the caches, 6 the init
                             and iterations as a gather from the input, 7 iterations as a
                             staged gather, 8 transposes of several iterations (and of the
-                            init, in the last pass) as a gather */
+                            init, in the last pass) as a gather, 9 copy of the input into
+                            the workspace with a zero row for each channel position past
+                            Nf (Nf not a power of two) */
   int32_t level_first;   /* first iteration covered (0 = the initialisation) */
   int32_t level_last;    /* last iteration covered */
   int32_t work_items;    /* workgroups per beam */

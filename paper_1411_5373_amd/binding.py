@@ -32,7 +32,7 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_status_string", "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
-              "input_gather", "staged_gather", "adjoint_gather")
+              "input_gather", "staged_gather", "adjoint_gather", "pad_input")
 
 _TORCH_TO_CODE = {torch.float32: FDMT_F32, torch.float16: FDMT_F16,
                   torch.uint8: FDMT_U8, torch.int32: FDMT_I32}

@@ -162,7 +162,7 @@ fdmt_status_t check_ragged(fdmt_ragged_t r, const void *a, const void *b, void *
   if (r->rb.sum_nt == 0) return FDMT_OK;  // nothing to read or write
   if (!a || !b) return fail(FDMT_E_INVALID, "input or output pointer is NULL");
   if (a == b) return fail(FDMT_E_INVALID, "input and output alias");
-  const size_t need = static_cast<size_t>(2) * r->plan->plan.ws_rows * r->rb.sum_ntp * 4;
+  const size_t need = fdmt::ragged_workspace_bytes(r->plan->plan, r->rb);
   if (need > 0 && (!ws || ws_bytes < need))
     return fail(FDMT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
                                       std::to_string(ws ? ws_bytes : 0));
@@ -315,6 +315,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     for (int32_t r : p.tab.rows[a.l1]) rows = std::max<int64_t>(rows, r);
     if (o.acc_dtype == FDMT_I32 || 255 * ((int64_t(1) << a.l1) + rows - 1) < (int64_t(1) << 24)) p.int_sums[i] = 1;
   }
+  p.pad_input = p.tab.slots != p.tab.nf;
   fdmt::plan_steps(p);
   // Time tiles of uniform batches run along the grid's y dimension (at most
   // 65535 workgroups).
@@ -418,7 +419,8 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
   *info = fdmt_step_info_t{};
   info->kind = static_cast<int32_t>(st.kind);
   // unless set below: reads the input (init) or a 4-byte plane, writes 4-byte elements
-  info->in_elem_bytes = st.kind == fdmt::Step::Init ? static_cast<int32_t>(in_b) : 4;
+  info->in_elem_bytes =
+      st.kind == fdmt::Step::Init || st.kind == fdmt::Step::PadIn ? static_cast<int32_t>(in_b) : 4;
   info->out_elem_bytes = 4;
   auto init_adds = [&]() {
     int64_t a = 0;
@@ -426,6 +428,14 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
     return a * nt;
   };
   switch (st.kind) {
+    case fdmt::Step::PadIn:
+      info->kind = 9;
+      info->work_items = T.slots;
+      info->bytes_read = static_cast<int64_t>(T.nf) * nt * in_b;
+      info->bytes_written = static_cast<int64_t>(T.slots) * nt * in_b;
+      info->staged_bytes = info->bytes_read;
+      info->out_elem_bytes = static_cast<int32_t>(in_b);
+      break;
     case fdmt::Step::Init:
       info->level_first = info->level_last = 0;
       info->work_items = T.slots;
@@ -654,7 +664,7 @@ fdmt_status_t fdmt_ragged_plan(fdmt_ragged_t *out, fdmt_plan_t p, int32_t nbeams
 
 size_t fdmt_ragged_workspace_bytes(fdmt_ragged_t r) {
   if (!r) return 0;
-  return static_cast<size_t>(2) * r->plan->plan.ws_rows * r->rb.sum_ntp * 4;
+  return fdmt::ragged_workspace_bytes(r->plan->plan, r->rb);
 }
 
 fdmt_status_t fdmt_ragged_forward(fdmt_ragged_t r, const void *in, void *out, void *ws, size_t ws_bytes,

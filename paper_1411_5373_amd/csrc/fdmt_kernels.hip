@@ -53,6 +53,26 @@ __global__ __launch_bounds__(kThreads) void init_kernel(
   }
 }
 
+// The input copied to 2^levels channel rows with zeros past row nf, so that
+// every channel position of the tree has an input row. Grid: (channel
+// position, time tile, beam).
+template <typename Tin, bool RAGGED>
+__global__ __launch_bounds__(kThreads) void pad_input_kernel(const Tin *__restrict__ in, Tin *__restrict__ out,
+                                                             int32_t nf, int64_t nt_u, int64_t in_bstride,
+                                                             int64_t out_bstride, RaggedMap rg) {
+  const int k = blockIdx.x;
+  const BeamSpan bs = beam_span<RAGGED>(rg, static_cast<int>(nt_u), nt_u, in_bstride, nt_u, out_bstride);
+  const int64_t nt = bs.nt;
+  const Tin *x = in + bs.src_off + static_cast<int64_t>(k) * nt;
+  Tin *o = out + bs.dst_off + static_cast<int64_t>(k) * nt;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int64_t t = static_cast<int64_t>(bs.tile) * kTile + i * kThreads + threadIdx.x;
+    if (t >= nt) break;
+    o[t] = k < nf ? x[t] : Tin(0);
+  }
+}
+
 // One iteration: out[r][t] = prev[lo][t] + (t >= s ? prev[hi][t - s] : 0).
 // Grid: (plane row, time tile, beam).
 template <typename Tacc, bool RAGGED>
@@ -556,6 +576,8 @@ View view(const Plan &p, Buf b, const void *in, void *out, void *ws, int batch, 
     case Buf::Ws0: return {ws, p.ntp, plane_b};
     case Buf::Ws1:
       return {static_cast<unsigned char *>(ws) + static_cast<size_t>(plane_b) * nb * 4, p.ntp, plane_b};
+    case Buf::InPad:
+      return {static_cast<unsigned char *>(ws) + round_up(2 * plane_b * nb * 4, 256), nt, p.tab.slots * nt};
   }
   return {nullptr, 0, 0};
 }
@@ -564,6 +586,7 @@ int64_t buf_rows(const Plan &p, Buf b, bool adjoint) {
   switch (b) {
     case Buf::In: return adjoint ? p.tab.nd : p.tab.nf;
     case Buf::Out: return adjoint ? p.tab.nf : p.tab.nd;
+    case Buf::InPad: return p.tab.slots;
     default: return p.ws_rows;
   }
 }
@@ -614,6 +637,13 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
   const View src = view(p, st.src, in, out, ws, batch, false, rb);
   const View dst = view(p, st.dst, in, out, ws, batch, false, rb);
   switch (st.kind) {
+    case Step::PadIn:
+      return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
+        hipLaunchKernelGGL((pad_input_kernel<Tin, decltype(r)::value>), dim3(T.slots, gy, gz), dim3(kThreads), 0,
+                           stream, static_cast<const Tin *>(src.ptr), static_cast<Tin *>(dst.ptr), T.nf, nt,
+                           src.bstride, dst.bstride, rg);
+        return hipSuccess;
+      });
     case Step::Init:
       return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         hipLaunchKernelGGL((init_kernel<Tin, Tacc, decltype(r)::value>), dim3(T.slots, gy, gz), dim3(kThreads), 0, stream,
@@ -825,10 +855,14 @@ void plan_steps(Plan &p) {
   p.adj_steps.clear();
   p.ws_rows = 0;
   auto ws = [](int i) { return (i & 1) ? Buf::Ws1 : Buf::Ws0; };
+  // Nf not a power of two: the forward reads a copy of the input with a zero
+  // row for every channel position past Nf
+  const Buf fin = p.pad_input ? Buf::InPad : Buf::In;
+  if (p.pad_input) p.fwd_steps.push_back({Step::PadIn, 0, Buf::In, Buf::InPad});
   if (L == 0) {
-    p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Out});
+    p.fwd_steps.push_back({Step::Init, 0, fin, Buf::Out});
   } else if (p.fwd.passes.empty()) {
-    p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Ws0});
+    p.fwd_steps.push_back({Step::Init, 0, fin, Buf::Ws0});
     for (int l = 1; l <= L; ++l)
       p.fwd_steps.push_back({Step::Merge, l, ws(l - 1), l == L ? Buf::Out : ws(l)});
     for (int l = 0; l < L; ++l) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[l]);
@@ -838,12 +872,12 @@ void plan_steps(Plan &p) {
     // reads ws(i) and writes ws(i + 1).
     const int sh = p.fwd.init_separate ? 1 : 0;
     if (sh) {
-      p.fwd_steps.push_back({Step::Init, 0, Buf::In, Buf::Ws0});
+      p.fwd_steps.push_back({Step::Init, 0, fin, Buf::Ws0});
       p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[0]);
     }
     for (int i = 0; i < n; ++i) {
       const Pass &ps = p.fwd.passes[i];
-      const Buf src = (i == 0 && !sh) ? Buf::In : ws(i - 1 + sh);
+      const Buf src = (i == 0 && !sh) ? fin : ws(i - 1 + sh);
       p.fwd_steps.push_back({Step::Fused, i, src, i == n - 1 ? Buf::Out : ws(i + sh)});
       if (i < n - 1) p.ws_rows = std::max<int64_t>(p.ws_rows, T.total[ps.l1]);
     }
@@ -870,9 +904,20 @@ void plan_steps(Plan &p) {
   }
 }
 
+static int64_t in_elem_bytes(const Plan &p) {
+  return p.in_dtype == FDMT_U8 ? 1 : (p.in_dtype == FDMT_F16 ? 2 : 4);
+}
+
 size_t workspace_bytes(const Plan &p, int batch) {
-  if (p.ws_rows == 0) return 0;
-  return static_cast<size_t>(2) * batch * p.ws_rows * p.ntp * 4;
+  size_t b = static_cast<size_t>(2) * batch * p.ws_rows * p.ntp * 4;
+  if (p.pad_input) b = round_up(b, 256) + static_cast<size_t>(batch) * p.tab.slots * p.nt * in_elem_bytes(p);
+  return b;
+}
+
+size_t ragged_workspace_bytes(const Plan &p, const RaggedBatch &rb) {
+  size_t b = static_cast<size_t>(2) * p.ws_rows * rb.sum_ntp * 4;
+  if (p.pad_input) b = round_up(b, 256) + static_cast<size_t>(p.tab.slots) * rb.sum_nt * in_elem_bytes(p);
+  return b;
 }
 
 template <typename Tin, typename Tacc, bool FI>
@@ -1002,6 +1047,7 @@ int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
   const int gather_tile = 256 * forward_vecs(p) * (kGatherThreads / 64 / p.gather_rows);
   switch (st.kind) {
+    case Step::PadIn:
     case Step::Init:
     case Step::Merge:
     case Step::MergeAdj:

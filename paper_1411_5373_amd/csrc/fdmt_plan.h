@@ -29,11 +29,13 @@ struct FftPlan;  // FFT-FDMT state (fdmt_fft.hip)
 
 // Where a step reads or writes: the caller's input/output or one of the two
 // workspace planes.
-enum class Buf { In, Out, Ws0, Ws1 };
+// InPad: the input copied to 2^levels channel rows, the rows past Nf zero
+// (Nf not a power of two); it follows the two planes in the workspace.
+enum class Buf { In, Out, Ws0, Ws1, InPad };
 
 // One kernel launch of a transform.
 struct Step {
-  enum Kind { Init, Merge, Fused, MergeAdj, InitAdj, AdjGather } kind;
+  enum Kind { Init, Merge, Fused, MergeAdj, InitAdj, AdjGather, PadIn } kind;
   int index;  // Merge/MergeAdj: iteration l; Fused: pass index in the schedule
   Buf src, dst;
 };
@@ -71,6 +73,7 @@ struct Plan {
   std::vector<uint8_t> int_sums; // per forward pass: uint8 input or uint16 planes in, sums integers below 2^24
   std::vector<Step> fwd_steps, adj_steps;
   int64_t ws_rows = 0;         // rows of each workspace plane
+  bool pad_input = false;      // Nf not a power of two: the forward reads a zero-padded copy
   FftPlan *fft = nullptr;      // FFT-FDMT state (FDMT_PLAN_FFT plans only)
 };
 
@@ -106,6 +109,7 @@ int step_tile(const Plan &p, bool adjoint, int step);
 // Output rows per workgroup of adjoint register-gather pass `pass`.
 int adjoint_rows(const Plan &p, int pass);
 size_t workspace_bytes(const Plan &p, int batch);
+size_t ragged_workspace_bytes(const Plan &p, const RaggedBatch &rb);
 // Option-1 rows of every channel position of one beam into FP32 rows of
 // `stride` elements (samples t < nt; the rest of each row is untouched).
 hipError_t launch_init_f32(const Plan &p, const void *in, float *plane0, int64_t stride, hipStream_t stream);

@@ -170,7 +170,7 @@ void emit_records(const Tables &t, bool from_input, int l0, int k, const Node *n
 // range), destination rows inside the produced plane.
 std::string audit_records(const Tables &t, const Pass &ps, const Rec *recs, const int32_t *heads) {
   const int k = ps.l1 - ps.l0;
-  const int64_t src_rows = ps.from_input ? t.nf : t.total[ps.l0];
+  const int64_t src_rows = ps.from_input ? t.slots : t.total[ps.l0];
   for (int b = 0; b < ps.nblocks; ++b) {
     const int32_t *h = heads + static_cast<int64_t>(b) * kRecHeader;
     const Rec *r = recs + h[0];
@@ -331,8 +331,8 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
     // (and the initialisation kernels); passes that stage input rows in LDS do
     // not apply it.
     if (first && kind != PassKind::Register)
-      for (int32_t x : t.pre)
-        if (x != 0) return "the d_min pre-shift needs the first pass to gather from the input";
+      for (int k = 0; k < t.nf; ++k)
+        if (t.pre[k] != 0) return "the d_min pre-shift needs the first pass to gather from the input";
     if (kind == PassKind::Staged) {
       const int k = std::min(k_req, L - l0);
       if (k > 5) return "at most 5 iterations per staged pass";
@@ -343,7 +343,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
       ps.l0 = l0;
       ps.l1 = l0 + k;
       ps.tile = p.tile;
-      ps.rows_in = first ? t.nf : t.total[l0];
+      ps.rows_in = first ? t.slots : t.total[l0];
       ps.rows_out = t.total[ps.l1];
       ps.rec_offset = static_cast<int64_t>(s.stage.size());
       ps.term_offset = static_cast<int64_t>(s.sterms.size());
@@ -417,13 +417,13 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
       ps.from_input = first;
       ps.l0 = l0;
       ps.l1 = l0 + k;
-      ps.rows_in = first ? t.nf : t.total[l0];
+      ps.rows_in = first ? t.slots : t.total[l0];
       ps.rows_out = t.total[ps.l1];
       ps.term_offset = static_cast<int64_t>(first ? s.iterms.size() : s.terms.size());
       std::vector<int32_t> channel_of;
       if (first) {
         channel_of.resize(t.total[0]);
-        for (int ch = 0; ch < t.nf; ++ch)
+        for (int ch = 0; ch < t.slots; ++ch)
           for (int d = 0; d < t.leaf_rows[ch]; ++d) channel_of[t.leaf_off[ch] + d] = ch;
       }
       std::vector<Term> cur, nxt;
@@ -444,7 +444,8 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
           for (const Term &x : cur) {
             const int ch = channel_of[x.row];
             const int d = x.row - t.leaf_off[ch];
-            s.iterms.push_back(InTerm{ch, x.shift + t.pre[ch], d, 0});
+            // a position without a channel reads a zero row of the padded input
+            s.iterms.push_back(InTerm{ch, x.shift + (ch < t.nf ? t.pre[ch] : 0), d, 0});
             ps.staged_rows += d + 1;
           }
         } else {
@@ -468,7 +469,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
     ps.node_offset = static_cast<int64_t>(s.nodes.size());
     ps.rec_offset = static_cast<int64_t>(s.recs.size());
     ps.head_offset = static_cast<int64_t>(s.heads.size());
-    ps.rows_in = first ? t.nf : t.total[l0];
+    ps.rows_in = first ? t.slots : t.total[l0];
     ps.rows_out = t.total[ps.l1];
     for (int sub = 0; sub < (t.slots >> ps.l1); ++sub) {
       const int n = t.rows[ps.l1][sub];
@@ -512,9 +513,6 @@ std::string build_schedule(Schedule &s, const Tables &t, const ScheduleParams &p
   const int L = t.levels;
   if (L == 0) return "";
   if (p.tile < 1 || p.first_levels < 1 || p.later_levels < 1) return "bad schedule parameters";
-  // Channel positions without a channel are zero rows of plane 0, which the
-  // initialisation writes; the passes start from there.
-  if (t.slots != t.nf) s.init_separate = true;
   int l0 = 0;
   while (l0 < L) {
     const bool first = l0 == 0 && !s.init_separate;
