@@ -39,6 +39,10 @@ SCHEDULES = [
          adjoint_tile_major=0xFFFF),
     dict(later_levels=2, gather_rows=16, adjoint_levels=1, adjoint_last_levels=1),
     dict(unfused=True),
+    dict(first_kernel=1, later_kernel=1, tile=256),        # staged passes from the padded input
+    dict(first_kernel=3, first_levels=3, later_levels=3, gather_rows=4, gather_vecs=4,
+         adjoint_levels=3, adjoint_last_levels=3, adjoint_last_rows=8),  # input gathers, uint16 planes
+    dict(first_kernel=3, first_levels=4, later_levels=4, gather_vecs=2),
 ]
 
 
