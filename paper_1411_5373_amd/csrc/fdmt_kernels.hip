@@ -73,6 +73,19 @@ __global__ __launch_bounds__(kThreads) void pad_input_kernel(const Tin *__restri
   }
 }
 
+// The same copy for a uniform batch whose beam blocks are 16-byte aligned: a
+// beam's padded block is its input block followed by zeros, copied in
+// 16-byte units. Grid: (chunks, beam).
+__global__ __launch_bounds__(kThreads) void pad_flat_kernel(const uint4 *__restrict__ in, uint4 *__restrict__ out,
+                                                            int64_t in_vecs, int64_t out_vecs) {
+  const int64_t b = blockIdx.y;
+  const uint4 *x = in + b * in_vecs;
+  uint4 *o = out + b * out_vecs;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < out_vecs;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    o[i] = i < in_vecs ? x[i] : make_uint4(0u, 0u, 0u, 0u);
+}
+
 // One iteration: out[r][t] = prev[lo][t] + (t >= s ? prev[hi][t - s] : 0).
 // Grid: (plane row, time tile, beam).
 template <typename Tacc, bool RAGGED>
@@ -637,7 +650,18 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
   const View src = view(p, st.src, in, out, ws, batch, false, rb);
   const View dst = view(p, st.dst, in, out, ws, batch, false, rb);
   switch (st.kind) {
-    case Step::PadIn:
+    case Step::PadIn: {
+      const int64_t in_bytes = T.nf * nt * static_cast<int64_t>(sizeof(Tin));
+      const int64_t out_bytes = T.slots * nt * static_cast<int64_t>(sizeof(Tin));
+      if (rb == nullptr && in_bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(src.ptr) & 15) == 0 &&
+          (reinterpret_cast<uintptr_t>(dst.ptr) & 15) == 0) {
+        const int64_t vecs = out_bytes / 16;
+        const unsigned gx = static_cast<unsigned>(std::min<int64_t>((vecs + kThreads - 1) / kThreads, 4096));
+        hipLaunchKernelGGL(pad_flat_kernel, dim3(gx, static_cast<unsigned>(batch)), dim3(kThreads), 0, stream,
+                           static_cast<const uint4 *>(src.ptr), static_cast<uint4 *>(dst.ptr), in_bytes / 16, vecs);
+        return hipGetLastError();
+      }
+    }
       return for_each_launch(p, rb, st, false, kTile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         hipLaunchKernelGGL((pad_input_kernel<Tin, decltype(r)::value>), dim3(T.slots, gy, gz), dim3(kThreads), 0,
                            stream, static_cast<const Tin *>(src.ptr), static_cast<Tin *>(dst.ptr), T.nf, nt,
