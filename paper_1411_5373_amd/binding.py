@@ -77,8 +77,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1411_5373_amd/build.py "
-                          "(or __graft_entry__.build()); there is no fallback path")
+        raise ImportError(f"{_LIB_PATH} is missing: build it with python paper_1411_5373_amd/build.py; "
+                          "there is no fallback path")
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     p_i32 = ctypes.POINTER(ctypes.c_int32)
