@@ -349,6 +349,17 @@ def main():
     alg = dom["bytes_read"] + dom["bytes_written"]
     achieved = alg / (per[j] / 1000.0) / 1e9
     traffic = read_traffic(key)
+    # Byte models of the transform: compulsory = the
+    # input read and the output written once; unfused = every plane of the
+    # level-by-level recursion written once and read once (uint8 input, FP32
+    # planes); schedule = what this plan's kernels consume and produce.
+    _, plane_rows = plan.info()
+    compulsory = {"forward": w.nf * w.nt * 1 + w.nd * w.nt * 4, "adjoint": (w.nd + w.nf) * w.nt * 4}
+    planes = sum(plane_rows) * w.nt * 4 + sum(plane_rows[:-1]) * w.nt * 4
+    unfused = {"forward": w.nf * w.nt * 1 + planes, "adjoint": w.nf * w.nt * 4 + planes}
+    models = {d: {"compulsory_gb": round(compulsory[d] / 1e9, 3), "unfused_gb": round(unfused[d] / 1e9, 3),
+                  "schedule_gb": round(b / 1e9, 3), "compulsory_gb_s": round(compulsory[d] / ms / 1e6, 1)}
+              for d, b, ms in (("forward", fwd_bytes, fwd_ms), ("adjoint", adj_bytes, adj_ms))}
     kernels = [{"direction": d, "kind": i["kind"], "levels": [i["level_first"], i["level_last"]],
                 "ms": round(m, 4), "alg_gb_s": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6, 1)}
                for m, (d, i) in zip(per, infos)]
@@ -371,8 +382,9 @@ def main():
                    "nf": w.nf, "nt": w.nt, "nd": w.nd, "batch": 1, "parallelism": "single GPU",
                    "schedule": plan.options},
         "forward": {"ms": round(fwd_ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (fwd_ms / 1000.0),
-                    "alg_hbm_gb_s": round(fwd_bytes / fwd_ms / 1e6, 1)},
-        "adjoint": {"ms": round(adj_ms, 4), "alg_hbm_gb_s": round(adj_bytes / adj_ms / 1e6, 1)},
+                    "alg_hbm_gb_s": round(fwd_bytes / fwd_ms / 1e6, 1), "bytes": models["forward"]},
+        "adjoint": {"ms": round(adj_ms, 4), "alg_hbm_gb_s": round(adj_bytes / adj_ms / 1e6, 1),
+                    "bytes": models["adjoint"]},
         "adjoint_forward_ratio": round(adj_ms / fwd_ms, 3),
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": key, "achieved": round(achieved, 1),
