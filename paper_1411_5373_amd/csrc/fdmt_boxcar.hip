@@ -70,32 +70,56 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_tile_kernel(const float *_
       const int first = (1 << j) - 1;
       for (int top = halo + nvalid - 1; top >= first; top -= kGroup * kBoxThreads) {
         float nv[kGroup];
+        const int base = top - tid;
+        if (top - kGroup * kBoxThreads + 1 >= first) {  // the whole group lies at or above `first`
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-          const int i = top - g * kBoxThreads - tid;
-          if (i >= first) nv[g] = buf[i] + buf[i - w];
-        }
+          for (int g = 0; g < kGroup; ++g) nv[g] = buf[base - g * kBoxThreads] + buf[base - g * kBoxThreads - w];
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-          const int i = top - g * kBoxThreads - tid;
-          if (i >= first) buf[i] = nv[g];
+          for (int g = 0; g < kGroup; ++g) buf[base - g * kBoxThreads] = nv[g];
+        } else {
+#pragma unroll
+          for (int g = 0; g < kGroup; ++g) {
+            const int i = base - g * kBoxThreads;
+            if (i >= first) nv[g] = buf[i] + buf[i - w];
+          }
+#pragma unroll
+          for (int g = 0; g < kGroup; ++g) {
+            const int i = base - g * kBoxThreads;
+            if (i >= first) buf[i] = nv[g];
+          }
         }
       }
       __syncthreads();
     }
+    // A thread visits its samples in increasing time, so a strictly larger
+    // value is the only way to move its peak: equal values keep the first.
     double s = 0.0, q = 0.0;
     float best = -__builtin_inff();
     int best_t = INT32_MAX;
+    if (nvalid == kBoxTile) {
 #pragma unroll
-    for (int k = 0; k < kBoxPerThread; ++k) {
-      const int i = tid + k * kBoxThreads;
-      if (i < nvalid) {
+      for (int k = 0; k < kBoxPerThread; ++k) {
+        const int i = tid + k * kBoxThreads;
         const float v = buf[halo + i];
         s += static_cast<double>(v);
         q += static_cast<double>(v) * static_cast<double>(v);
-        if (better(v, i, best, best_t)) {
+        if (v > best || (v == best && best_t == INT32_MAX)) {
           best = v;
           best_t = i;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kBoxPerThread; ++k) {
+        const int i = tid + k * kBoxThreads;
+        if (i < nvalid) {
+          const float v = buf[halo + i];
+          s += static_cast<double>(v);
+          q += static_cast<double>(v) * static_cast<double>(v);
+          if (v > best || (v == best && best_t == INT32_MAX)) {
+            best = v;
+            best_t = i;
+          }
         }
       }
     }
