@@ -218,6 +218,32 @@ def test_c3_full_size_sampled():
         print(f"  c3 f16 row {dt}: max|err|/RMS = {_rel(y[dt], ref):.3e}")
 
 
+def test_c3_benchmark_configuration_full_size():
+    """The benchmark's step at its full size and launch configuration (tuned
+    plan, Nf=4096, Nt=65536, Nd=2048): the uint8 -> FP32 forward is exact at
+    row 0 (channel sums), three whole rows and 40 sampled outputs (oracle path
+    sums); the FP32 adjoint equals the oracle's binary32 adjoint over the whole
+    [Nf][Nt] plane, bit for bit."""
+    w = W.WORKLOADS["c3"]
+    u8, _, _ = W.make_c3()
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=torch.float32, tuned=True)
+    print(f"c3 tuned step {p.options}", flush=True)
+    y = p.forward(_dev(u8)).cpu().numpy()
+    np.testing.assert_array_equal(y[0].astype(np.int64), u8.astype(np.int64).sum(axis=0))
+    for dt in [2, 1024, w.nd - 1]:
+        np.testing.assert_array_equal(y[dt].astype(np.int64), brute_row(u8, tab, dt))
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        dt, t0 = int(rng.integers(w.nd)), int(rng.integers(w.nt))
+        assert int(y[dt, t0]) == brute_point(u8, tab, dt, t0)
+    del y
+    g = np.random.default_rng(W.SEED_BASE + 102).standard_normal((w.nd, w.nt), dtype=np.float32)
+    xb = p.adjoint(_dev(g)).cpu().numpy()
+    print("c3 tuned adjoint: oracle binary32 adjoint", flush=True)
+    np.testing.assert_array_equal(xb, oadj(g, w.f_min, w.f_max, w.nf, tab, acc=np.float32))
+
+
 def test_autograd_function():
     """loss = logsumexp over each beam's DM-time plane (the differentiable
     workload's loss on its Nf=32, Nt=256, Nd=32 slice). The gradient autograd
