@@ -244,6 +244,23 @@ def test_c3_benchmark_configuration_full_size():
     np.testing.assert_array_equal(xb, oadj(g, w.f_min, w.f_max, w.nf, tab, acc=np.float32))
 
 
+def test_c5_benchmark_configuration():
+    """The differentiable workload's launch configuration (tuned plan, batch 16,
+    Nf=1024, Nt=16384, Nd=1024, 0.4-0.8 GHz): the batched forward and adjoint
+    of two sampled beams equal the oracle's binary32 transform and adjoint."""
+    w = W.WORKLOADS["c5"]
+    x = W.make_c5()
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    p = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, tuned=True)
+    print(f"c5 tuned {p.options}", flush=True)
+    y = p.forward(_dev(x)).cpu().numpy()
+    g = W.random_input((w.batch, w.nd, w.nt), np.float32, seed=W.SEED_BASE + 55)
+    xb = p.adjoint(_dev(g)).cpu().numpy()
+    for b in (0, w.batch - 1):
+        np.testing.assert_array_equal(y[b], ofdmt(x[b], w.f_min, w.f_max, w.nd, tab, acc=np.float32))
+        np.testing.assert_array_equal(xb[b], oadj(g[b], w.f_min, w.f_max, w.nf, tab, acc=np.float32))
+
+
 def test_autograd_function():
     """loss = logsumexp over each beam's DM-time plane (the differentiable
     workload's loss on its Nf=32, Nt=256, Nd=32 slice). The gradient autograd

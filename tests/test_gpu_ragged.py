@@ -245,3 +245,31 @@ def test_c4_full_size():
     gs, xbs = _unpack(g, w.nd, lengths), _unpack(xb, w.nf, lengths)
     for b in sample:
         assert torch.equal(xbs[b], F.Plan(w.nf, lengths[b], w.nd, w.f_min, w.f_max).adjoint(gs[b])), b
+
+
+def test_c4_benchmark_configuration():
+    """The ragged benchmark's launch configuration: the tuned FP32 plan (Nt =
+    the longest beam) over all 256 beams, forward and adjoint; the shortest,
+    the longest and a third beam equal the oracle's binary32 transform and
+    adjoint bit for bit."""
+    w = W.WORKLOADS["c4"]
+    lengths = [int(n) for n in W.c4_lengths()]
+    tot = sum(lengths)
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    p = F.Plan(w.nf, max(lengths), w.nd, w.f_min, w.f_max, tuned=True)
+    print(f"c4 tuned {p.options}", flush=True)
+    r = F.RaggedPlan(p, lengths)
+    order = np.argsort(lengths)
+    sample = [int(order[0]), int(order[-1]), int(order[len(order) // 2])]
+    x = W.torch_noise((w.nf * tot,), W.SEED_BASE + 42, DEV)
+    ys = _unpack(r.forward(x), w.nd, lengths)
+    xs = _unpack(x, w.nf, lengths)
+    for b in sample:
+        np.testing.assert_array_equal(ys[b].cpu().numpy(),
+                                      ofdmt(xs[b].cpu().numpy(), w.f_min, w.f_max, w.nd, tab, acc=np.float32))
+    del ys, xs, x
+    g = W.torch_noise((w.nd * tot,), W.SEED_BASE + 43, DEV)
+    xbs, gs = _unpack(r.adjoint(g), w.nf, lengths), _unpack(g, w.nd, lengths)
+    for b in sample:
+        np.testing.assert_array_equal(xbs[b].cpu().numpy(),
+                                      oadj(gs[b].cpu().numpy(), w.f_min, w.f_max, w.nf, tab, acc=np.float32))
