@@ -1,11 +1,12 @@
 #!/bin/bash
 # Re-tunes the schedules of the benchmark workloads on the current GPU and
 # writes them to the cache file given as $1 (default: this directory's
-# <arch>.json). Each workload takes a few seconds.
+# <arch>.json). Each workload takes one to a few minutes (15 timed calls per
+# candidate: the adjoint work-order candidates differ by about 1%).
 set -e
 cd "$(dirname "$0")/../.."
 export FDMT_TUNE_CACHE=${1:-}
-T="python -u -m paper_1411_5373_amd.autotune --write"
+T="python -u -m paper_1411_5373_amd.autotune --write --reps 15"
 # Nf=4096, Nt=65536, Nd=2048, 1.2-1.6 GHz: the step's forms
 $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype u8 --acc-dtype f32
 $T --nf 4096 --nt 65536 --nd 2048 --band 1.2 1.6 --in-dtype f16 --acc-dtype f32
