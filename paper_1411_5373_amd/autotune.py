@@ -204,6 +204,8 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
                 fwd_best = (ms, cand)
             del p, fn
         for cand in adjoint_candidates(rows):
+            if lengths and cand["adjoint_tile_major"] != "none":
+                continue  # ragged launches take their work order from the tile maps
             try:
                 def make(**o):
                     return B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma,
