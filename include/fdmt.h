@@ -139,7 +139,8 @@ typedef struct {
   uint32_t adjoint_tile_major; /* bit i set: adjoint gather pass i (launch order) runs each row
                                   group's time tiles back to back on one XCD instead of all
                                   groups of a tile together; suits passes whose leaves sit at
-                                  large shifts (0 = default: none) */
+                                  large shifts (0 = default: none). Uniform batches only:
+                                  ragged launches follow their tile maps */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
