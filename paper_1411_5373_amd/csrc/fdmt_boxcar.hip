@@ -97,15 +97,37 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_tile_kernel(const float *_
     float best = -__builtin_inff();
     int best_t = INT32_MAX;
     if (nvalid == kBoxTile) {
+      // The thread's first sample opens its peak unless it is a NaN; after
+      // that only a strictly larger value moves it.
+      const float v0 = buf[halo + tid];
+      s += static_cast<double>(v0);
+      q += static_cast<double>(v0) * static_cast<double>(v0);
+      if (v0 == v0) {
+        best = v0;
+        best_t = tid;
+      }
+      if (best_t != INT32_MAX) {
 #pragma unroll
-      for (int k = 0; k < kBoxPerThread; ++k) {
-        const int i = tid + k * kBoxThreads;
-        const float v = buf[halo + i];
-        s += static_cast<double>(v);
-        q += static_cast<double>(v) * static_cast<double>(v);
-        if (v > best || (v == best && best_t == INT32_MAX)) {
-          best = v;
-          best_t = i;
+        for (int k = 1; k < kBoxPerThread; ++k) {
+          const int i = tid + k * kBoxThreads;
+          const float v = buf[halo + i];
+          s += static_cast<double>(v);
+          q += static_cast<double>(v) * static_cast<double>(v);
+          if (v > best) {
+            best = v;
+            best_t = i;
+          }
+        }
+      } else {
+        for (int k = 1; k < kBoxPerThread; ++k) {
+          const int i = tid + k * kBoxThreads;
+          const float v = buf[halo + i];
+          s += static_cast<double>(v);
+          q += static_cast<double>(v) * static_cast<double>(v);
+          if (v > best || (v == best && best_t == INT32_MAX)) {
+            best = v;
+            best_t = i;
+          }
         }
       }
     } else {
