@@ -129,7 +129,8 @@ typedef struct {
                              power -2 of Eq. Cf2f0 becomes gamma); finite, nonzero
                              (0 = default: -2, the cold-plasma law). Changes the tables
                              and so the results */
-  int32_t d_min;          /* smallest total delay searched, in samples, >= 0 (Sec. 4.2,
+  int32_t d_min;          /* smallest total delay searched, in samples, 0..2^30 with
+                             Nt + d_min + 2 Nd < 2^31 - 8192 (Sec. 4.2,
                              different range of dispersions): channel k's input is
                              delayed by pre_k = round(d_min * phi(c_k)), phi the fraction
                              of the band delay at its centre c_k, so output row dt
@@ -328,6 +329,28 @@ size_t fdmt_boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_
  * FDMT_E_WORKSPACE, FDMT_E_DEVICE. Enqueued on hip_stream; allocates nothing. */
 fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
                                  fdmt_boxcar_t *out, void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Tuned schedule lookup. The package's autotuner times candidate schedules
+ * on the GPU and stores the fastest per workload in a JSON cache; this call
+ * lets a C caller start from that schedule as the Python layer does. The
+ * schedule only changes speed, never results (Sec. 4.2 leaves memory access
+ * and fusion to the implementation).
+ *   cache_path  JSON cache; NULL = $FDMT_TUNE_CACHE if set, else the cache
+ *               shipped beside the library, <dir of libfdmt.so>/tuning/<arch>.json
+ *   arch        architecture name ("gfx950"); NULL = the current device's
+ *   opt         in: in_dtype, acc_dtype, gamma, d_min and any explicit schedule
+ *               fields (nonzero ones are kept); out: every zero schedule field
+ *               that the cache entry sets is filled in (with d_min > 0 a
+ *               cached first_kernel of 1 or 2 becomes 3, the gather from the
+ *               input that applies the pre-shift)
+ *   found       (may be NULL) 1 if the cache held this workload, else 0
+ * The key is the architecture, Nf, Nd, the band, gamma when not -2, the
+ * dtypes and Nt rounded up to a power of two. A missing cache file is not an
+ * error (found = 0). FDMT_E_INVALID: NULL opt, sizes < 1, a malformed cache
+ * or an unknown field in the matching entry; FDMT_E_DEVICE: arch NULL and no
+ * current device. Touches no device memory; pass the result to fdmt_plan(). */
+fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32_t nf, int64_t nt, int32_t nd,
+                                 double f_min, double f_max, fdmt_options_t *opt, int32_t *found);
 
 /* Static description of a status code. */
 const char *fdmt_status_string(fdmt_status_t s);

@@ -440,6 +440,17 @@ def fdmt_fft(img, f_min, f_max, nd, tables=None, n=None):
 # frequencies commutes with the transform, so several widths share one FDMT)
 # ----------------------------------------------------------------------------
 
+def boxcar(plane, w):
+    """b_w[t] = y[t] + y[t-1] + ... + y[t-w+1] over the last axis, with y = 0
+    before t = 0: the causal boxcar of width w by its definition, in float64."""
+    y = np.asarray(plane, dtype=np.float64)
+    nt = y.shape[-1]
+    b = np.zeros_like(y)
+    for i in range(min(w, nt)):
+        b[..., i:] += y[..., : nt - i]
+    return b
+
+
 def boxcar_search(plane, max_log2, acc=None):
     """For every row of plane[..., nd, nt] and width w = 2^j, j = 0..max_log2:
     b_w[t] = y[t] + y[t-1] + ... + y[t-w+1] (y = 0 before t = 0), its largest
@@ -455,12 +466,7 @@ def boxcar_search(plane, max_log2, acc=None):
     widths = [1 << j for j in range(max_log2 + 1)]
     sums = []
     if acc is None:
-        y64 = y.astype(np.float64)
-        for w in widths:
-            b = np.zeros_like(y64)
-            for i in range(min(w, nt)):
-                b[..., i:] += y64[..., : nt - i]
-            sums.append(b)
+        sums = [boxcar(y, w) for w in widths]
     else:
         b = y.astype(acc)
         sums.append(b.copy())

@@ -29,7 +29,8 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
-            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_status_string", "fdmt_last_error")
+            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_tuned_options", "fdmt_status_string",
+            "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
               "input_gather", "staged_gather", "adjoint_gather", "pad_input")
@@ -125,6 +126,9 @@ def load():
     lib.fdmt_boxcar_workspace_bytes.restype = sz
     lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.fdmt_boxcar_search.restype = ctypes.c_int
+    lib.fdmt_tuned_options.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, i64, i32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(_Options), p_i32]
+    lib.fdmt_tuned_options.restype = ctypes.c_int
     lib.fdmt_status_string.argtypes = [ctypes.c_int]
     lib.fdmt_status_string.restype = ctypes.c_char_p
     lib.fdmt_last_error.argtypes = []
@@ -165,6 +169,29 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
+
+
+SCHEDULE_FIELDS = ("first_levels", "later_levels", "tile", "lds_kib", "max_block_rows", "first_kernel",
+                   "later_kernel", "stream_tiles", "gather_rows", "adjoint_levels", "adjoint_last_levels",
+                   "gather_vecs", "adjoint_last_rows", "adjoint_tile_major")
+
+
+def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, gamma=0.0, d_min=0,
+                       cache_path=None, arch=None, **explicit):
+    """The autotuner's schedule for this workload through the C ABI: a dict of
+    the schedule fields the cache sets (explicit nonzero fields kept as given),
+    or None when the cache has no entry."""
+    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0)
+    for k, v in explicit.items():
+        setattr(opt, k, int(v))
+    found = ctypes.c_int32()
+    _check(load().fdmt_tuned_options(None if cache_path is None else os.fsencode(cache_path),
+                                     None if arch is None else arch.encode(), int(nf), int(nt), int(nd),
+                                     float(f_min), float(f_max), ctypes.byref(opt), ctypes.byref(found)),
+           "fdmt_tuned_options")
+    if not found.value:
+        return None
+    return {k: getattr(opt, k) for k in SCHEDULE_FIELDS if getattr(opt, k) != 0}
 
 
 def fdmt_workspace_bytes(plan, batch):
@@ -313,12 +340,11 @@ class Plan:
         self.device = None if host_only else torch.device("cuda", torch.cuda.current_device())
         self.tuned = None
         if tuned and not host_only and not unfused:
-            from . import autotune
-            self.tuned = autotune.lookup(nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=self.gamma)
+            # the cache lookup is the library's (fdmt_tuned_options); explicit
+            # schedule fields override the cached ones
+            self.tuned = fdmt_tuned_options(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
+                                            _TORCH_TO_CODE[acc_dtype], gamma=self.gamma, d_min=self.d_min)
             if self.tuned:
-                if self.d_min and self.tuned.get("first_kernel") in (1, 2):
-                    # the pre-shift needs the gather from the input
-                    self.tuned = dict(self.tuned, first_kernel=3)
                 schedule = dict(self.tuned, **schedule)
         self.options = dict(schedule)
         self.handle = None

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
       sums.flush_below(0);
     }
   };
-  if (t_wave + 256 * CV + max_shift <= nt)
+  if (static_cast<int64_t>(t_wave) + 256 * CV + max_shift <= nt)
     run(std::true_type());
   else
     run(std::false_type());

@@ -2,8 +2,12 @@
 // upload and error reporting. See include/fdmt.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 
@@ -11,6 +15,7 @@
 #include "fdmt_boxcar.h"
 #include "fdmt_fft.h"
 #include "fdmt_plan.h"
+#include "fdmt_tune.h"
 
 struct fdmt_plan_s {
   fdmt::Plan plan;
@@ -208,7 +213,11 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
   if (o.adjoint_last_rows < 0 || o.adjoint_last_rows > 16 || (o.adjoint_last_rows & (o.adjoint_last_rows - 1)))
     return fail(FDMT_E_INVALID, "adjoint_last_rows must be 1, 2, 4, 8 or 16");
-  if (o.d_min < 0) return fail(FDMT_E_INVALID, "d_min must be >= 0");
+  // Shifts, sample indices and their sums stay int32 in the kernels: d_min is
+  // at most 2^30, and Nt + d_min + 2 Nd leaves 2^13 samples of headroom.
+  if (o.d_min < 0 || o.d_min > (1 << 30)) return fail(FDMT_E_INVALID, "d_min must be in [0, 2^30]");
+  if (nt + o.d_min + 2 * static_cast<int64_t>(nd) > INT32_MAX - 8192)
+    return fail(FDMT_E_INVALID, "Nt + d_min + 2 Nd must stay below 2^31 - 8192");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
     return fail(FDMT_E_INVALID, "max_block_rows must be in [1, 4096]");
   if (o.flags & ~(FDMT_PLAN_HOST_ONLY | FDMT_PLAN_UNFUSED | FDMT_PLAN_WIDE_PLANES | FDMT_PLAN_FFT))
@@ -754,6 +763,87 @@ fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, 
   const hipError_t e =
       fdmt::launch_boxcar(plane, batch, nd, nt, max_log2, out, ws, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(e, "boxcar search launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32_t nf, int64_t nt, int32_t nd,
+                                 double f_min, double f_max, fdmt_options_t *opt, int32_t *found) {
+  if (found) *found = 0;
+  if (!opt) return fail(FDMT_E_INVALID, "opt is NULL");
+  if (nf < 1 || nt < 1 || nd < 1) return fail(FDMT_E_INVALID, "Nf, Nt and Nd must be >= 1");
+  std::string a;
+  if (arch) {
+    a = arch;
+  } else {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDeviceProperties");
+    a = prop.gcnArchName;
+  }
+  a = a.substr(0, a.find(':'));  // "gfx950:sramecc+:xnack-" -> "gfx950"
+  std::string path;
+  if (cache_path) {
+    path = cache_path;
+  } else if (const char *env = std::getenv("FDMT_TUNE_CACHE"); env && *env) {
+    path = env;
+  } else {
+    // the cache shipped beside the library: <directory of libfdmt.so>/tuning/<arch>.json
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void *>(&fdmt_tuned_options), &info) || !info.dli_fname)
+      return fail(FDMT_E_INVALID, "cannot locate the library to find its tuning cache");
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    path = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning/" + a + ".json";
+  }
+  const double gamma = opt->gamma != 0.0 ? opt->gamma : -2.0;
+  const std::string key = fdmt::tune_key(a, nf, nt, nd, f_min, f_max, opt->in_dtype, opt->acc_dtype, gamma);
+  std::map<std::string, double> o;
+  bool hit = false;
+  std::string err;
+  try {
+    err = fdmt::tune_lookup(path, key, o, hit);
+  } catch (const std::bad_alloc &) {
+    return fail(FDMT_E_NOMEM, "host allocation while reading the tuning cache");
+  }
+  if (!err.empty()) return fail(FDMT_E_INVALID, "tuning cache: " + err);
+  if (!hit) return FDMT_OK;
+  struct Field {
+    const char *name;
+    int32_t *i;
+    uint32_t *u;
+  };
+  const Field fields[] = {{"first_levels", &opt->first_levels, nullptr},
+                          {"later_levels", &opt->later_levels, nullptr},
+                          {"tile", &opt->tile, nullptr},
+                          {"lds_kib", &opt->lds_kib, nullptr},
+                          {"max_block_rows", &opt->max_block_rows, nullptr},
+                          {"first_kernel", &opt->first_kernel, nullptr},
+                          {"later_kernel", &opt->later_kernel, nullptr},
+                          {"stream_tiles", &opt->stream_tiles, nullptr},
+                          {"gather_rows", &opt->gather_rows, nullptr},
+                          {"adjoint_levels", &opt->adjoint_levels, nullptr},
+                          {"adjoint_last_levels", &opt->adjoint_last_levels, nullptr},
+                          {"gather_vecs", &opt->gather_vecs, nullptr},
+                          {"adjoint_last_rows", &opt->adjoint_last_rows, nullptr},
+                          {"adjoint_tile_major", nullptr, &opt->adjoint_tile_major}};
+  for (const auto &kv : o) {
+    const Field *f = nullptr;
+    for (const Field &c : fields)
+      if (kv.first == c.name) f = &c;
+    if (!f) return fail(FDMT_E_INVALID, "tuning cache entry " + key + ": unknown schedule field " + kv.first);
+    const double v = kv.second;
+    if (!(v >= 0.0 && v <= 4294967295.0 && v == std::floor(v)))
+      return fail(FDMT_E_INVALID, "tuning cache entry " + key + ": bad value of " + kv.first);
+    // explicit (nonzero) fields of the caller win over the cache
+    if (f->i && *f->i == 0) *f->i = static_cast<int32_t>(v);
+    if (f->u && *f->u == 0) *f->u = static_cast<uint32_t>(v);
+  }
+  // the d_min pre-shift rides on the input terms: keep a gather from the input
+  if (opt->d_min > 0 && (opt->first_kernel == 1 || opt->first_kernel == 2)) opt->first_kernel = 3;
+  if (found) *found = 1;
   return FDMT_OK;
 }
 

@@ -108,6 +108,17 @@ def test_dmin_plan_rules():
     F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=0, first_kernel=2)
 
 
+def test_huge_dmin_refused():
+    """Shifts and sample indices stay int32 in the kernels: d_min above 2^30,
+    or Nt + d_min + 2 Nd within 8192 of 2^31, is refused before any table is
+    built (a host-only plan shows it)."""
+    for nt, d_min in ((1000, 2 ** 30 + 1), (1000, 2 ** 31 - 1), (2 ** 31 - 2 ** 30, 2 ** 30)):
+        with pytest.raises(F.FDMTError) as e:
+            F.Plan(64, nt, 64, 1.2, 1.6, host_only=True, d_min=d_min)
+        assert e.value.status == B.FDMT_E_INVALID and "d_min" in F.fdmt_last_error()
+    F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, d_min=2 ** 30)
+
+
 def test_boxcar_argument_errors_before_launch():
     """fdmt_boxcar_search validates pointers, sizes and the workspace before
     it touches the device."""

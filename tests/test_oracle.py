@@ -574,3 +574,38 @@ def test_fft_fdmt_without_padding_wraps():
             assert y[dt, t0] == total, (dt, t0)
     np.testing.assert_array_equal(np.rint(fdmt_fft(x, *band, nd, t, n=fft_length(nt, nd))).astype(np.int64),
                                   fdmt(x, *band, nd, t))
+
+
+def test_boxcar_float64_checker_accepts_tree_and_rejects_planted_errors():
+    """The GPU boxcar's parity check (float64 definition with rounding bounds)
+    accepts a binary32 evaluation of the doubling tree (here the oracle's own),
+    including ties and rows shorter than the widest boxcar, and rejects
+    results with a wrong time, a wrong peak, stdev of another width or a
+    shifted mean."""
+    import copy
+
+    from numerics import check_boxcar_float64
+    m = 6
+    y = _rng(9).standard_normal((2, 3, 700)).astype(np.float32)
+    y[0, 1, 300] = 40.0                      # a unique maximum at every width
+    y[1, 2, :] = 0.0
+    y[1, 2, [10, 600]] = 5.0                 # equal maxima
+    good = boxcar_search(y, m, acc=np.float32)
+    check_boxcar_float64(good, y, m)
+    check_boxcar_float64(boxcar_search(y[..., :20], m, acc=np.float32), y[..., :20], m)
+    planted = []
+    bad = copy.deepcopy(good)
+    bad["t"][0, 3, 1] += 1                   # unique maximum, time off by one
+    planted.append(bad)
+    bad = copy.deepcopy(good)
+    bad["peak"][0, 2, 0] *= 1 + 1e-4         # peak beyond the rounding bound
+    planted.append(bad)
+    bad = copy.deepcopy(good)
+    bad["stdev"][:, 4] = good["stdev"][:, 5]  # statistics of another width
+    planted.append(bad)
+    bad = copy.deepcopy(good)
+    bad["mean"][1, 1, 0] += 1e-3
+    planted.append(bad)
+    for b in planted:
+        with pytest.raises(AssertionError):
+            check_boxcar_float64(b, y, m)

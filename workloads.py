@@ -138,6 +138,18 @@ def make_c3(seed=SEED_BASE + 2, nt=None):
     return u8, f16, pulses
 
 
+def make_c3_f32(seed=SEED_BASE + 2, nt=None):
+    """The FP32 form of the Nf=4096 workload: the same N(0,1) noise and pulses
+    as make_c3, before quantisation."""
+    w = WORKLOADS["c3"]
+    nt = w.nt if nt is None else nt
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((w.nf, nt), dtype=np.float32)
+    pulses = draw_pulses(rng, 16, w.nd, nt)
+    inject_pulses(x, w.f_min, w.f_max, pulses)
+    return x
+
+
 def c4_lengths(seed=SEED_BASE + 3, beams=256, lo=2048, hi=32768):
     rng = np.random.default_rng(seed)
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=beams))).astype(np.int64)
