@@ -10,13 +10,20 @@ Inputs are synthetic and resident in HBM before timing starts.
 Prints one JSON line. `value` is DM-trial x samples per second of the whole
 step (Nd * Nt / step time); forward-only and adjoint-only rates, achieved HBM
 bandwidth, the adjoint/forward time ratio and the other precision forms (with
-their speedup over the FP32 form and the accuracy against the oracle recorded
-in profiles/precision_c3.txt) are reported beside it, and so are the ragged
-256-beam workload and the batch-16 differentiable workload. `roofline` describes the step's longest kernel: its
-algorithmic bytes (every element it must read and write, once) over its
-average duration measured with HIP events on the launch stream.
-`cpu_baseline` times the CPU oracle (NumPy, one core) on a bounded slice of
-the same workload.
+their speedup over the FP32 form) are reported beside it, and so are the
+ragged 256-beam workload and the batch-16 differentiable workload.
+`roofline` describes the step's longest kernel: its algorithmic bytes (every
+element it must read and write, once) over its average duration measured
+with HIP events on the launch stream, against the HBM peak and against the
+library's own streaming copy measured in the same run.
+
+The CPU leg (skipped with --cpu-sample 0) runs the oracle: it times it on a
+bounded slice of the workload (`cpu_baseline`; the ragged and differentiable
+workloads on a pool of host cores, `cpu_baselines`), and it checks this run's
+GPU outputs against it on causal slices (`accuracy_vs_oracle`): the first
+samples of each forward output, which depend only on the first input
+samples, and the last samples of the adjoint output, which depend only on
+the last gradient samples.
 """
 from __future__ import annotations
 
@@ -42,6 +49,8 @@ KERNEL_SOURCES = ("paper_1411_5373_amd/csrc/fdmt_kernels.hip",
                   "paper_1411_5373_amd/csrc/fdmt_device.h",
                   "paper_1411_5373_amd/csrc/fdmt_schedule.cpp",
                   "paper_1411_5373_amd/tuning/gfx950.json")
+ACCURACY_SAMPLES = 4096  # length of the causal slices checked against the oracle
+MAX_POOL = 16            # worker processes of the CPU leg (one GPU's share of host cores)
 
 
 def source_hash():
@@ -72,7 +81,9 @@ def read_traffic(kernel_key):
 
 
 def time_steps(plan, tensors, steps, warmup, torch):
-    """Runs warmup + timed steps; returns (wall ms per step, per-kernel mean ms)."""
+    """Runs warmup + timed steps; returns (wall ms per step, per-kernel mean ms,
+    step descriptions). Every kernel is bracketed by HIP events recorded on the
+    stream the kernels are launched on (torch's current stream)."""
     x, y, g, xb, ws = tensors
     fwd = plan.steps(False)
     adj = plan.steps(True)
@@ -103,6 +114,12 @@ def time_steps(plan, tensors, steps, warmup, torch):
     return (t1 - t0) * 1000.0 / steps, per, infos
 
 
+# ------------------------------------------------------------------ CPU leg
+
+def host_cores():
+    return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(nt_sample, min_seconds=10.0, max_reps=4):
     """Oracle forward (int64) + adjoint (float64) on the first nt_sample samples,
     repeated until at least min_seconds of CPU work (at most max_reps times)."""
@@ -121,29 +138,136 @@ def cpu_baseline(nt_sample, min_seconds=10.0, max_reps=4):
         fdmt_adjoint(g, w.f_min, w.f_max, w.nf, tab)
         reps += 1
     dt = (time.perf_counter() - t0) / reps
-    return {"value": w.nd * nt_sample / dt, "unit": "DM-trial*samples/s", "cores": 1,
+    n = host_cores()
+    return {"value": w.nd * nt_sample / dt, "unit": "DM-trial*samples/s", "cores": 1, "host_cores": n,
             "kind": "oracle",
             "sample": f"one step (forward uint8 -> int64, adjoint float64) of Nf=4096, Nd=2048 on the "
                       f"first {nt_sample} of 65536 samples, {reps} repetition(s), {dt:.2f} s each; "
-                      f"NumPy, single thread"}
+                      f"NumPy, single thread: 1 of {n} host cores"}
 
 
-PRECISION_FILE = os.path.join(ROOT, "profiles", "precision_c3.txt")
+def _oracle_c4_beam(b, nt):
+    """Oracle forward (float64) of beam b of the ragged workload (a pool worker)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import fdmt
+    w = W.WORKLOADS["c4"]
+    img, _ = W.make_c4_beam(b, nt)
+    fdmt(img.astype(np.float64), w.f_min, w.f_max, w.nd)
+    return w.nd * int(nt)
 
 
-def read_precision():
-    """Per-form accuracy measured against the oracle (tests/precision_report.py):
-    {form: {"exact": bool, "rms_rel_err": x, "max_err_rel_rms": y}}. Accuracy
-    does not depend on the schedule (every schedule adds the same tree)."""
+def _oracle_c5_beam(b):
+    """Oracle forward and adjoint (float64) of beam b of the differentiable
+    workload, the adjoint applied to the loss gradient softmax(A x) (a pool
+    worker)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import build_tables, fdmt, fdmt_adjoint
+    w = W.WORKLOADS["c5"]
+    x = W.make_c5()[b].astype(np.float64)
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    y = fdmt(x, w.f_min, w.f_max, w.nd, tab)
+    p = np.exp(y - y.max())
+    fdmt_adjoint(p / p.sum(), w.f_min, w.f_max, w.nf, tab)
+    return w.nd * w.nt
+
+
+def cpu_baselines_pooled(beams_c4=48):
+    """The ragged and differentiable workloads' oracle on a process pool over
+    beams (spawned interpreters that import only NumPy and the oracle)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import workloads as W
+    n = host_cores()
+    workers = min(MAX_POOL, n)
     out = {}
-    if not os.path.exists(PRECISION_FILE):
-        return out
-    for line in open(PRECISION_FILE):
-        if line.startswith("#") or not line.strip():
-            continue
-        f = line.split()
-        out[f[0]] = {"exact": f[3] == "1", "rms_rel_err": float(f[4]), "max_err_rel_rms": float(f[5])}
+    lengths = [int(v) for v in W.c4_lengths()][:beams_c4]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+        list(pool.map(_oracle_c4_beam, [0] * workers, [2048] * workers))  # start the workers
+        t0 = time.perf_counter()
+        cells = sum(pool.map(_oracle_c4_beam, range(len(lengths)), lengths))
+        dt = time.perf_counter() - t0
+        out["ragged_forward"] = {
+            "value": cells / dt, "unit": "DM-trial*samples/s", "cores": workers, "host_cores": n,
+            "kind": "oracle",
+            "sample": f"forward (float64) of beams 0-{len(lengths) - 1} of the 256-beam workload "
+                      f"({sum(lengths)} samples), one beam per worker, {workers} of {n} host cores, "
+                      f"{dt:.1f} s"}
+        w = W.WORKLOADS["c5"]
+        t0 = time.perf_counter()
+        cells = sum(pool.map(_oracle_c5_beam, range(w.batch)))
+        dt = time.perf_counter() - t0
+        out["differentiable"] = {
+            "value": cells / dt, "unit": "DM-trial*samples/s", "cores": workers, "host_cores": n,
+            "kind": "oracle",
+            "sample": f"the whole batch-16 workload: forward + adjoint of softmax (float64) per beam, "
+                      f"one beam per worker, {workers} of {n} host cores, {dt:.1f} s"}
     return out
+
+
+def accuracy(got, ref, integer):
+    """Error of a GPU result against the oracle: bit-exact flag, RMS error and
+    largest error, both relative to the oracle output's RMS."""
+    import numpy as np
+    ref64 = np.asarray(ref, dtype=np.float64)
+    err = np.asarray(got, dtype=np.float64) - ref64
+    rms = float(np.sqrt(np.mean(ref64 * ref64))) or 1.0
+    if integer:
+        exact = bool(np.array_equal(np.asarray(got).astype(np.int64), np.asarray(ref).astype(np.int64)))
+    else:
+        exact = bool(np.all(err == 0))
+    return {"exact": exact, "rms_rel_err": float(np.sqrt(np.mean(err * err))) / rms,
+            "max_err_rel_rms": float(np.max(np.abs(err))) / rms}
+
+
+def accuracy_leg(checks, w):
+    """Compares this run's GPU outputs with the oracle on their slices.
+    checks: {name: (kind, input slice, GPU output slice)}; kind 'fwd' (first
+    samples of a forward) or 'adj' (last samples of an adjoint)."""
+    import numpy as np
+
+    from oracle import build_tables, fdmt, fdmt_adjoint
+    tab = build_tables(w.nf, w.nd, w.f_min, w.f_max)
+    out = {}
+    for name, (kind, x, y) in checks.items():
+        integer = x.dtype.kind in "iu"
+        xin = x.astype(np.int64) if integer else x.astype(np.float64)
+        if kind == "fwd":
+            ref = fdmt(xin, w.f_min, w.f_max, w.nd, tab)
+        else:
+            ref = fdmt_adjoint(xin, w.f_min, w.f_max, w.nf, tab)
+        res = accuracy(y, ref, integer and y.dtype.kind in "iuf")
+        n = x.shape[-1]
+        res["sample"] = (f"first {n} of {w.nt} samples of every output row" if kind == "fwd"
+                         else f"last {n} of {w.nt} samples of every channel")
+        out[name] = res
+    return out
+
+
+# ------------------------------------------------------------------ GPU legs
+
+def copy_ceiling(F, torch, nbytes=1 << 30, reps=10):
+    """Read + write bandwidth of the library's streaming copy kernel on this
+    GPU (the practical ceiling of a kernel that moves every byte once)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    F.copy_bytes(b, a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        F.copy_bytes(b, a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    ok = bool(torch.equal(a, b))
+    del a, b
+    return {"bytes_copied": nbytes, "ms": round(ms, 4), "gb_s": round(2 * nbytes / ms / 1e6, 1), "verified": ok}
 
 
 def differentiable_c5(F, torch, W, reps=3):
@@ -198,6 +322,8 @@ def boxcar_on_output(F, torch, y, max_log2=8, reps=10):
 
 
 def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
+    """Tuned forward of one precision form on a fresh input; returns its timing
+    and the (input, output) slices the accuracy check compares."""
     plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, tuned=True)
     gen = torch.Generator(device="cuda").manual_seed(11)
     if in_dtype == torch.uint8:
@@ -217,7 +343,9 @@ def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
-    return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0)}
+    k = ACCURACY_SAMPLES
+    sl = ("fwd", x[:, :k].cpu().numpy(), y[:, :k].cpu().numpy())
+    return {"ms": round(ms, 4), "dm_trial_samples_per_s": w.nd * w.nt / (ms / 1000.0)}, sl
 
 
 def fft_fdmt(F, torch, w, shift_ms, reps=5):
@@ -298,23 +426,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=32768,
-                    help="samples of the workload the CPU oracle baseline processes (0: skip)")
+                    help="samples of the workload the CPU oracle baseline processes (0: skip the CPU leg, "
+                         "including the accuracy checks)")
     ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the ragged-batch and differentiable workloads")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="only run one plain device-to-device copy of BYTES (HBM counter calibration)")
+                    help="only run one streaming copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
-    if args.copy_probe:
-        import torch
-        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(beams and time ranges shard across GPUs without exchange, see the design notes)",
@@ -328,6 +447,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        F.copy_bytes(b, a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+
+    copy = copy_ceiling(F, torch)
     w = W.WORKLOADS["c3"]
     plan = F.Plan(w.nf, w.nt, w.nd, w.f_min, w.f_max, in_dtype=torch.uint8, acc_dtype=torch.float32,
                   tuned=True)
@@ -339,6 +469,9 @@ def main():
     torch.cuda.synchronize()
 
     ms_step, per, infos = time_steps(plan, (x, y, g, xb, ws), args.steps, args.warmup, torch)
+    k = ACCURACY_SAMPLES
+    checks = {"step_forward_u8_f32": ("fwd", x[:, :k].cpu().numpy(), y[:, :k].cpu().numpy()),
+              "step_adjoint_f32": ("adj", g[:, -k:].cpu().numpy(), xb[:, -k:].cpu().numpy())}
     fwd_ms = sum(m for m, (d, _) in zip(per, infos) if d == "forward")
     adj_ms = sum(m for m, (d, _) in zip(per, infos) if d == "adjoint")
     fwd_bytes = sum(i["bytes_read"] + i["bytes_written"] for d, i in infos if d == "forward")
@@ -361,7 +494,9 @@ def main():
                   "schedule_gb": round(b / 1e9, 3), "compulsory_gb_s": round(compulsory[d] / ms / 1e6, 1)}
               for d, b, ms in (("forward", fwd_bytes, fwd_ms), ("adjoint", adj_bytes, adj_ms))}
     kernels = [{"direction": d, "kind": i["kind"], "levels": [i["level_first"], i["level_last"]],
-                "ms": round(m, 4), "alg_gb_s": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6, 1)}
+                "ms": round(m, 4), "alg_gb_s": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6, 1),
+                "frac_of_peak": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / HBM_PEAK_GBS, 3),
+                "frac_of_copy": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / copy["gb_s"], 3)}
                for m, (d, i) in zip(per, infos)]
 
     out = {
@@ -389,26 +524,23 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": key, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "algorithmic_bytes": alg, "launch_ms": round(per[j], 4),
+                     "copy_ceiling_gb_s": copy["gb_s"], "frac_of_copy": round(achieved / copy["gb_s"], 4)},
+        "copy_ceiling": copy,
     }
     if not args.no_forms:
-        forms = {
-            "u8_in_f32_acc": forward_only(F, torch, w, torch.uint8, torch.float32),
-            "f16_in_f32_acc": forward_only(F, torch, w, torch.float16, torch.float32),
-            "f32_in_f32_acc": forward_only(F, torch, w, torch.float32, torch.float32),
-            "u8_in_i32_acc": forward_only(F, torch, w, torch.uint8, torch.int32),
-            "i32_in_i32_acc": forward_only(F, torch, w, torch.int32, torch.int32),
-        }
-        acc = read_precision()
-        for name, form in forms.items():
+        names = {"u8_in_f32_acc": (torch.uint8, torch.float32), "f16_in_f32_acc": (torch.float16, torch.float32),
+                 "f32_in_f32_acc": (torch.float32, torch.float32), "u8_in_i32_acc": (torch.uint8, torch.int32),
+                 "i32_in_i32_acc": (torch.int32, torch.int32)}
+        forms = {}
+        for name, (i, a) in names.items():
+            forms[name], checks[name] = forward_only(F, torch, w, i, a)
+            torch.cuda.empty_cache()
+        for form in forms.values():
             form["speedup_vs_f32"] = round(forms["f32_in_f32_acc"]["ms"] / form["ms"], 3)
-            if name in acc:
-                form["accuracy_vs_oracle"] = acc[name]
         out["precision_forms"] = forms
         out["fft_fdmt"] = fft_fdmt(F, torch, w, forms["f32_in_f32_acc"]["ms"])
         torch.cuda.empty_cache()
-        if "adjoint_f32" in acc:
-            out["adjoint"]["accuracy_vs_oracle"] = acc["adjoint_f32"]
     out["boxcar"] = boxcar_on_output(F, torch, y)
     del x, g, y, xb, ws, plan
     if not args.no_ragged:
@@ -418,7 +550,14 @@ def main():
         out["differentiable"] = differentiable_c5(F, torch, W)
         torch.cuda.empty_cache()
     if args.cpu_sample > 0:
+        acc = accuracy_leg(checks, w)
+        out["forward"]["accuracy_vs_oracle"] = acc.pop("step_forward_u8_f32")
+        out["adjoint"]["accuracy_vs_oracle"] = acc.pop("step_adjoint_f32")
+        for name, res in acc.items():
+            out["precision_forms"][name]["accuracy_vs_oracle"] = res
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        if not args.no_ragged:
+            out["cpu_baselines"] = cpu_baselines_pooled()
     print(json.dumps(out), flush=True)
 
 

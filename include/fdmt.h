@@ -330,6 +330,15 @@ size_t fdmt_boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_
 fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
                                  fdmt_boxcar_t *out, void *ws, size_t ws_bytes, void *hip_stream);
 
+/* Streaming device copy of `bytes` bytes (16-byte aligned, non-overlapping
+ * device buffers), enqueued on hip_stream. Not part of the transform: a
+ * kernel that reads and writes every byte once, coalesced, 16 bytes per lane,
+ * so its bandwidth is the practical ceiling of the transform's HBM-bound
+ * gathers on the same device (the HBM peak is the other reference).
+ * FDMT_E_INVALID for NULL, misaligned or overlapping buffers; bytes = 0 is a
+ * no-op. Allocates nothing. */
+fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Tuned schedule lookup. The package's autotuner times candidate schedules
  * on the GPU and stores the fastest per workload in a JSON cache; this call
  * lets a C caller start from that schedule as the Python layer does. The

@@ -29,7 +29,7 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
-            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_tuned_options", "fdmt_status_string",
+            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
             "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
@@ -126,6 +126,8 @@ def load():
     lib.fdmt_boxcar_workspace_bytes.restype = sz
     lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.fdmt_boxcar_search.restype = ctypes.c_int
+    lib.fdmt_copy_bytes.argtypes = [vp, vp, sz, vp]
+    lib.fdmt_copy_bytes.restype = ctypes.c_int
     lib.fdmt_tuned_options.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, i64, i32, ctypes.c_double,
                                        ctypes.c_double, ctypes.POINTER(_Options), p_i32]
     lib.fdmt_tuned_options.restype = ctypes.c_int
@@ -169,6 +171,20 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
+
+
+def fdmt_copy_bytes(dst_ptr, src_ptr, nbytes, stream):
+    _check(load().fdmt_copy_bytes(dst_ptr, src_ptr, int(nbytes), stream), "fdmt_copy_bytes")
+
+
+def copy_bytes(dst, src):
+    """Streaming copy of src's bytes into dst (device tensors of equal byte
+    size) with the library's copy kernel, on the current stream."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst and src must be contiguous and of equal byte size")
+    fdmt_copy_bytes(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n, _stream_handle(src.device))
+    return dst
 
 
 SCHEDULE_FIELDS = ("first_levels", "later_levels", "tile", "lds_kib", "max_block_rows", "first_kernel",

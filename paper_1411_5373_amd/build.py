@@ -28,7 +28,7 @@ HIP_FLAGS = [
 CXX_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
 
 HIP_SOURCES = ["fdmt_kernels.hip", "fdmt_gather.hip", "fdmt_narrow.hip", "fdmt_adjoint.hip", "fdmt_boxcar.hip",
-               "fdmt_fft.hip", "fdmt_api.hip"]
+               "fdmt_fft.hip", "fdmt_copy.hip", "fdmt_api.hip"]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib",  # FFT-FDMT's transforms
         "-ldl"]  # dladdr: the tuning cache beside the library
 CXX_SOURCES = ["fdmt_tables.cpp", "fdmt_schedule.cpp", "fdmt_tune.cpp"]

@@ -13,6 +13,7 @@
 
 #include "../../include/fdmt.h"
 #include "fdmt_boxcar.h"
+#include "fdmt_copy.h"
 #include "fdmt_fft.h"
 #include "fdmt_plan.h"
 #include "fdmt_tune.h"
@@ -763,6 +764,18 @@ fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, 
   const hipError_t e =
       fdmt::launch_boxcar(plane, batch, nd, nt, max_log2, out, ws, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return device_fail(e, "boxcar search launch");
+  return FDMT_OK;
+}
+
+fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hip_stream) {
+  if (bytes == 0) return FDMT_OK;
+  if (!dst || !src) return fail(FDMT_E_INVALID, "src or dst is NULL");
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) != 0)
+    return fail(FDMT_E_INVALID, "src and dst must be 16-byte aligned");
+  const uintptr_t d = reinterpret_cast<uintptr_t>(dst), s = reinterpret_cast<uintptr_t>(src);
+  if (d < s + bytes && s < d + bytes) return fail(FDMT_E_INVALID, "src and dst overlap");
+  const hipError_t e = fdmt::launch_stream_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "stream copy launch");
   return FDMT_OK;
 }
 

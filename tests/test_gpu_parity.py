@@ -527,3 +527,13 @@ def test_uint16_planes_exact(sched, nf, nt, nd, band):
         y = narrow.forward(xd)
         assert torch.equal(y, wide.forward(xd))
         np.testing.assert_array_equal(y.cpu().numpy().astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("nbytes", [1, 15, 16, 17, 4096, 1 << 20, (1 << 22) + 7])
+def test_copy_bytes(nbytes):
+    """The streaming copy the benchmark measures its ceiling with copies every
+    byte, including a tail shorter than 16 bytes."""
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=DEV)
+    dst = torch.zeros_like(src)
+    F.copy_bytes(dst, src)
+    assert torch.equal(dst, src)
