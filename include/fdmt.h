@@ -142,6 +142,22 @@ typedef struct {
                                   groups of a tile together; suits passes whose leaves sit at
                                   large shifts (0 = default: none). Uniform batches only:
                                   ragged launches follow their tile maps */
+  int32_t gather_threads;  /* workgroup size of the forward cache gathers: 64, 128, 256, 512 or
+                              1024 threads, at least 64 * gather_rows (0 = default 1024). A
+                              workgroup covers its rows over (threads / 64 / rows) waves per
+                              row; smaller workgroups let a CU start new work as single
+                              waves finish */
+  int32_t adjoint_threads; /* the same for the adjoint gathers into planes, at least
+                              64 * gather_rows (0 = default 1024) */
+  int32_t adjoint_last_threads; /* the same for the last adjoint pass (into the channels), at
+                                   least 64 times its rows per workgroup (0 = adjoint_threads) */
+  int32_t rule;           /* delay-table rule (Sec. 4.2, rounding and binning): 0 = one C per
+                             merge at the border frequency, the halves sharing the sample t1;
+                             1 = two C's: a channel is the point of its label (lower edge), a
+                             sub-band spans its first to its last label, the lower half's
+                             delay uses C at the lower sub-band's end label and the upper
+                             half's shift C at the upper sub-band's start label, so each
+                             output adds one sample per channel. Changes the results */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

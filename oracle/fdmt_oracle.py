@@ -56,6 +56,19 @@ listed with its justification in the design notes):
          it is read as Algorithm 1's (reading R-init), since both algorithms
          compute the same transform. Its time axis is zero-padded to
          Nt + Nd - 1 samples, the least padding after which no path wraps.
+  R-twoC the two versions of C (Sec. 4.2, rounding and binning), a table rule
+         of its own (rule=1): a channel is the point of its label (lower
+         edge) e_k and a sub-band's delay runs from its first channel's label
+         to its last's. Merging [k0..km-1] and [km..k1]: the lower half's delay
+         is d_lo = round_half_up(dt * C_lo), C_lo = C with f1 = e_{km-1} (the
+         end frequency of the lower sub-band) and f2 = e_{k1}; the upper half
+         starts s = round_half_up(dt * C_hi) back, C_hi = C with f1 = e_{km}
+         (the start frequency of the upper sub-band), and spans d_hi = dt - s.
+         The curve's travel between the two labels is then the gap s - d_lo.
+         A channel alone spans no delay, so each needs only row 0 (its
+         samples, the Option-1 sum with no chain) and every output adds one
+         sample per channel. Copy nodes and channel-free sub-bands as in
+         R-nf. Parity unpinned against the authors' code, which is absent.
   R-nf   Nf need not be a power of two (Sec. 4.2, the case Nf != 2^k): the
          iterations still pair sub-bands 2j and 2j+1, sub-band j of iteration
          l holding channels j*2^l .. min((j+1)*2^l, Nf) - 1, so there are
@@ -122,13 +135,14 @@ class Tables:
                                 # in a copy node (reading R-nf)
     gamma: float = -2.0         # delay law dt ~ f^gamma
     pre: list = None            # per channel: the d_min pre-shift (reading R-dmin)
+    rule: int = 0               # 0: one C at the border (R-round); 1: two C's (R-twoC)
 
     @property
     def leaf_rows(self):
         return self.rows[0]
 
 
-def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
+def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0, rule=0):
     """Per iteration l = 1..log2(Nf) and sub-band j (channels j*2^l .. (j+1)*2^l - 1,
     f0 = e[j*2^l], f1 = e[(2j+1)*2^(l-1)], f2 = e[(j+1)*2^l]):
         for each dt: t0 - t1 = d_lo = round(C_{f2,f0} * dt)   (lower half's delay)
@@ -138,7 +152,11 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
     gamma: the delay law dt ~ f^gamma (reading R-law). d_min: the smallest
     delay searched (reading R-dmin), which sets the per-channel pre-shift.
     Any Nf >= 1 (reading R-nf): sub-band j of iteration l holds channels
-    j*2^l .. min((j+1)*2^l, Nf) - 1; f2 is the upper edge of its last channel."""
+    j*2^l .. min((j+1)*2^l, Nf) - 1; f2 is the upper edge of its last channel.
+    rule=1 (reading R-twoC): two coefficients per merge, from the lower
+    sub-band's last label and the upper sub-band's first, over the band's
+    label span; the lower half's delay and the upper half's shift then
+    differ."""
     if nf < 1:
         raise ValueError("Nf must be >= 1")
     if nd < 1:
@@ -149,6 +167,8 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
         raise ValueError("gamma must be finite and nonzero")
     if d_min < 0:
         raise ValueError("d_min must be >= 0")
+    if rule not in (0, 1):
+        raise ValueError("rule must be 0 (one C) or 1 (two C's)")
     levels = (nf - 1).bit_length()
     e = channel_edges(nf, f_min, f_max)
 
@@ -171,14 +191,24 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
                 split[l].append([(dt, 0, None) for dt in range(rows[l][j])])
                 rows[l - 1][2 * j] = rows[l][j]
                 continue
-            f0 = e[j << l]
-            f1 = e[(2 * j + 1) << (l - 1)]
-            f2 = e[min((j + 1) << l, nf)]
-            c = merge_coefficient(f0, f1, f2, gamma)
             triples = []
-            for dt in range(rows[l][j]):
-                d_lo = round_half_up(dt * c)
-                triples.append((d_lo, d_lo, dt - d_lo))
+            if rule == 0:
+                f0 = e[j << l]
+                f1 = e[(2 * j + 1) << (l - 1)]
+                f2 = e[min((j + 1) << l, nf)]
+                c = merge_coefficient(f0, f1, f2, gamma)
+                for dt in range(rows[l][j]):
+                    d_lo = round_half_up(dt * c)
+                    triples.append((d_lo, d_lo, dt - d_lo))
+            else:
+                mid = (2 * j + 1) << (l - 1)            # first channel of the upper half
+                first, last = e[j << l], e[min((j + 1) << l, nf) - 1]
+                c_lo = merge_coefficient(first, e[mid - 1], last, gamma)
+                c_hi = merge_coefficient(first, e[mid], last, gamma)
+                for dt in range(rows[l][j]):
+                    d_lo = round_half_up(dt * c_lo)
+                    s = round_half_up(dt * c_hi)
+                    triples.append((d_lo, s, dt - s))
             split[l].append(triples)
             last = triples[-1]
             rows[l - 1][2 * j] = last[0] + 1
@@ -190,7 +220,7 @@ def build_tables(nf, nd, f_min, f_max, gamma=-2.0, d_min=0):
             centre = 0.5 * (e[k] + e[k + 1])
             phi = (_law(f_min, gamma) - _law(centre, gamma)) / den
             pre[k] = round_half_up(float(d_min) * phi)
-    return Tables(nf, nd, f_min, f_max, levels, rows, split, float(gamma), pre)
+    return Tables(nf, nd, f_min, f_max, levels, rows, split, float(gamma), pre, rule)
 
 
 # ----------------------------------------------------------------------------

@@ -41,19 +41,23 @@ GATHER_ROWS_DEFAULT = 8  # the library's gather_rows when the option is 0
 # Fields that shape only the forward or only the adjoint schedule.
 FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
                   "max_block_rows", "stream_tiles")
-ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows", "adjoint_tile_major")
+ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows", "adjoint_tile_major",
+                  "adjoint_last_threads")
 SHARED_FIELDS = ("gather_rows", "gather_vecs")
 
 
 def forward_candidates():
     """Forward schedules worth timing: level-by-level LDS first pass, or a
-    gather straight from the input, followed by cache gathers."""
+    gather straight from the input, followed by cache gathers or staged
+    gathers."""
     out = []
     for later in (2, 3):
         out.append(dict(first_kernel=2, first_levels=4, later_levels=later))
         out.append(dict(first_kernel=2, first_levels=4, later_levels=later, stream_tiles=1))
         for first in (2, 3, 4):
             out.append(dict(first_kernel=3, first_levels=first, later_levels=later))
+        # later passes as staged gathers (each workgroup's term rows in LDS)
+        out.append(dict(first_kernel=3, first_levels=3, later_levels=later, later_kernel=1))
     return out
 
 
@@ -65,10 +69,22 @@ TILE_MAJOR_MASKS = ("none", "ends", "all")
 
 def adjoint_candidates(gather_rows=GATHER_ROWS_DEFAULT):
     """Adjoint pass depths, channels per workgroup of the last pass (the shared
-    gather shape, or a whole sub-band per workgroup) and work order."""
+    gather shape, or a whole sub-band per workgroup), the last pass's
+    workgroup size (1024 threads, or 256 with at most 4 channels) and work
+    order."""
     last_rows = [0] + [r for r in (8, 16) if r > gather_rows]
-    return [dict(adjoint_levels=a, adjoint_last_levels=b, adjoint_last_rows=r, adjoint_tile_major=m)
-            for a in (1, 2, 3) for b in (1, 2, 3) for r in last_rows for m in TILE_MAJOR_MASKS]
+    small = [r for r in ([0] if gather_rows <= 4 else []) + [2, 4] if r != gather_rows]
+    shapes = [(r, 0) for r in last_rows] + [(r, 256) for r in small]
+    out = []
+    for a in (1, 2, 3):
+        for b in (1, 2, 3):
+            for r, th in shapes:
+                for m in TILE_MAJOR_MASKS:
+                    c = dict(adjoint_levels=a, adjoint_last_levels=b, adjoint_last_rows=r, adjoint_tile_major=m)
+                    if th:
+                        c["adjoint_last_threads"] = th
+                    out.append(c)
+    return out
 
 
 def tile_major_mask(name, passes):
@@ -111,8 +127,9 @@ def nt_bucket(nt):
     return b
 
 
-def cache_key(arch_name, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=-2.0):
+def cache_key(arch_name, nf, nt, nd, f_min, f_max, in_dtype, acc_dtype, gamma=-2.0, rule=0):
     law = "" if float(gamma) == -2.0 else f"/gamma{float(gamma):.6g}"
+    law += "/twoC" if rule == 1 else ""
     return (f"{arch_name}/nf{nf}/nd{nd}/band{float(f_min):.6g}-{float(f_max):.6g}{law}/"
             f"{_NAMES[in_dtype]}->{_NAMES[acc_dtype]}/nt{nt_bucket(nt)}")
 

@@ -56,7 +56,9 @@ class _Options(ctypes.Structure):
                 ("adjoint_levels", ctypes.c_int32), ("adjoint_last_levels", ctypes.c_int32),
                 ("gather_vecs", ctypes.c_int32), ("adjoint_last_rows", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32),
-                ("adjoint_tile_major", ctypes.c_uint32)]
+                ("adjoint_tile_major", ctypes.c_uint32), ("gather_threads", ctypes.c_int32),
+                ("adjoint_threads", ctypes.c_int32), ("adjoint_last_threads", ctypes.c_int32),
+                ("rule", ctypes.c_int32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -160,14 +162,15 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
               first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
               adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0,
-              adjoint_tile_major=0):
+              adjoint_tile_major=0, gather_threads=0, adjoint_threads=0, adjoint_last_threads=0, rule=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
                    int(later_levels), int(tile), int(lds_kib), int(max_block_rows),
                    int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows),
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
-                   int(adjoint_last_rows), float(gamma), int(d_min), int(adjoint_tile_major))
+                   int(adjoint_last_rows), float(gamma), int(d_min), int(adjoint_tile_major),
+                   int(gather_threads), int(adjoint_threads), int(adjoint_last_threads), int(rule))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -189,15 +192,16 @@ def copy_bytes(dst, src):
 
 SCHEDULE_FIELDS = ("first_levels", "later_levels", "tile", "lds_kib", "max_block_rows", "first_kernel",
                    "later_kernel", "stream_tiles", "gather_rows", "adjoint_levels", "adjoint_last_levels",
-                   "gather_vecs", "adjoint_last_rows", "adjoint_tile_major")
+                   "gather_vecs", "adjoint_last_rows", "adjoint_tile_major", "gather_threads", "adjoint_threads",
+                   "adjoint_last_threads")
 
 
 def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, gamma=0.0, d_min=0,
-                       cache_path=None, arch=None, **explicit):
+                       rule=0, cache_path=None, arch=None, **explicit):
     """The autotuner's schedule for this workload through the C ABI: a dict of
     the schedule fields the cache sets (explicit nonzero fields kept as given),
     or None when the cache has no entry."""
-    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0)
+    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0, 0, 0, 0, int(rule))
     for k, v in explicit.items():
         setattr(opt, k, int(v))
     found = ctypes.c_int32()
@@ -339,9 +343,11 @@ class Plan:
 
     def __init__(self, nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float32,
                  host_only=False, unfused=False, tuned=False, wide_planes=False, gamma=-2.0, d_min=0,
-                 fft=False, **schedule):
+                 fft=False, rule=0, **schedule):
         """`gamma`: the delay law dt ~ f^gamma (-2: cold plasma). `d_min`: the
-        smallest delay searched (row dt is delay d_min + dt). `fft`: also build
+        smallest delay searched (row dt is delay d_min + dt). `rule`: the
+        delay-table rule (0: one C per merge; 1: two C's, see
+        fdmt_options_t). `fft`: also build
         the FFT-FDMT state for forward_fft(). `schedule`:
         fdmt_options_t schedule fields (first_kernel, first_levels, ...).
         tuned=True first takes the autotuner's stored options for this
@@ -350,6 +356,7 @@ class Plan:
         self.f_min, self.f_max = float(f_min), float(f_max)
         self.gamma = float(gamma)
         self.d_min = int(d_min)
+        self.rule = int(rule)
         self.in_dtype, self.acc_dtype = in_dtype, acc_dtype
         flags = ((FDMT_PLAN_HOST_ONLY if host_only else 0) | (FDMT_PLAN_UNFUSED if unfused else 0) |
                  (FDMT_PLAN_WIDE_PLANES if wide_planes else 0) | (FDMT_PLAN_FFT if fft else 0))
@@ -359,13 +366,15 @@ class Plan:
             # the cache lookup is the library's (fdmt_tuned_options); explicit
             # schedule fields override the cached ones
             self.tuned = fdmt_tuned_options(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
-                                            _TORCH_TO_CODE[acc_dtype], gamma=self.gamma, d_min=self.d_min)
+                                            _TORCH_TO_CODE[acc_dtype], gamma=self.gamma, d_min=self.d_min,
+                                            rule=self.rule)
             if self.tuned:
                 schedule = dict(self.tuned, **schedule)
         self.options = dict(schedule)
         self.handle = None
         self.handle = fdmt_plan(nf, nt, nd, f_min, f_max, _TORCH_TO_CODE[in_dtype],
-                                _TORCH_TO_CODE[acc_dtype], flags, gamma=self.gamma, d_min=self.d_min, **schedule)
+                                _TORCH_TO_CODE[acc_dtype], flags, gamma=self.gamma, d_min=self.d_min,
+                                rule=self.rule, **schedule)
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None

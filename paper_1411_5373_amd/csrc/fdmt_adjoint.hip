@@ -22,11 +22,14 @@ namespace {
 // to its parent at depth K-1. A leaf sample at or past nt is zero, which is
 // the transpose's "t + s < nt" rule.
 //
-// Leaves are loaded kChunk at a time, all eight runs of four samples in
-// flight before any is used. A wave whose samples, at every shift of the
-// pass, stay below nt (all but the last tile of a row) takes the interior
-// path, whose loads need no checks; the edge path checks every access.
+// Leaves are loaded a chunk at a time, all eight runs of four samples in
+// flight before any is used (four leaves of one run: a longer unrolled chunk
+// of single runs needs more registers than the 1024-thread budget allows).
+// A wave whose samples, at every shift of the pass, stay below nt (all but
+// the last tile of a row) takes the interior path, whose loads need no
+// checks; the edge path checks every access.
 constexpr int kAdjChunk = 8;
+constexpr int adjoint_chunk(int cv) { return cv == 1 ? kAdjChunk / 2 : kAdjChunk / cv; }
 
 // Four lanes' worth of accumulator in registers (naturally aligned; memory
 // accesses go through the 4-byte-aligned Vec4).
@@ -127,7 +130,7 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
                                              const int4 *__restrict__ leaves, int x0, int x1, int t, int nt) {
   typedef typename Vec4<Tacc>::type V;
   typedef Reg4<Tacc> R;
-  constexpr int kChunk = kAdjChunk / CV;
+  constexpr int kChunk = adjoint_chunk(CV);
   for (int x = x0; x < x1; x += kChunk) {
     const int n = x1 - x < kChunk ? x1 - x : kChunk;
     int4 e[kChunk];
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     int32_t rows_per_wg, int32_t tiles_fastest, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   constexpr int kSpan = adjoint_wave_span(CV, LAG);
-  const int waves = kGatherThreads / 64;
+  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
@@ -225,7 +228,7 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
                                  int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                                  int32_t nrows) {
 #define FDMT_ADJ(KK, CC, RR, LL)                                                                         \
-  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL>), g.grid, dim3(kGatherThreads), 0, g.stream, \
+  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL>), g.grid, dim3(g.threads), 0, g.stream, \
                      src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,      \
                      dst_bstride, nrows, g.rows_per_wg, g.tiles_fastest, g.rg)
 #define FDMT_ADJ_K(CC, RR)                                    \

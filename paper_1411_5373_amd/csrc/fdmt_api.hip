@@ -214,9 +214,24 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
   if (o.adjoint_last_rows < 0 || o.adjoint_last_rows > 16 || (o.adjoint_last_rows & (o.adjoint_last_rows - 1)))
     return fail(FDMT_E_INVALID, "adjoint_last_rows must be 1, 2, 4, 8 or 16");
+  for (int32_t th : {o.gather_threads, o.adjoint_threads, o.adjoint_last_threads})
+    if (th < 0 || th > 1024 || (th && (th < 64 || (th & (th - 1)))))
+      return fail(FDMT_E_INVALID, "gather_threads, adjoint_threads and adjoint_last_threads must be 64, 128, 256, "
+                                  "512 or 1024");
+  {
+    const int rows = o.gather_rows ? o.gather_rows : 8;
+    const int last_rows = o.adjoint_last_rows ? o.adjoint_last_rows : rows;
+    const int adj = o.adjoint_threads ? o.adjoint_threads : 1024;
+    if (64 * rows > (o.gather_threads ? o.gather_threads : 1024))
+      return fail(FDMT_E_INVALID, "gather_threads must be at least 64 * gather_rows");
+    if (64 * rows > adj) return fail(FDMT_E_INVALID, "adjoint_threads must be at least 64 * gather_rows");
+    if (64 * last_rows > (o.adjoint_last_threads ? o.adjoint_last_threads : adj))
+      return fail(FDMT_E_INVALID, "the last adjoint pass's workgroup must hold at least 64 * its rows threads");
+  }
   // Shifts, sample indices and their sums stay int32 in the kernels: d_min is
   // at most 2^30, and Nt + d_min + 2 Nd leaves 2^13 samples of headroom.
   if (o.d_min < 0 || o.d_min > (1 << 30)) return fail(FDMT_E_INVALID, "d_min must be in [0, 2^30]");
+  if (o.rule != 0 && o.rule != 1) return fail(FDMT_E_INVALID, "rule must be 0 (one C) or 1 (two C's)");
   if (nt + o.d_min + 2 * static_cast<int64_t>(nd) > INT32_MAX - 8192)
     return fail(FDMT_E_INVALID, "Nt + d_min + 2 Nd must stay below 2^31 - 8192");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
@@ -233,7 +248,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   fdmt::Plan &p = h->plan;
   try {
     const std::string err =
-        fdmt::build_tables(p.tab, nf, nd, f_min, f_max, o.gamma != 0.0 ? o.gamma : -2.0, o.d_min);
+        fdmt::build_tables(p.tab, nf, nd, f_min, f_max, o.gamma != 0.0 ? o.gamma : -2.0, o.d_min, o.rule);
     if (!err.empty()) {
       delete h;
       return fail(FDMT_E_INVALID, err);
@@ -250,6 +265,9 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (o.stream_tiles) p.tiles_per_wg = p.rec_tiles = o.stream_tiles;
   if (o.gather_rows) p.gather_rows = o.gather_rows;
   if (o.gather_vecs) p.gather_vecs = o.gather_vecs;
+  if (o.gather_threads) p.gather_threads = o.gather_threads;
+  if (o.adjoint_threads) p.adjoint_threads = o.adjoint_threads;
+  p.adjoint_last_threads = o.adjoint_last_threads;
   p.adjoint_last_rows = o.adjoint_last_rows;
   p.adjoint_tile_major = o.adjoint_tile_major;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
@@ -467,9 +485,9 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->kind = ps.kind == fdmt::PassKind::Staged ? 7 : !ps.gather ? 2 : ps.from_input ? 6 : 5;
       info->level_first = ps.from_input ? 0 : ps.l0 + 1;
       info->level_last = ps.l1;
-      const int fv = P.gather_vecs < 2 ? P.gather_vecs : 2;  // forward gathers take at most 2 runs
+      const int64_t gt = fdmt::step_tile(P, false, step);  // samples per gather workgroup
       info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
-                                                          ((nt + 4096 * fv / P.gather_rows - 1) / (4096 * fv / P.gather_rows)))
+                                                          ((nt + gt - 1) / gt))
                                    : static_cast<int32_t>(
                                          ps.nblocks *
                                          ((nt + ps.tile - 1) / ps.tile +
@@ -812,7 +830,8 @@ fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32
     path = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning/" + a + ".json";
   }
   const double gamma = opt->gamma != 0.0 ? opt->gamma : -2.0;
-  const std::string key = fdmt::tune_key(a, nf, nt, nd, f_min, f_max, opt->in_dtype, opt->acc_dtype, gamma);
+  const std::string key =
+      fdmt::tune_key(a, nf, nt, nd, f_min, f_max, opt->in_dtype, opt->acc_dtype, gamma, opt->rule);
   std::map<std::string, double> o;
   bool hit = false;
   std::string err;
@@ -841,7 +860,10 @@ fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32
                           {"adjoint_last_levels", &opt->adjoint_last_levels, nullptr},
                           {"gather_vecs", &opt->gather_vecs, nullptr},
                           {"adjoint_last_rows", &opt->adjoint_last_rows, nullptr},
-                          {"adjoint_tile_major", nullptr, &opt->adjoint_tile_major}};
+                          {"adjoint_tile_major", nullptr, &opt->adjoint_tile_major},
+                          {"gather_threads", &opt->gather_threads, nullptr},
+                          {"adjoint_threads", &opt->adjoint_threads, nullptr},
+                          {"adjoint_last_threads", &opt->adjoint_last_threads, nullptr}};
   for (const auto &kv : o) {
     const Field *f = nullptr;
     for (const Field &c : fields)

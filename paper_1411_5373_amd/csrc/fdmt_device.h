@@ -102,7 +102,8 @@ __device__ __forceinline__ int2 gather_item(int groups, bool tiles_fastest) {
 // makes them scalar loads.
 typedef const __attribute__((address_space(4))) int32_t *ConstInts;
 
-// Workgroup size of the register-gather kernels.
+// Largest workgroup of the register-gather kernels (their register budget is
+// set for it); a launch may use 64 .. 1024 threads, a power of two.
 constexpr int kGatherThreads = 1024;
 
 // Four consecutive elements at 4-byte alignment: one 16-byte global access.

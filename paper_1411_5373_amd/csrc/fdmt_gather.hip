@@ -35,9 +35,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   constexpr int N = 1 << K;
   // A workgroup holds rows_per_wg consecutive output rows (the rows share
   // most terms, so repeats hit this CU's L1) over one tile of
-  // 256 * CV * (kGatherThreads / 64 / rows_per_wg) samples; a lane handles CV
+  // 256 * CV * (blockDim.x / 64 / rows_per_wg) samples; a lane handles CV
   // runs of 4 samples, 256 apart.
-  const int waves = kGatherThreads / 64;
+  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;  // waves per row
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
   typedef typename Vec4<Tdst>::type D4;
   typedef typename In4<Tin>::type I4;
   constexpr int N = 1 << K;
-  const int waves = kGatherThreads / 64;
+  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
@@ -343,7 +343,7 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
 #define FDMT_GATHER(KK, CC, RR)                                                                         \
-  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, \
+  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0, \
                      g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, \
                      g.rows_per_wg, g.rg)
 #define FDMT_GATHER_K(CC, RR)             \
@@ -368,7 +368,7 @@ template <typename Tin, typename Tacc, typename Tdst>
 hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows) {
 #define FDMT_IGATHER(KK, CC, RR)                                                                          \
-  hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0, \
+  hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0, \
                      g.stream, src, dst, terms, nt, src_bstride, dst_stride, dst_bstride, nrows,          \
                      g.rows_per_wg, g.rg)
 #define FDMT_IGATHER_K(CC, RR)             \

@@ -738,7 +738,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;
         const int cv = forward_vecs(p);
-        const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
+        const int tile = 256 * cv * (p.gather_threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int4 *tm = p.dev_iterms + ps.term_offset;
@@ -746,7 +746,8 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const bool narrow_out = p.narrow[st.index];
         const bool int_sums = p.int_sums[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-          const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          g.threads = p.gather_threads;
           if constexpr (std::is_same<Tin, uint8_t>::value) {
             if (narrow_out)  // exact integer sums below 2^16
               return launch_narrow_input_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
@@ -764,14 +765,15 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
         const int cv = forward_vecs(p);  // runs of 4 samples per lane: 1 or 2
-        const int tile = 256 * cv * (kGatherThreads / 64 / rpw);
+        const int tile = 256 * cv * (p.gather_threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int2 *tm = p.dev_terms + ps.term_offset;
         const bool narrow_in = st.index > 0 && p.narrow[st.index - 1];
         const bool narrow_out = p.narrow[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-          const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
+          g.threads = p.gather_threads;
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
             // uint16 out: the integer-sum kernel (a lane's 8 samples are one
@@ -844,7 +846,8 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       if (ps.depth < 1 || ps.depth > 5) return hipErrorInvalidValue;
       const int rpw = adjoint_rows(p, st.index);
       const int cv = p.gather_vecs;
-      const int tile = adjoint_wave_span(cv, ps.lagged) * (kGatherThreads / 64 / rpw);
+      const int threads = adjoint_threads(p, st.index);
+      const int tile = adjoint_wave_span(cv, ps.lagged) * (threads / 64 / rpw);
       const unsigned gx = static_cast<unsigned>((ps.nrows + rpw - 1) / rpw);
       const int4 *lv = p.dev_adj_leaves + ps.leaf_offset;
       const int32_t *sr = p.dev_adj_starts + ps.start_offset;
@@ -854,7 +857,8 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       const int32_t nt32 = static_cast<int32_t>(nt);
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
         const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw, ps.lagged,
-                             st.index < 32 ? static_cast<int>((p.adjoint_tile_major >> st.index) & 1u) : 0};
+                             st.index < 32 ? static_cast<int>((p.adjoint_tile_major >> st.index) & 1u) : 0,
+                             threads};
         return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, ps.max_shift, src.stride, src.bstride,
                                            dst.stride, dst.bstride, ps.nrows);
       });
@@ -1067,9 +1071,13 @@ int adjoint_rows(const Plan &p, int pass) {
   return p.adj.passes[pass].to_input && p.adjoint_last_rows ? p.adjoint_last_rows : p.gather_rows;
 }
 
+int adjoint_threads(const Plan &p, int pass) {
+  return p.adj.passes[pass].to_input && p.adjoint_last_threads ? p.adjoint_last_threads : p.adjoint_threads;
+}
+
 int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
-  const int gather_tile = 256 * forward_vecs(p) * (kGatherThreads / 64 / p.gather_rows);
+  const int gather_tile = 256 * forward_vecs(p) * (p.gather_threads / 64 / p.gather_rows);
   switch (st.kind) {
     case Step::PadIn:
     case Step::Init:
@@ -1078,7 +1086,7 @@ int step_tile(const Plan &p, bool adjoint, int i) {
     case Step::InitAdj: return kTile;
     case Step::AdjGather:
       return adjoint_wave_span(p.gather_vecs, p.adj.passes[st.index].lagged) *
-             (kGatherThreads / 64 / adjoint_rows(p, st.index));
+             (adjoint_threads(p, st.index) / 64 / adjoint_rows(p, st.index));
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;

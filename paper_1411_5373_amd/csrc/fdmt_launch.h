@@ -20,6 +20,7 @@ struct GatherLaunch {
   int depth, vecs, rows_per_wg;
   bool lagged = false;  // adjoint: lagged leaf list (subtrees listed once)
   int tiles_fastest = 0;  // adjoint: run each row group's time tiles back to back (uniform launches)
+  int threads = kGatherThreads;  // workgroup size: 64 .. 1024, a multiple of 64 * rows_per_wg
 };
 
 // Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,

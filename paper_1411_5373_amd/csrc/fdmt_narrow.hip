@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   constexpr int N = 1 << K;
   constexpr int S = NarrowShape<FROM_INPUT, CV>::S;
   constexpr int W = NarrowShape<FROM_INPUT, CV>::W;
-  const int waves = kGatherThreads / 64;
+  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int col_waves = waves / rows_per_wg;
   const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
@@ -228,7 +228,7 @@ hipError_t launch_narrow(const GatherLaunch &g, const void *src, Tdst *dst, cons
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
 #define FDMT_NARROW(KK, CC, RR)                                                                                 \
-  hipLaunchKernelGGL((narrow_gather_kernel<FROM_INPUT, Tdst, KK, CC, RR>), g.grid, dim3(kGatherThreads), 0,     \
+  hipLaunchKernelGGL((narrow_gather_kernel<FROM_INPUT, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0,     \
                      g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows,   \
                      g.rows_per_wg, g.rg)
 #define FDMT_NARROW_K(CC, RR)              \

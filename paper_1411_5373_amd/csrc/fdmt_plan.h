@@ -65,6 +65,9 @@ struct Plan {
   int rec_tiles = 8;           // time tiles one level-by-level (LDS) workgroup runs
   int gather_rows = 8;         // output rows per register-gather workgroup
   int gather_vecs = 1;         // runs of 4 samples per lane in register gathers (1, 2 or 4)
+  int gather_threads = 1024;   // workgroup size of the forward register gathers (64 .. 1024)
+  int adjoint_threads = 1024;  // workgroup size of the adjoint register gathers (64 .. 1024)
+  int adjoint_last_threads = 0;  // ... of the last adjoint pass (0: adjoint_threads)
   int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: gather_rows)
   uint32_t adjoint_tile_major = 0;  // bit i: adjoint pass i runs each row group's tiles back to back
   const int2 *dev_sterms = nullptr;
@@ -108,6 +111,8 @@ hipError_t launch_adjoint(const Plan &p, const void *grad_out, void *grad_in, in
 int step_tile(const Plan &p, bool adjoint, int step);
 // Output rows per workgroup of adjoint register-gather pass `pass`.
 int adjoint_rows(const Plan &p, int pass);
+// Workgroup size of adjoint register-gather pass `pass`.
+int adjoint_threads(const Plan &p, int pass);
 size_t workspace_bytes(const Plan &p, int batch);
 size_t ragged_workspace_bytes(const Plan &p, const RaggedBatch &rb);
 // Option-1 rows of every channel position of one beam into FP32 rows of

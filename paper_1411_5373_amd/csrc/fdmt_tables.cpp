@@ -20,6 +20,16 @@
 // other merge splits a band of unequal halves at their border, f2 being the
 // upper edge of its last channel. Bands without a channel have one row.
 //
+// The two-C rule (Sec. 4.2, rounding and binning; `rule` 1) treats a
+// channel as the point of its label (lower edge) e_k, a sub-band's delay
+// running from its first channel's label to its last's. A merge of channels
+// k0..km-1 and km..k1 then computes C twice over the label span [e_k0, e_k1]:
+// with the lower sub-band's end frequency e_{km-1} for the lower half's delay
+// d_lo, and with the upper sub-band's start frequency e_km for the upper
+// half's shift s (its delay being dt - s), so the curve's travel between the
+// two labels is the gap s - d_lo. A single channel spans no delay: every
+// channel needs only row 0.
+//
 // A known smallest delay d_min (Sec. 4.2, different range of dispersions) is
 // a frequency-dependent shift of the input: channel k is delayed by
 // pre_k = round(d_min * phi(c_k)) samples, phi(f) = (f_min^g - f^g) /
@@ -28,6 +38,7 @@
 // row adds in channel k is then centred on the curve's passage through it).
 #include "fdmt_tables.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace fdmt {
@@ -49,13 +60,15 @@ int32_t round_half_up(double x) { return static_cast<int32_t>(std::floor(x + 0.5
 
 } // namespace
 
-std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma, int d_min) {
+std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma, int d_min,
+                         int rule) {
   if (nf < 1) return "Nf must be >= 1";
   if (nd < 1) return "Nd must be >= 1";
   if (!(f_min > 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
     return "need 0 < f_min < f_max (finite)";
   if (!std::isfinite(gamma) || gamma == 0.0) return "the delay law's power must be finite and nonzero";
   if (d_min < 0) return "d_min must be >= 0";
+  if (rule != 0 && rule != 1) return "rule must be 0 (one C) or 1 (two C's)";
   int levels = 0;
   while ((1 << levels) < nf) ++levels;
   const int slots = 1 << levels;
@@ -69,6 +82,7 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
   t.f_max = f_max;
   t.gamma = gamma;
   t.d_min = d_min;
+  t.rule = rule;
 
   const double df = (f_max - f_min) / nf;
   std::vector<double> edge(slots + 1);
@@ -82,28 +96,41 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
 
   // Top-down: split every sub-band of iteration l, which fixes the row counts
   // of iteration l - 1.
-  std::vector<std::vector<std::vector<int32_t>>> lo_of(levels + 1), hi_of(levels + 1);
+  std::vector<std::vector<std::vector<int32_t>>> lo_of(levels + 1), hi_of(levels + 1), s_of(levels + 1);
   for (int l = levels; l >= 1; --l) {
     const int nsub = slots >> l;
     t.rows[l - 1].assign(2 * nsub, 0);
     lo_of[l].resize(nsub);
     hi_of[l].resize(nsub);
+    s_of[l].resize(nsub);
     for (int j = 0; j < nsub; ++j) {
-      const double f0 = edge[static_cast<size_t>(j) << l];
-      const double f1 = edge[static_cast<size_t>(2 * j + 1) << (l - 1)];
-      const double f2 = edge[static_cast<size_t>(j + 1) << l];
-      // a band with no channel (f0 = f2) has only row 0, which any C maps to 0
-      const double c = f2 == f0 ? 0.0 : merge_coefficient(f0, f1, f2, gamma);
+      const int64_t first = static_cast<int64_t>(j) << l, mid = static_cast<int64_t>(2 * j + 1) << (l - 1);
+      const int64_t end = std::min<int64_t>(static_cast<int64_t>(j + 1) << l, nf);  // past its last channel
+      double c_lo, c_hi;
+      if (first >= nf) {
+        c_lo = c_hi = 0.0;  // a band with no channel has only row 0, which any C maps to 0
+      } else if (mid >= nf) {
+        c_lo = c_hi = 1.0;  // no channel in the upper half: the band is its lower half
+      } else if (rule == 0) {
+        c_lo = c_hi = merge_coefficient(edge[first], edge[mid], edge[end], gamma);
+      } else {
+        c_lo = merge_coefficient(edge[first], edge[mid - 1], edge[end - 1], gamma);
+        c_hi = merge_coefficient(edge[first], edge[mid], edge[end - 1], gamma);
+      }
       const int32_t n = t.rows[l][j];
       auto &lo = lo_of[l][j];
       auto &hi = hi_of[l][j];
+      auto &sh = s_of[l][j];
       lo.resize(n);
       hi.resize(n);
+      sh.resize(n);
       for (int32_t dt = 0; dt < n; ++dt) {
-        const int32_t d = round_half_up(static_cast<double>(dt) * c);
-        if (d < 0 || d > dt) return "merge coefficient outside [0, 1]";
+        const int32_t d = round_half_up(static_cast<double>(dt) * c_lo);
+        const int32_t sv = round_half_up(static_cast<double>(dt) * c_hi);
+        if (d < 0 || d > dt || sv < 0 || sv > dt) return "merge coefficient outside [0, 1]";
         lo[dt] = d;
-        hi[dt] = dt - d;
+        sh[dt] = sv;
+        hi[dt] = dt - sv;
       }
       t.rows[l - 1][2 * j] = lo[n - 1] + 1;
       t.rows[l - 1][2 * j + 1] = hi[n - 1] + 1;
@@ -141,12 +168,12 @@ std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, 
       const int64_t lo_base = t.row_off[l - 1][2 * j];
       const int64_t hi_base = t.row_off[l - 1][2 * j + 1];
       for (int32_t dt = 0; dt < t.rows[l][j]; ++dt) {
-        const int32_t dl = lo_of[l][j][dt], dh = hi_of[l][j][dt];
+        const int32_t dl = lo_of[l][j][dt], dh = hi_of[l][j][dt], sv = s_of[l][j][dt];
         const int64_t r = base + dt;
-        m[r] = MergeRow{static_cast<int32_t>(lo_base + dl), static_cast<int32_t>(hi_base + dh), dl, j};
+        m[r] = MergeRow{static_cast<int32_t>(lo_base + dl), static_cast<int32_t>(hi_base + dh), sv, j};
         t.d_lo[l][r] = dl;
         t.d_hi[l][r] = dh;
-        t.shift[l][r] = dl;
+        t.shift[l][r] = sv;
         // Inverse maps: the parents of a child row are consecutive because
         // both d_lo and d_hi are non-decreasing in dt.
         AdjRow &al = a[lo_base + dl];

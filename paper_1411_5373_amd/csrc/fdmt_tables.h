@@ -32,6 +32,7 @@ struct Tables {
   double f_min = 0, f_max = 0;
   double gamma = -2.0;  // delay law dt ~ f^gamma
   int32_t d_min = 0;    // smallest total delay searched; row dt is delay d_min + dt
+  int rule = 0;         // 0: one C at the border frequency; 1: two C's (channel labels)
   // rows[l][j]: dt rows of sub-band j after iteration l (l = 0: channel j's
   // Option-1 partial sums; l = levels: the single output sub-band, nd rows).
   std::vector<std::vector<int32_t>> rows;
@@ -53,10 +54,11 @@ struct Tables {
   std::vector<int32_t> pre;
 };
 
-// Builds every table for the delay law dt ~ f^gamma (-2: cold plasma) and the
-// pre-shift for delays from d_min on. Returns "" on success or a description
-// of the problem.
+// Builds every table for the delay law dt ~ f^gamma (-2: cold plasma), the
+// pre-shift for delays from d_min on and the table rule (0: one C per merge
+// at the border frequency; 1: two C's from the channel labels either side).
+// Returns "" on success or a description of the problem.
 std::string build_tables(Tables &t, int nf, int nd, double f_min, double f_max, double gamma = -2.0,
-                         int d_min = 0);
+                         int d_min = 0, int rule = 0);
 
 } // namespace fdmt

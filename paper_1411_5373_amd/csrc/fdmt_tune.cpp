@@ -174,12 +174,13 @@ const char *dtype_name(int d) {
 }  // namespace
 
 std::string tune_key(const std::string &arch, int nf, int64_t nt, int nd, double f_min, double f_max,
-                     int in_dtype, int acc_dtype, double gamma) {
+                     int in_dtype, int acc_dtype, double gamma, int rule) {
   int64_t bucket = 1;
   while (bucket < nt) bucket *= 2;
   std::string k = arch + "/nf" + std::to_string(nf) + "/nd" + std::to_string(nd) + "/band" + fmt_g6(f_min) + "-" +
                   fmt_g6(f_max);
   if (gamma != -2.0) k += "/gamma" + fmt_g6(gamma);
+  if (rule == 1) k += "/twoC";
   k += std::string("/") + dtype_name(in_dtype) + "->" + dtype_name(acc_dtype) + "/nt" + std::to_string(bucket);
   return k;
 }

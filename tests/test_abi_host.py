@@ -92,6 +92,34 @@ def test_power_law_tables_match_oracle(gamma, nf, nd, band):
         assert e.value.status == B.FDMT_E_INVALID
 
 
+@pytest.mark.parametrize("nf,nd,band,gamma", [(2, 9, (1.0, 2.0), -2.0), (64, 64, (1.2, 1.6), -2.0),
+                                              (4096, 2048, (1.2, 1.6), -2.0), (1024, 1024, (0.4, 0.8), -2.0),
+                                              (3, 40, (1.0, 2.0), -2.0), (100, 90, (1.2, 1.6), -2.0),
+                                              (1000, 1024, (1.2, 1.6), -2.0), (600, 700, (0.4, 0.8), 2.0),
+                                              (5, 300, (1.2, 1.6), -3.0)])
+def test_two_c_tables_match_oracle(nf, nd, band, gamma):
+    """The two-C rule (rule=1, Sec. 4.2 rounding and binning): the library's
+    tables equal the oracle's element by element, with the upper half's
+    shift differing from the lower half's delay; channels keep row 0 only."""
+    ref = build_tables(nf, nd, *band, gamma=gamma, rule=1)
+    p = F.Plan(nf, 1000, nd, *band, host_only=True, gamma=gamma, rule=1)
+    levels, rows = p.info()
+    assert levels == ref.levels and rows == _plane_rows(ref)
+    for k in range(nf):
+        assert p.tables(0, k)[3] == 1
+    gaps = 0
+    for l in range(1, levels + 1):
+        for j in range(len(ref.rows[l])):
+            d_lo, s, d_hi, n = p.tables(l, j)
+            assert n == ref.rows[l][j]
+            assert list(zip(d_lo, s, d_hi)) == _triples(ref.split[l][j]), (l, j)
+            gaps += sum(1 for a, b, c in zip(d_lo, s, d_hi) if c >= 0 and b != a)
+    assert gaps > 0 or nd < 3
+    with pytest.raises(F.FDMTError) as e:
+        F.Plan(nf, 1000, nd, *band, host_only=True, rule=2)
+    assert e.value.status == B.FDMT_E_INVALID
+
+
 def test_dmin_plan_rules():
     """d_min >= 0; the pre-shift needs the first pass to gather from the
     input, which a d_min plan picks by default; LDS first passes are refused."""

@@ -51,15 +51,15 @@ def test_fft_forward_matches_oracle(nf, nt, nd, band, in_dtype):
 
 
 def test_fft_batch_and_variants():
-    """A batch equals single calls bit for bit; d_min and another law follow
-    the oracle built with them."""
+    """A batch equals single calls bit for bit; d_min, another law and the
+    two-C table rule follow the oracle built with them."""
     nf, nt, nd, band = 128, 2000, 200, (1.2, 1.6)
     x = W.random_input((3, nf, nt), np.float32, seed=5)
     p = F.Plan(nf, nt, nd, *band, fft=True)
     y = p.forward_fft(_dev(x))
     for b in range(3):
         assert torch.equal(y[b], p.forward_fft(_dev(x[b])))
-    for kw in (dict(d_min=500), dict(gamma=1.0)):
+    for kw in (dict(d_min=500), dict(gamma=1.0), dict(rule=1)):
         t = build_tables(nf, nd, *band, **kw)
         q = F.Plan(nf, nt, nd, *band, fft=True, **kw)
         _check(q.forward_fft(_dev(x[0])).cpu().numpy(), offt(x[0].astype(np.float64), *band, nd, t), str(kw))

@@ -367,6 +367,10 @@ SCHEDULES = [
     dict(first_levels=4, later_levels=2, gather_rows=16, gather_vecs=2, adjoint_levels=3,
          adjoint_last_levels=1),
     dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=4),
+    # smaller workgroups for the cache gathers
+    dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4, gather_threads=256),
+    dict(first_levels=2, later_levels=3, first_kernel=3, gather_rows=1, gather_threads=64),
+    dict(first_levels=4, later_levels=2, first_kernel=2, gather_rows=2, gather_threads=512),
 ]
 
 
@@ -474,6 +478,16 @@ ADJOINT_SCHEDULES = [
     dict(adjoint_levels=3, adjoint_last_levels=3, gather_vecs=2, adjoint_last_rows=16, adjoint_tile_major=0b1001),
     dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=4, gather_vecs=4, adjoint_tile_major=0xFFFFFFFF),
     dict(adjoint_levels=1, adjoint_last_levels=2, gather_vecs=1, adjoint_tile_major=0b10),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=4, gather_vecs=4, adjoint_last_rows=4,
+         adjoint_threads=256, adjoint_tile_major=0b1001),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=2, gather_vecs=4, adjoint_last_rows=8,
+         adjoint_threads=512),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=1, gather_vecs=2, adjoint_last_rows=1,
+         adjoint_threads=64),
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=4, gather_vecs=4, adjoint_last_rows=4,
+         adjoint_last_threads=256, adjoint_tile_major=0b1001),
+    dict(adjoint_levels=2, adjoint_last_levels=3, gather_rows=8, gather_vecs=1, adjoint_last_rows=2,
+         adjoint_last_threads=128),
 ]
 
 
@@ -537,3 +551,43 @@ def test_copy_bytes(nbytes):
     dst = torch.zeros_like(src)
     F.copy_bytes(dst, src)
     assert torch.equal(dst, src)
+
+
+TWO_C_SCHEDULES = [dict(), dict(unfused=True),
+                   dict(first_kernel=3, first_levels=3, later_levels=3, gather_rows=4, gather_vecs=4,
+                        adjoint_levels=3, adjoint_last_levels=3, adjoint_last_threads=256, adjoint_tile_major=9),
+                   dict(first_kernel=2, first_levels=4, later_levels=2, adjoint_levels=2, adjoint_last_levels=1),
+                   dict(first_levels=3, later_levels=3, tile=256, lds_kib=64)]
+
+
+@pytest.mark.parametrize("sched", TWO_C_SCHEDULES)
+@pytest.mark.parametrize("nf,nt,nd,band,gamma,d_min", [(256, 3001, 300, (1.2, 1.6), -2.0, 0),
+                                                       (4096, 3000, 2048, (1.2, 1.6), -2.0, 0),
+                                                       (100, 2000, 150, (0.4, 0.8), -2.0, 0),
+                                                       (64, 1030, 100, (1.2, 1.6), 2.0, 0),
+                                                       (1024, 4000, 256, (1.2, 1.6), -2.0, 900),
+                                                       (2, 500, 300, (1.0, 2.0), -2.0, 0)])
+def test_two_c_forward_and_adjoint(sched, nf, nt, nd, band, gamma, d_min):
+    """The two-C table rule (Sec. 4.2, rounding and binning) runs through every
+    kernel form unchanged (the upper half's shift is a table column): uint8
+    forward exact against the int64 oracle built with rule=1 (int32 and FP32
+    sums), FP32 forward and adjoint bit-exact against its binary32
+    evaluation."""
+    print(f"two-C {sched} nf={nf} nt={nt} nd={nd} gamma={gamma} d_min={d_min}", flush=True)
+    tab = build_tables(nf, nd, *band, gamma=gamma, d_min=d_min, rule=1)
+    kw = dict(sched, rule=1, gamma=gamma, d_min=d_min)
+    try:
+        F.Plan(nf, nt, nd, *band, host_only=True, **kw)
+    except F.FDMTError as e:
+        assert e.status == 2
+        pytest.skip(str(e))
+    x = W.random_input((nf, nt), np.uint8, seed=nf + nd + 11)
+    ref = ofdmt(x.astype(np.int64), *band, nd, tab)
+    for acc in (torch.int32, torch.float32):
+        y = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=acc, **kw).forward(_dev(x)).cpu().numpy()
+        np.testing.assert_array_equal(y.astype(np.int64), ref)
+    xf = W.random_input((nf, nt), np.float32, seed=nf + 3)
+    pf = F.Plan(nf, nt, nd, *band, **kw)
+    np.testing.assert_array_equal(pf.forward(_dev(xf)).cpu().numpy(), ofdmt(xf, *band, nd, tab, acc=np.float32))
+    g = W.random_input((nd, nt), np.float32, seed=nd + 5)
+    np.testing.assert_array_equal(pf.adjoint(_dev(g)).cpu().numpy(), oadj(g, *band, nf, tab, acc=np.float32))

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import read_golden
-from oracle import (boxcar_search, brute_ideal, brute_point, brute_row, build_tables, fdmt,
+from oracle import (boxcar_search, brute_ideal, brute_point, brute_row, build_tables, channel_edges, fdmt,
                     fdmt_adjoint, fdmt_fft, fft_length, path)
 import workloads as W
 
@@ -609,3 +609,97 @@ def test_boxcar_float64_checker_accepts_tree_and_rejects_planted_errors():
     for b in planted:
         with pytest.raises(AssertionError):
             check_boxcar_float64(b, y, m)
+
+
+# ---------------------------------------------------------------- two-C rule (reading R-twoC)
+
+def test_two_c_hand_derived_example():
+    """The two-C rule on the hand-derived Nf=4 example: lower half's delay from
+    C at the lower sub-band's end label, upper half's shift from C at the upper
+    sub-band's start label (tests/golden/tiny_twoc_nf4_nd4.txt)."""
+    f_min, f_max, nd, img, expect = read_golden("tiny_twoc_nf4_nd4.txt")
+    np.testing.assert_array_equal(fdmt(img, f_min, f_max, nd, build_tables(4, nd, f_min, f_max, rule=1)), expect)
+
+
+def test_two_c_two_channels_closed_form():
+    """Nf = 2: C_lo = 0 and C_hi = 1 exactly, so row dt is I[0][t] + I[1][t - dt]
+    (one sample per channel, the upper channel dt samples earlier)."""
+    x = _rng(21).integers(0, 100, size=(2, 40)).astype(np.int64)
+    y = fdmt(x, 0.4, 0.8, 25, build_tables(2, 25, 0.4, 0.8, rule=1))
+    for dt in range(25):
+        ref = x[0].copy()
+        ref[dt:] += x[1, : 40 - dt]
+        np.testing.assert_array_equal(y[dt], ref)
+
+
+def _label_law(t):
+    """Per channel, the fraction of the label-to-label delay reached at its label."""
+    e = channel_edges(t.nf, t.f_min, t.f_max)
+    g = t.gamma
+    law = (lambda f: 1.0 / (f * f)) if g == -2.0 else (lambda f: f ** g)
+    if t.nf == 1:
+        return [0.0]
+    return [(law(e[k]) - law(e[0])) / (law(e[t.nf - 1]) - law(e[0])) for k in range(t.nf)]
+
+
+@pytest.mark.parametrize("nf,nd,band,gamma", [(8, 30, (1.2, 1.6), -2.0), (64, 64, (1.2, 1.6), -2.0),
+                                              (1024, 1024, (0.4, 0.8), -2.0), (100, 90, (1.2, 1.6), -2.0),
+                                              (256, 300, (1.0, 3.0), 2.0), (7, 50, (1.0, 2.0), -2.0)])
+def test_two_c_paths(nf, nd, band, gamma):
+    """Under the two-C rule every channel adds exactly one sample (row 0), the
+    first channel at t0 and the last at t0 - dt exactly, and every channel's
+    shift is within log2(Nf)/2 samples of dt times the label law (each
+    iteration rounds once, by at most 1/2, a convex combination of its
+    parent's errors). Channel rows are all 1; every inverse table entry is
+    used."""
+    t = build_tables(nf, nd, *band, gamma=gamma, rule=1)
+    assert all(r == 1 for r in t.rows[0][:nf])
+    bound = t.levels / 2 + 1e-9
+    phi = _label_law(t)
+    for dt in range(nd):
+        p = path(t, dt)
+        assert all(delta == 0 for _, delta in p)
+        assert p[0][0] == 0 and p[-1][0] == (dt if nf > 1 else 0)
+        for k, (sigma, _) in enumerate(p):
+            assert abs(sigma - dt * phi[k]) <= bound, (dt, k, sigma)
+        assert all(p[k][0] <= p[k + 1][0] for k in range(nf - 1))
+
+
+@pytest.mark.parametrize("nf,nt,nd,band", [(16, 200, 40, (1.2, 1.6)), (5, 100, 30, (1.0, 2.0)),
+                                           (64, 300, 64, (0.4, 0.8))])
+def test_two_c_recursion_equals_path_sums(nf, nt, nd, band):
+    """The recursion under the two-C tables equals explicit summation of one
+    sample per channel along each row's path (integers, exact); row 0 is the
+    channel sum; all-ones data give Nf wherever t0 >= dt; the adjoint is the
+    exact transpose."""
+    t = build_tables(nf, nd, *band, rule=1)
+    x = _rng(nf + nd).integers(0, 50, size=(nf, nt)).astype(np.int64)
+    y = fdmt(x, *band, nd, t)
+    for dt in range(0, nd, 3):
+        np.testing.assert_array_equal(y[dt], brute_row(x, t, dt))
+    np.testing.assert_array_equal(y[0], x.sum(axis=0))
+    ones = fdmt(np.ones((nf, nt), dtype=np.int64), *band, nd, t)
+    for dt in range(nd):
+        assert np.all(ones[dt, dt:] == nf)
+    g = _rng(nt).integers(-20, 20, size=(nd, nt)).astype(np.int64)
+    assert int((y * g).sum()) == int((x * fdmt_adjoint(g, *band, nf, t)).sum())
+
+
+def test_two_c_recovers_pulse_at_labels():
+    """A width-1 pulse that crosses each channel at its label time (the point
+    the rule samples) is found within 2 samples of its (dt, T), with at least
+    0.6 Nf of its amplitude, the criterion of the one-C pulse pin (the path
+    sits up to log2(Nf)/2 samples off the exact curve, so a width-1 pulse
+    loses some channels)."""
+    nf, nt, nd, band = 256, 2000, 400, (1.2, 1.6)
+    t = build_tables(nf, nd, *band, rule=1)
+    phi = _label_law(t)
+    x = np.zeros((nf, nt))
+    for dt, T, amp in ((333, 1500, 5.0), (57, 900, 3.0)):
+        for k in range(nf):
+            x[k, int(round(T - dt * phi[k]))] += amp
+        y = fdmt(x, *band, nd, t)
+        i, j = np.unravel_index(np.argmax(y), y.shape)
+        assert abs(i - dt) <= 2 and abs(j - T) <= 2, (i, j)
+        assert y[i, j] >= 0.6 * amp * nf, y[i, j] / (amp * nf)
+        x[:] = 0
