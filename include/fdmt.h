@@ -377,6 +377,21 @@ fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hi
 fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32_t nf, int64_t nt, int32_t nd,
                                  double f_min, double f_max, fdmt_options_t *opt, int32_t *found);
 
+/* The boxcar search above without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the partials live in a static
+ * 32 MiB device buffer of the library, one per GPU, held until the process
+ * ends. Same arguments, results and stream order as fdmt_boxcar_search();
+ * allocates nothing and calls no allocating routine. The buffer keeps the
+ * last call's contents (every partial is written before it is read), and
+ * calls that overlap on one GPU (other streams, other threads) race on it:
+ * serialise them. FDMT_E_WORKSPACE when the search needs more than 32 MiB
+ * (fdmt_boxcar_workspace_bytes() > 33554432, e.g. more than 2048 rows x
+ * 65536 samples x 11 widths); FDMT_E_INVALID as fdmt_boxcar_search();
+ * FDMT_E_DEVICE when the buffer's device address cannot be found. */
+fdmt_status_t fdmt_boxcar_search_noalloc(const float *plane, int32_t batch, int32_t nd, int64_t nt,
+                                         int32_t max_log2, fdmt_boxcar_t *out, void *hip_stream);
+
 /* Static description of a status code. */
 const char *fdmt_status_string(fdmt_status_t s);
 

@@ -29,7 +29,7 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
-            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
+            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_boxcar_search_noalloc", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
             "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
@@ -128,6 +128,8 @@ def load():
     lib.fdmt_boxcar_workspace_bytes.restype = sz
     lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.fdmt_boxcar_search.restype = ctypes.c_int
+    lib.fdmt_boxcar_search_noalloc.argtypes = [vp, i32, i32, i64, i32, vp, vp]
+    lib.fdmt_boxcar_search_noalloc.restype = ctypes.c_int
     lib.fdmt_copy_bytes.argtypes = [vp, vp, sz, vp]
     lib.fdmt_copy_bytes.restype = ctypes.c_int
     lib.fdmt_tuned_options.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, i64, i32, ctypes.c_double,
@@ -244,6 +246,11 @@ def fdmt_boxcar_workspace_bytes(batch, nd, nt, max_log2):
 def fdmt_boxcar_search(plane_ptr, batch, nd, nt, max_log2, out_ptr, ws_ptr, ws_bytes, stream):
     _check(load().fdmt_boxcar_search(plane_ptr, int(batch), int(nd), int(nt), int(max_log2), out_ptr, ws_ptr,
                                      int(ws_bytes), stream), "fdmt_boxcar_search")
+
+
+def fdmt_boxcar_search_noalloc(plane_ptr, batch, nd, nt, max_log2, out_ptr, stream):
+    _check(load().fdmt_boxcar_search_noalloc(plane_ptr, int(batch), int(nd), int(nt), int(max_log2), out_ptr,
+                                             stream), "fdmt_boxcar_search_noalloc")
 
 
 def fdmt_step_count(plan, adjoint=False):

@@ -785,6 +785,27 @@ fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, 
   return FDMT_OK;
 }
 
+fdmt_status_t fdmt_boxcar_search_noalloc(const float *plane, int32_t batch, int32_t nd, int64_t nt,
+                                         int32_t max_log2, fdmt_boxcar_t *out, void *hip_stream) {
+  if (!plane || !out) return fail(FDMT_E_INVALID, "plane or out is NULL");
+  if (!boxcar_sizes_ok(batch, nd, nt, max_log2))
+    return fail(FDMT_E_INVALID, "need batch, nd in [1, 65535], nt in [1, 2^31 - 1], max_log2 in [0, 10]");
+  const size_t need = fdmt::boxcar_workspace_bytes(batch, nd, nt, max_log2);
+  if (need > fdmt::kBoxScratchBytes)
+    return fail(FDMT_E_WORKSPACE, "the search needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                      std::to_string(fdmt::kBoxScratchBytes) +
+                                      " of the static buffer: use fdmt_boxcar_search with a workspace");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  void *ws = nullptr;
+  e = fdmt::boxcar_static_scratch(dev, &ws);
+  if (e != hipSuccess) return device_fail(e, "static boxcar scratch");
+  e = fdmt::launch_boxcar(plane, batch, nd, nt, max_log2, out, ws, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "boxcar search launch");
+  return FDMT_OK;
+}
+
 fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hip_stream) {
   if (bytes == 0) return FDMT_OK;
   if (!dst || !src) return fail(FDMT_E_INVALID, "src or dst is NULL");

@@ -22,6 +22,15 @@ struct BoxPartial {
 
 size_t boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2);
 
+// Size of the library's static boxcar scratch (fdmt_boxcar_search_noalloc):
+// 32 MiB, the partials of e.g. 2048 rows x 65536 samples x 11 widths.
+constexpr size_t kBoxScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+
+// Device address of the static boxcar scratch on `device`, which must be the
+// calling thread's current device (looked up on the first call per device).
+hipError_t boxcar_static_scratch(int device, void **ptr);
+
 // plane: device [batch][nd][nt] FP32; out: device [batch][max_log2 + 1][nd];
 // ws: boxcar_workspace_bytes() of device memory.
 hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,

@@ -7,8 +7,17 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "fdmt_boxcar.h"
+
+// Device scratch of the allocation-free boxcar search: the per-(row, tile,
+// width) partials, for callers that cannot allocate (see
+// boxcar_static_scratch). Each GPU the library runs on holds its own copy
+// until the process ends. Host code must not pass this name to a kernel: on
+// the host it stands for a host-side shadow, not the device address, which
+// boxcar_static_scratch looks up per device.
+static __device__ __align__(256) unsigned char scratch[fdmt::kBoxScratchBytes];
 
 namespace fdmt {
 
@@ -201,6 +210,26 @@ __global__ __launch_bounds__(256) void boxcar_combine_kernel(const BoxPartial *_
 size_t boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2) {
   const int64_t ntiles = (nt + kBoxTile - 1) / kBoxTile;
   return static_cast<size_t>(batch) * (max_log2 + 1) * nd * ntiles * sizeof(BoxPartial);
+}
+
+hipError_t boxcar_static_scratch(int device, void **ptr) {
+  // device addresses of `scratch`, looked up once per device with that device current
+  static std::mutex lock;
+  static void *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(lock);
+  if (!addr[device]) {
+    int current = -1;
+    hipError_t e = hipGetDevice(&current);
+    if (e != hipSuccess) return e;
+    if (current != device) return hipErrorInvalidDevice;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
