@@ -11,8 +11,9 @@ Prints one JSON line. `value` is DM-trial x samples per second of the whole
 step (Nd * Nt / step time); forward-only and adjoint-only rates, achieved HBM
 bandwidth, the adjoint/forward time ratio and the other precision forms (with
 their speedup over the FP32 form) are reported beside it, and so are the
-ragged 256-beam workload and the batch-16 differentiable workload.
-`roofline` describes the step's longest kernel: its algorithmic bytes (every
+ragged 256-beam workload and the batch-16 differentiable workload, and the
+forward transform with the boxcar search and candidate list fused into its
+last pass. `roofline` describes the step's longest kernel: its algorithmic bytes (every
 element it must read and write, once) over its average duration measured
 with HIP events on the launch stream, against the HBM peak and against the
 library's own streaming copy measured in the same run.
@@ -321,6 +322,56 @@ def boxcar_on_output(F, torch, y, max_log2=8, reps=10):
             "alg_gb_s": round(nd * nt * 4 / ms / 1e6, 1)}
 
 
+def forward_search_leg(F, torch, plan, x, y, max_log2=8, threshold=7.0, reps=10):
+    """The forward transform with the boxcar search (widths 1..2^max_log2) and
+    its candidate list (fdmt_forward_search), against the forward followed
+    by the standalone search over its output, and with the search run inside
+    the last forward pass (search_rows = 1)."""
+    import ctypes
+    nd, nt = y.shape
+    stats = torch.empty((1, max_log2 + 1, nd, 5), dtype=torch.int32, device=y.device)
+    cap = 1 << 16
+    cands = torch.empty((cap, 6), dtype=torch.int32, device=y.device)
+    count = torch.zeros(1, dtype=torch.int32, device=y.device)
+    vp = ctypes.c_void_p
+    stream = F.binding._stream_handle(y.device)
+
+    def search_call(p):
+        ws = p.search_workspace(1, max_log2)
+        return lambda: F.fdmt_forward_search(p.handle, vp(x.data_ptr()), vp(y.data_ptr()), 1, max_log2, threshold,
+                                             vp(stats.data_ptr()), vp(cands.data_ptr()), cap, vp(count.data_ptr()),
+                                             vp(ws.data_ptr()), ws.numel(), stream)
+
+    fws = plan.workspace(1)
+    bws = torch.empty(F.fdmt_boxcar_workspace_bytes(1, nd, nt, max_log2), dtype=torch.uint8, device=y.device)
+
+    def separate():
+        plan.forward(x, out=y, ws=fws)
+        F.boxcar_search(y, max_log2, ws=bws)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = timed(search_call(plan))
+    n = int(count.item())
+    sep = timed(separate)
+    in_pass = F.Plan(plan.nf, plan.nt, plan.nd, plan.f_min, plan.f_max, in_dtype=plan.in_dtype,
+                     acc_dtype=plan.acc_dtype, search_rows=1, **plan.options)
+    in_pass_ms = timed(search_call(in_pass)) if in_pass.search_fused(max_log2) else None
+    return {"widths": f"1..{1 << max_log2}", "threshold_snr": threshold, "candidates": n,
+            "ms": round(ms, 4), "forward_then_search_ms": round(sep, 4),
+            "search_in_last_pass_ms": None if in_pass_ms is None else round(in_pass_ms, 4),
+            "dm_trial_samples_per_s": nd * nt / (ms / 1000.0)}
+
+
 def forward_only(F, torch, w, in_dtype, acc_dtype, reps=10):
     """Tuned forward of one precision form on a fresh input; returns its timing
     and the (input, output) slices the accuracy check compares."""
@@ -542,6 +593,7 @@ def main():
         out["fft_fdmt"] = fft_fdmt(F, torch, w, forms["f32_in_f32_acc"]["ms"])
         torch.cuda.empty_cache()
     out["boxcar"] = boxcar_on_output(F, torch, y)
+    out["search"] = forward_search_leg(F, torch, plan, x, y)
     del x, g, y, xb, ws, plan
     if not args.no_ragged:
         torch.cuda.empty_cache()

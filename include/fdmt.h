@@ -158,6 +158,12 @@ typedef struct {
                              delay uses C at the lower sub-band's end label and the upper
                              half's shift C at the upper sub-band's start label, so each
                              output adds one sample per channel. Changes the results */
+  int32_t search_rows;    /* fdmt_forward_search(): 0 (default) runs the boxcar search after
+                             the transform, over its output; 1, 2 or 4 runs it inside the
+                             last forward pass (a register gather into FP32) on each
+                             workgroup's output tile in LDS, with that many rows per
+                             workgroup and tiles of 2048 samples. Same results either way;
+                             after the transform is the faster on MI355X at Nf = 4096 */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each
@@ -334,6 +340,19 @@ typedef struct {
   float snr;
 } fdmt_boxcar_t;
 
+/* A candidate event of fdmt_forward_search(): in beam `beam`, row `dt`, the
+ * width-2^width_log2 running sum's largest value `peak` inside one block of
+ * 2048 samples (first at time t), with snr = (peak - mean) / stdev against
+ * the row's statistics of that width over the whole record. */
+typedef struct {
+  int32_t beam;
+  int32_t dt;
+  int32_t t;
+  int32_t width_log2;
+  float peak;
+  float snr;
+} fdmt_candidate_t;
+
 /* Workspace (bytes) of fdmt_boxcar_search; 0 for invalid sizes. */
 size_t fdmt_boxcar_workspace_bytes(int32_t batch, int32_t nd, int64_t nt, int32_t max_log2);
 
@@ -376,6 +395,34 @@ fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hi
  * current device. Touches no device memory; pass the result to fdmt_plan(). */
 fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32_t nf, int64_t nt, int32_t nd,
                                  double f_min, double f_max, fdmt_options_t *opt, int32_t *found);
+
+/* Forward transform followed by the boxcar search of its output and a list
+ * of candidate events (Sec. 1: a detection is a statistic above a
+ * threshold; Sec. 4.2, pulse profile: one transform serves every width).
+ * out receives the forward output as fdmt_forward() (FP32 plans only);
+ * stats (device, [batch][max_log2 + 1][Nd]) the per-row results of
+ * fdmt_boxcar_search() on it. Every block of 2048 samples of every beam, row
+ * and width whose largest running sum has snr = (peak - mean) / stdev >=
+ * threshold (row statistics of that width; 0 when stdev is 0) is one
+ * candidate (fdmt_candidate_t, its first time in the block): up to `cap` of
+ * them are written to cands (device) in no particular order, and *count
+ * (device int32) receives how many there were (it may exceed cap).
+ * When fdmt_search_fused() is 1 (options.search_rows > 0 and a last pass
+ * that is a register gather) the search runs inside the last forward pass on
+ * each workgroup's output tile while it is in LDS, plus one small kernel for
+ * the windows that cross tile starts; otherwise the standalone search
+ * kernels read the transform's output back. Either way the running
+ * sums are the same doubling tree as fdmt_boxcar_search(), so peaks and
+ * their times are identical. ws: fdmt_search_workspace_bytes() of device
+ * memory (256-byte aligned). Allocates nothing; graph-capturable (the count
+ * is cleared by a kernel). Errors: those of fdmt_forward(), FDMT_E_UNSUPPORTED
+ * for an int32 plan, FDMT_E_INVALID for max_log2 outside [0, 10], a NaN
+ * threshold, NULL stats or count, cap < 0 or NULL cands with cap > 0. */
+size_t fdmt_search_workspace_bytes(fdmt_plan_t p, int32_t batch, int32_t max_log2);
+int32_t fdmt_search_fused(fdmt_plan_t p, int32_t max_log2);
+fdmt_status_t fdmt_forward_search(fdmt_plan_t p, const void *in, void *out, int32_t batch, int32_t max_log2,
+                                  float threshold, fdmt_boxcar_t *stats, fdmt_candidate_t *cands, int32_t cap,
+                                  int32_t *count, void *ws, size_t ws_bytes, void *hip_stream);
 
 /* The boxcar search above without a workspace argument, for callers that
  * cannot allocate device memory (code under HIP graph capture, tight serving

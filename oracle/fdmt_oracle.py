@@ -517,3 +517,35 @@ def boxcar_search(plane, max_log2, acc=None):
         for k, v in zip(("peak", "t", "mean", "stdev", "snr"), (peak, t, mean, sd, snr)):
             out[k].append(v)
     return {k: np.stack(v, axis=-2) for k, v in out.items()}
+
+
+def boxcar_candidates(plane, max_log2, threshold, block=2048):
+    """Candidate events of the boxcar search (Sec. 1: a detection is a
+    statistic above a threshold; Sec. 4.2, pulse profile: one transform serves
+    every width). For every beam b, row dt, width w = 2^j and block of
+    `block` samples [k*block, (k+1)*block) of the record: the block's largest
+    b_w (its first time t), and its S/N = (peak - mean) / stdev with the row's
+    mean and stdev of b_w over the whole record (0 if stdev is 0); a block
+    whose S/N is at least `threshold` is one candidate. Float64, b_w by its
+    definition. Returns a list of (b, dt, j, t, peak, snr), in that order of
+    loops (b, j, dt, k)."""
+    y = np.asarray(plane, dtype=np.float64)
+    if y.ndim == 2:
+        y = y[None]
+    nb, nd, nt = y.shape
+    out = []
+    for b in range(nb):
+        for j in range(max_log2 + 1):
+            bw = boxcar(y[b], 1 << j)
+            mean = bw.mean(axis=1)
+            sd = bw.std(axis=1)
+            for dt in range(nd):
+                for k in range(0, nt, block):
+                    seg = bw[dt, k: k + block]
+                    i = int(np.argmax(seg))
+                    peak = float(seg[i])
+                    snr = (peak - mean[dt]) / sd[dt] if sd[dt] > 0 else 0.0
+                    if snr >= threshold:
+                        out.append((b, dt, j, k + i, peak, snr))
+    return out
+

@@ -29,7 +29,8 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_plan", "fdmt_ragged_workspace_bytes", "fdmt_ragged_forward",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
-            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_boxcar_search_noalloc", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
+            "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_search_workspace_bytes", "fdmt_search_fused", "fdmt_forward_search",
+            "fdmt_boxcar_search_noalloc", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
             "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
@@ -58,7 +59,7 @@ class _Options(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32),
                 ("adjoint_tile_major", ctypes.c_uint32), ("gather_threads", ctypes.c_int32),
                 ("adjoint_threads", ctypes.c_int32), ("adjoint_last_threads", ctypes.c_int32),
-                ("rule", ctypes.c_int32)]
+                ("rule", ctypes.c_int32), ("search_rows", ctypes.c_int32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -128,6 +129,12 @@ def load():
     lib.fdmt_boxcar_workspace_bytes.restype = sz
     lib.fdmt_boxcar_search.argtypes = [vp, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.fdmt_boxcar_search.restype = ctypes.c_int
+    lib.fdmt_search_workspace_bytes.argtypes = [vp, i32, i32]
+    lib.fdmt_search_workspace_bytes.restype = sz
+    lib.fdmt_search_fused.argtypes = [vp, i32]
+    lib.fdmt_search_fused.restype = ctypes.c_int32
+    lib.fdmt_forward_search.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, vp, vp, i32, vp, vp, sz, vp]
+    lib.fdmt_forward_search.restype = ctypes.c_int
     lib.fdmt_boxcar_search_noalloc.argtypes = [vp, i32, i32, i64, i32, vp, vp]
     lib.fdmt_boxcar_search_noalloc.restype = ctypes.c_int
     lib.fdmt_copy_bytes.argtypes = [vp, vp, sz, vp]
@@ -164,7 +171,8 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
               first_levels=0, later_levels=0, tile=0, lds_kib=0, max_block_rows=0,
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
               adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0,
-              adjoint_tile_major=0, gather_threads=0, adjoint_threads=0, adjoint_last_threads=0, rule=0):
+              adjoint_tile_major=0, gather_threads=0, adjoint_threads=0, adjoint_last_threads=0, rule=0,
+              search_rows=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
@@ -172,7 +180,8 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
                    int(first_kernel), int(later_kernel), int(stream_tiles), int(gather_rows),
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
                    int(adjoint_last_rows), float(gamma), int(d_min), int(adjoint_tile_major),
-                   int(gather_threads), int(adjoint_threads), int(adjoint_last_threads), int(rule))
+                   int(gather_threads), int(adjoint_threads), int(adjoint_last_threads), int(rule),
+                   int(search_rows))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -195,7 +204,7 @@ def copy_bytes(dst, src):
 SCHEDULE_FIELDS = ("first_levels", "later_levels", "tile", "lds_kib", "max_block_rows", "first_kernel",
                    "later_kernel", "stream_tiles", "gather_rows", "adjoint_levels", "adjoint_last_levels",
                    "gather_vecs", "adjoint_last_rows", "adjoint_tile_major", "gather_threads", "adjoint_threads",
-                   "adjoint_last_threads")
+                   "adjoint_last_threads", "search_rows")
 
 
 def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, gamma=0.0, d_min=0,
@@ -203,7 +212,7 @@ def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FD
     """The autotuner's schedule for this workload through the C ABI: a dict of
     the schedule fields the cache sets (explicit nonzero fields kept as given),
     or None when the cache has no entry."""
-    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0, 0, 0, 0, int(rule))
+    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0, 0, 0, 0, int(rule), 0)
     for k, v in explicit.items():
         setattr(opt, k, int(v))
     found = ctypes.c_int32()
@@ -246,6 +255,21 @@ def fdmt_boxcar_workspace_bytes(batch, nd, nt, max_log2):
 def fdmt_boxcar_search(plane_ptr, batch, nd, nt, max_log2, out_ptr, ws_ptr, ws_bytes, stream):
     _check(load().fdmt_boxcar_search(plane_ptr, int(batch), int(nd), int(nt), int(max_log2), out_ptr, ws_ptr,
                                      int(ws_bytes), stream), "fdmt_boxcar_search")
+
+
+def fdmt_search_workspace_bytes(plan, batch, max_log2):
+    return int(load().fdmt_search_workspace_bytes(plan, int(batch), int(max_log2)))
+
+
+def fdmt_search_fused(plan, max_log2):
+    return bool(load().fdmt_search_fused(plan, int(max_log2)))
+
+
+def fdmt_forward_search(plan, in_ptr, out_ptr, batch, max_log2, threshold, stats_ptr, cands_ptr, cap, count_ptr,
+                        ws_ptr, ws_bytes, stream):
+    _check(load().fdmt_forward_search(plan, in_ptr, out_ptr, int(batch), int(max_log2), float(threshold),
+                                      stats_ptr, cands_ptr, int(cap), count_ptr, ws_ptr, int(ws_bytes), stream),
+           "fdmt_forward_search")
 
 
 def fdmt_boxcar_search_noalloc(plane_ptr, batch, nd, nt, max_log2, out_ptr, stream):
@@ -430,6 +454,44 @@ class Plan:
         """FFT-FDMT (Algorithm 2) of x; the plan needs fft=True."""
         return self._run(fdmt_forward_fft, x, out, self.nf, self.nd, self.in_dtype, self.acc_dtype,
                          self.fft_workspace() if ws is None else ws)
+
+    def search_workspace(self, batch=1, max_log2=8):
+        n = fdmt_search_workspace_bytes(self.handle, batch, max_log2)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+
+    def search_fused(self, max_log2=8):
+        """True when forward_search runs the boxcar search inside the last
+        forward pass (otherwise it reads the output back)."""
+        return fdmt_search_fused(self.handle, max_log2)
+
+    def forward_search(self, x, max_log2=8, threshold=6.0, cap=65536, out=None, ws=None):
+        """Forward transform plus boxcar search (fdmt_forward_search). Returns
+        (output, stats, candidates, count): stats as boxcar_search() returns
+        them, candidates an int32 tensor [min(count, cap)][6] of (beam, dt, t,
+        width_log2, peak bits, snr bits) - view columns 4 and 5 as float32 -
+        and count the number of candidates found (possibly above cap)."""
+        if x.device != self.device or x.dtype != self.in_dtype or x.shape[-2:] != (self.nf, self.nt):
+            raise ValueError("input does not match the plan")
+        x = x.contiguous()
+        batch = 1 if x.dim() == 2 else x.shape[0]
+        shape = (self.nd, self.nt) if x.dim() == 2 else (batch, self.nd, self.nt)
+        if out is None:
+            out = torch.empty(shape, dtype=self.acc_dtype, device=self.device)
+        if ws is None:
+            ws = self.search_workspace(batch, max_log2)
+        stats = torch.empty((batch, max_log2 + 1, self.nd, 5), dtype=torch.int32, device=self.device)
+        cands = torch.empty((max(cap, 1), 6), dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        fdmt_forward_search(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch,
+                            max_log2, threshold, ctypes.c_void_p(stats.data_ptr()),
+                            ctypes.c_void_p(cands.data_ptr()), cap, ctypes.c_void_p(count.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(self.device))
+        n = int(count.item())
+        f = stats.view(torch.float32)
+        res = {"peak": f[..., 0], "t": stats[..., 1], "mean": f[..., 2], "stdev": f[..., 3], "snr": f[..., 4]}
+        if x.dim() == 2:
+            res = {k: v[0] for k, v in res.items()}
+        return out, res, cands[:min(n, cap)], n
 
     def steps(self, adjoint=False):
         """Per-kernel description of the forward (or adjoint) launch sequence."""

@@ -232,6 +232,8 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   // at most 2^30, and Nt + d_min + 2 Nd leaves 2^13 samples of headroom.
   if (o.d_min < 0 || o.d_min > (1 << 30)) return fail(FDMT_E_INVALID, "d_min must be in [0, 2^30]");
   if (o.rule != 0 && o.rule != 1) return fail(FDMT_E_INVALID, "rule must be 0 (one C) or 1 (two C's)");
+  if (o.search_rows < 0 || o.search_rows > 4 || (o.search_rows & (o.search_rows - 1)))
+    return fail(FDMT_E_INVALID, "search_rows must be 1, 2 or 4");
   if (nt + o.d_min + 2 * static_cast<int64_t>(nd) > INT32_MAX - 8192)
     return fail(FDMT_E_INVALID, "Nt + d_min + 2 Nd must stay below 2^31 - 8192");
   if (o.max_block_rows < 0 || o.max_block_rows > 4096)
@@ -268,6 +270,7 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   if (o.gather_threads) p.gather_threads = o.gather_threads;
   if (o.adjoint_threads) p.adjoint_threads = o.adjoint_threads;
   p.adjoint_last_threads = o.adjoint_last_threads;
+  if (o.search_rows) p.search_rows = o.search_rows;
   p.adjoint_last_rows = o.adjoint_last_rows;
   p.adjoint_tile_major = o.adjoint_tile_major;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
@@ -785,6 +788,59 @@ fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, 
   return FDMT_OK;
 }
 
+size_t fdmt_search_workspace_bytes(fdmt_plan_t p, int32_t batch, int32_t max_log2) {
+  if (!p || batch < 1 || batch > 65535 || max_log2 < 0 || max_log2 > fdmt::kBoxMaxLog2) return 0;
+  const fdmt::Plan &P = p->plan;
+  const size_t fwd = fdmt::round_up(static_cast<int64_t>(fdmt::workspace_bytes(P, batch)), 256);
+  const size_t part = fdmt::round_up(
+      static_cast<int64_t>(fdmt::boxcar_workspace_bytes(batch, P.tab.nd, P.nt, max_log2)), 256);
+  return fwd + part + static_cast<size_t>(batch) * (max_log2 + 1) * P.tab.nd * sizeof(double2);
+}
+
+int32_t fdmt_search_fused(fdmt_plan_t p, int32_t max_log2) {
+  return p && fdmt::search_fusable(p->plan, max_log2) ? 1 : 0;
+}
+
+fdmt_status_t fdmt_forward_search(fdmt_plan_t p, const void *in, void *out, int32_t batch, int32_t max_log2,
+                                  float threshold, fdmt_boxcar_t *stats, fdmt_candidate_t *cands, int32_t cap,
+                                  int32_t *count, void *ws, size_t ws_bytes, void *hip_stream) {
+  if (!p) return fail(FDMT_E_INVALID, "plan is NULL");
+  if (p->plan.acc_dtype != FDMT_F32) return fail(FDMT_E_UNSUPPORTED, "the search reads an FP32 output plane");
+  if (max_log2 < 0 || max_log2 > fdmt::kBoxMaxLog2) return fail(FDMT_E_INVALID, "max_log2 must be in [0, 10]");
+  if (!stats || !count || cap < 0 || (cap > 0 && !cands))
+    return fail(FDMT_E_INVALID, "stats or count is NULL, cap < 0, or cands NULL with cap > 0");
+  if (!(threshold == threshold)) return fail(FDMT_E_INVALID, "threshold is NaN");
+  const size_t need = fdmt_search_workspace_bytes(p, batch, max_log2);
+  if (need == 0) return fail(FDMT_E_INVALID, "batch must be in [1, 65535]");
+  if (!ws || ws_bytes < need)
+    return fail(FDMT_E_WORKSPACE, "search workspace needs " + std::to_string(need) + " bytes, got " +
+                                      std::to_string(ws ? ws_bytes : 0));
+  const fdmt_status_t st = check_call(p, in, out, batch, ws, ws_bytes);
+  if (st != FDMT_OK) return st;
+  const fdmt::Plan &P = p->plan;
+  auto *base = static_cast<unsigned char *>(ws);
+  const size_t fwd = fdmt::round_up(static_cast<int64_t>(fdmt::workspace_bytes(P, batch)), 256);
+  const size_t partb = fdmt::round_up(
+      static_cast<int64_t>(fdmt::boxcar_workspace_bytes(batch, P.tab.nd, P.nt, max_log2)), 256);
+  auto *part = reinterpret_cast<fdmt::BoxPartial *>(base + fwd);
+  auto *mean_sd = reinterpret_cast<double2 *>(base + fwd + partb);
+  auto stream = static_cast<hipStream_t>(hip_stream);
+  float *plane = static_cast<float *>(out);
+  hipError_t e;
+  if (fdmt::search_fusable(P, max_log2)) {
+    e = fdmt::launch_forward_search(P, in, plane, batch, ws, part, max_log2, stream);
+  } else {
+    e = fdmt::launch_forward(P, in, out, batch, ws, stream);
+    if (e == hipSuccess) e = fdmt::launch_boxcar_tiles(plane, batch, P.tab.nd, P.nt, max_log2, part, stream);
+  }
+  if (e == hipSuccess) e = fdmt::launch_boxcar_combine(part, batch, P.tab.nd, P.nt, max_log2, stats, mean_sd, stream);
+  if (e == hipSuccess)
+    e = fdmt::launch_boxcar_candidates(part, mean_sd, batch, P.tab.nd, P.nt, max_log2, threshold, cands, cap, count,
+                                       stream);
+  if (e != hipSuccess) return device_fail(e, "forward search launch");
+  return FDMT_OK;
+}
+
 fdmt_status_t fdmt_boxcar_search_noalloc(const float *plane, int32_t batch, int32_t nd, int64_t nt,
                                          int32_t max_log2, fdmt_boxcar_t *out, void *hip_stream) {
   if (!plane || !out) return fail(FDMT_E_INVALID, "plane or out is NULL");
@@ -884,7 +940,8 @@ fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32
                           {"adjoint_tile_major", nullptr, &opt->adjoint_tile_major},
                           {"gather_threads", &opt->gather_threads, nullptr},
                           {"adjoint_threads", &opt->adjoint_threads, nullptr},
-                          {"adjoint_last_threads", &opt->adjoint_last_threads, nullptr}};
+                          {"adjoint_last_threads", &opt->adjoint_last_threads, nullptr},
+                          {"search_rows", &opt->search_rows, nullptr}};
   for (const auto &kv : o) {
     const Field *f = nullptr;
     for (const Field &c : fields)

@@ -36,4 +36,21 @@ hipError_t boxcar_static_scratch(int device, void **ptr);
 hipError_t launch_boxcar(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
                          fdmt_boxcar_t *out, void *ws, hipStream_t stream);
 
+// The steps of the search. Partials part[((b * (max_log2 + 1) + j) * nd + row) * ntiles + tile]
+// cover tile `tile` = samples [tile * kBoxTile, (tile + 1) * kBoxTile) of
+// row `row`; the tile kernel fills them from the plane, or the last forward
+// pass fills the windows inside each tile and launch_boxcar_edges adds the
+// windows straddling each tile start. combine reduces them per row (and
+// stores the float64 mean and stdev in mean_sd when not null); candidates
+// keeps each tile's peak whose S/N reaches the threshold.
+hipError_t launch_boxcar_tiles(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                               BoxPartial *part, hipStream_t stream);
+hipError_t launch_boxcar_edges(const float *plane, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                               BoxPartial *part, hipStream_t stream);
+hipError_t launch_boxcar_combine(const BoxPartial *part, int32_t batch, int32_t nd, int64_t nt, int32_t max_log2,
+                                 fdmt_boxcar_t *out, double2 *mean_sd, hipStream_t stream);
+hipError_t launch_boxcar_candidates(const BoxPartial *part, const double2 *mean_sd, int32_t batch, int32_t nd,
+                                    int64_t nt, int32_t max_log2, float threshold, fdmt_candidate_t *cand,
+                                    int32_t cap, int32_t *found, hipStream_t stream);
+
 } // namespace fdmt

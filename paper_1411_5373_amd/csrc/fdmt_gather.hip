@@ -24,11 +24,130 @@ namespace {
 // 4 per lane; every term is one unaligned 16-byte load per lane, all issued
 // before any add. Rows run fastest in the workgroup order so neighbouring
 // rows - which share most of their terms - meet in one XCD's L2.
-template <typename Tsrc, typename Tacc, typename Tdst, int K, int CV, bool RAGGED>
+template <typename T>
+__device__ __forceinline__ T xor_lane(T x, int mask) {
+  return __shfl_xor(x, mask, 64);
+}
+
+// Peak order: larger value first, then earlier time.
+__device__ __forceinline__ bool better_peak(float v, int t, float bv, int bt) {
+  return v > bv || (v == bv && t < bt);
+}
+
+// Boxcar search over a workgroup's output tile, fused into the last forward
+// pass (Sec. 4.2, pulse profile: one transform serves every width). Each row
+// of the workgroup puts its tile of W = 256 * CV * col_waves samples into
+// LDS after 2^m - 1 zeros, builds width 2w from width w as
+// b_2w[i] = b_w[i] + b_w[i - w] (the doubling tree of the standalone search,
+// so every value is the same sum of the same terms) and, per width, reduces
+// the sum, sum of squares and first peak of b_w over the windows that lie
+// inside the tile into its partial. A window that reaches back past the
+// tile start is left to the edge kernel, except in the first tile, where
+// the zeros are the record's zero history.
+typedef float F4 __attribute__((ext_vector_type(4)));
+
+template <int CV>
+__device__ __forceinline__ void search_tile(const F4 (&out)[CV],
+                                            const SearchTile &st, int wave, int lane, int col_waves,
+                                            int rows_per_wg, int r, bool row_ok, int tile, int nt, int nrows) {
+  extern __shared__ float sbuf[];
+  struct Red {
+    double s, q;
+    float peak;
+    int t;
+  };
+  constexpr int kPer = 4 * CV;  // tile samples per thread: W / (64 * col_waves)
+  const int m = st.max_log2;
+  const int halo = (1 << m) - 1;
+  const int width = 256 * CV * col_waves;
+  const int len = halo + width;
+  const int rl = wave / col_waves;              // row within the workgroup
+  const int rt = (wave % col_waves) * 64 + lane;  // thread within the row
+  const int nthr = 64 * col_waves;
+  float *rb = sbuf + rl * len;
+  Red *red = reinterpret_cast<Red *>(sbuf + ((rows_per_wg * len + 1) & ~1));
+  const int64_t start = static_cast<int64_t>(tile) * width;
+  const int nvalid = nt - start < width ? static_cast<int>(nt - start) : width;
+  for (int i = rt; i < halo; i += nthr) rb[i] = 0.0f;
+  const int u0 = (wave % col_waves) * 256 * CV + 4 * lane;
+#pragma unroll
+  for (int c = 0; c < CV; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[halo + u0 + 256 * c + q] = out[c][q];
+  __syncthreads();
+  for (int j = 0; j <= m; ++j) {
+    if (j > 0) {
+      const int hw = 1 << (j - 1);
+      float nv[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int i = halo + rt + k * nthr;
+        nv[k] = rb[i] + rb[i - hw];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) rb[halo + rt + k * nthr] = nv[k];
+      __syncthreads();
+    }
+    const int lo = tile == 0 ? 0 : (1 << j) - 1;
+    double s = 0.0, q = 0.0;
+    float best = -__builtin_inff();
+    int bt = INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int u = rt + k * nthr;  // increasing in k: equal values keep the first
+      if (u >= lo && u < nvalid) {
+        const float x = rb[halo + u];
+        s += static_cast<double>(x);
+        q += static_cast<double>(x) * static_cast<double>(x);
+        if (x > best || (x == best && bt == INT32_MAX)) {
+          best = x;
+          bt = u;
+        }
+      }
+    }
+#pragma unroll
+    for (int mk = 32; mk >= 1; mk >>= 1) {
+      s += xor_lane(s, mk);
+      q += xor_lane(q, mk);
+      const float ov = xor_lane(best, mk);
+      const int ot = xor_lane(bt, mk);
+      if (better_peak(ov, ot, best, bt)) {
+        best = ov;
+        bt = ot;
+      }
+    }
+    if (lane == 0) red[rl * col_waves + wave % col_waves] = Red{s, q, best, bt};
+    __syncthreads();
+    if (rt == 0 && row_ok) {
+      Red a = red[rl * col_waves];
+      for (int c = 1; c < col_waves; ++c) {
+        const Red x = red[rl * col_waves + c];
+        a.s += x.s;
+        a.q += x.q;
+        if (better_peak(x.peak, x.t, a.peak, a.t)) {
+          a.peak = x.peak;
+          a.t = x.t;
+        }
+      }
+      const int b = blockIdx.z;
+      BoxPartial &p = st.part[((static_cast<int64_t>(b) * (m + 1) + j) * nrows + r) * st.ntiles + tile];
+      p.sum = a.s;
+      p.sumsq = a.q;
+      p.peak = a.peak;
+      p.t = a.t == INT32_MAX ? INT32_MAX : static_cast<int32_t>(start) + a.t;
+    }
+  }
+}
+
+// SEARCH (the last pass of a forward with the boxcar search, uniform
+// batches, FP32 output): after storing its outputs, the workgroup runs the
+// boxcar search over its tile of each of its rows in LDS (see search_tile).
+template <typename Tsrc, typename Tacc, typename Tdst, int K, int CV, bool RAGGED, bool SEARCH = false>
 __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     const Tsrc *__restrict__ src, Tdst *__restrict__ dst, const int2 *__restrict__ terms,
     int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
-    int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg) {
+    int64_t dst_bstride, int32_t nrows, int32_t rows_per_wg, RaggedMap rg, SearchTile search) {
   typedef typename Vec4<Tacc>::type V;
   typedef typename Vec4<Tsrc>::type S4;
   typedef typename Vec4<Tdst>::type D4;
@@ -44,16 +163,19 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   const int2 item = gather_item<RAGGED>(groups, false);
   const int g = item.x;
   const int r = g * rows_per_wg + wave / col_waves;
-  if (r >= nrows) return;
+  // with the search every thread stays for its barriers: rows past the last
+  // and samples past the record compute zeros and store nothing
+  if (!SEARCH && r >= nrows) return;
+  const bool row_ok = r < nrows;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
   if (!RAGGED) bs.tile = item.y;
   const int nt = bs.nt;
   const int64_t src_stride = bs.src_stride;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
-  if (t >= nt) return;
+  if (!SEARCH && t >= nt) return;
   const Tsrc *base = src + bs.src_off;
-  const int2 *tm = terms + static_cast<int64_t>(r) * N;
+  const int2 *tm = terms + static_cast<int64_t>(row_ok ? r : nrows - 1) * N;
   int2 e[N];
   int smax = 0;
 #pragma unroll
@@ -125,15 +247,23 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     for (int j = 0; j < N; j += 2 * span)
 #pragma unroll
       for (int c = 0; c < CV; ++c) v[j][c] = v[j][c] + v[j + span][c];
+  if (row_ok) {
 #pragma unroll
-  for (int c = 0; c < CV; ++c) {
-    const int tc = t + 256 * c;
-    Tdst *o = dst + bs.dst_off + r * bs.dst_stride + tc;
-    if (tc + 4 <= nt) {
-      *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
-    } else {
-      for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = static_cast<Tdst>(v[0][c][i]);
+    for (int c = 0; c < CV; ++c) {
+      const int tc = t + 256 * c;
+      Tdst *o = dst + bs.dst_off + r * bs.dst_stride + tc;
+      if (tc + 4 <= nt) {
+        *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
+      } else {
+        for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = static_cast<Tdst>(v[0][c][i]);
+      }
     }
+  }
+  if constexpr (SEARCH) {
+    F4 outf[CV];  // the values just stored (FP32 output)
+#pragma unroll
+    for (int c = 0; c < CV; ++c) outf[c] = __builtin_convertvector(v[0][c], F4);
+    search_tile<CV>(outf, search, wave, lane, col_waves, rows_per_wg, r, row_ok, bs.tile, nt, nrows);
   }
 }
 
@@ -342,10 +472,38 @@ template <typename Tsrc, typename Tacc, typename Tdst>
 hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, const int2 *terms, int32_t nt,
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
+  if (g.search.part) {
+    // the last forward pass with the boxcar search: FP32 output, uniform batches
+    if constexpr (std::is_same<Tdst, float>::value) {
+      if (g.ragged) return hipErrorInvalidValue;
+      const int col_waves = g.threads / 64 / g.rows_per_wg;
+      const int len = (1 << g.search.max_log2) - 1 + 256 * g.vecs * col_waves;
+      const size_t lds = ((g.rows_per_wg * len + 1) & ~1) * sizeof(float) +
+                         static_cast<size_t>(g.rows_per_wg) * col_waves * 24;
+#define FDMT_SEARCH(KK, CC)                                                                                   \
+  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, false, true>), g.grid, dim3(g.threads), lds, \
+                     g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows,       \
+                     g.rows_per_wg, g.rg, g.search)
+#define FDMT_SEARCH_K(CC)                  \
+  switch (g.depth) {                       \
+    case 1: FDMT_SEARCH(1, CC); break;     \
+    case 2: FDMT_SEARCH(2, CC); break;     \
+    case 3: FDMT_SEARCH(3, CC); break;     \
+    case 4: FDMT_SEARCH(4, CC); break;     \
+    default: return hipErrorInvalidValue;  \
+  }
+      if (g.vecs == 2) { FDMT_SEARCH_K(2) } else { FDMT_SEARCH_K(1) }
+#undef FDMT_SEARCH_K
+#undef FDMT_SEARCH
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
 #define FDMT_GATHER(KK, CC, RR)                                                                         \
   hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0, \
                      g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, \
-                     g.rows_per_wg, g.rg)
+                     g.rows_per_wg, g.rg, g.search)
 #define FDMT_GATHER_K(CC, RR)             \
   switch (g.depth) {                      \
     case 1: FDMT_GATHER(1, CC, RR); break; \

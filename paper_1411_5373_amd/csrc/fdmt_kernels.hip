@@ -644,7 +644,7 @@ hipError_t for_each_launch(const Plan &p, const RaggedBatch *rb, const Step &st,
 
 template <typename Tin, typename Tacc>
 hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void *out, int batch,
-                            void *ws, hipStream_t stream, const RaggedBatch *rb) {
+                            void *ws, hipStream_t stream, const RaggedBatch *rb, const SearchTile *search) {
   const Tables &T = p.tab;
   const int64_t nt = p.nt;
   const View src = view(p, st.src, in, out, ws, batch, false, rb);
@@ -763,9 +763,12 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
       if (ps.gather) {
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
-        const int rpw = p.gather_rows;  // rows per workgroup: 1, 2, 4, 8 or 16
+        // rows per workgroup (1, 2, 4, 8 or 16) and workgroup size; a pass
+        // that runs the search may take its own
+        const int rpw = search && search->rows ? search->rows : p.gather_rows;
+        const int threads = search && search->threads ? search->threads : p.gather_threads;
         const int cv = forward_vecs(p);  // runs of 4 samples per lane: 1 or 2
-        const int tile = 256 * cv * (p.gather_threads / 64 / rpw);
+        const int tile = 256 * cv * (threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int2 *tm = p.dev_terms + ps.term_offset;
@@ -773,7 +776,8 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const bool narrow_out = p.narrow[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
-          g.threads = p.gather_threads;
+          g.threads = threads;
+          if (search) g.search = *search;
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
             // uint16 out: the integer-sum kernel (a lane's 8 samples are one
@@ -1003,7 +1007,7 @@ hipError_t prepare_kernels(const Plan &p) {
 }
 
 hipError_t run_step(const Plan &p, bool adjoint, int i, const void *in, void *out, int batch,
-                    void *ws, hipStream_t stream, const RaggedBatch *rb) {
+                    void *ws, hipStream_t stream, const RaggedBatch *rb, const SearchTile *search) {
   if (adjoint) {
     const Step &st = p.adj_steps[i];
     if (p.acc_dtype == FDMT_F32) return run_adjoint_step<float>(p, st, in, out, batch, ws, stream, rb);
@@ -1012,15 +1016,15 @@ hipError_t run_step(const Plan &p, bool adjoint, int i, const void *in, void *ou
   const Step &st = p.fwd_steps[i];
   if (p.acc_dtype == FDMT_F32) {
     switch (p.in_dtype) {
-      case FDMT_F32: return run_forward_step<float, float>(p, st, in, out, batch, ws, stream, rb);
-      case FDMT_F16: return run_forward_step<_Float16, float>(p, st, in, out, batch, ws, stream, rb);
-      case FDMT_U8: return run_forward_step<uint8_t, float>(p, st, in, out, batch, ws, stream, rb);
+      case FDMT_F32: return run_forward_step<float, float>(p, st, in, out, batch, ws, stream, rb, search);
+      case FDMT_F16: return run_forward_step<_Float16, float>(p, st, in, out, batch, ws, stream, rb, search);
+      case FDMT_U8: return run_forward_step<uint8_t, float>(p, st, in, out, batch, ws, stream, rb, search);
       default: return hipErrorInvalidValue;
     }
   }
   switch (p.in_dtype) {
-    case FDMT_U8: return run_forward_step<uint8_t, int32_t>(p, st, in, out, batch, ws, stream, rb);
-    case FDMT_I32: return run_forward_step<int32_t, int32_t>(p, st, in, out, batch, ws, stream, rb);
+    case FDMT_U8: return run_forward_step<uint8_t, int32_t>(p, st, in, out, batch, ws, stream, rb, search);
+    case FDMT_I32: return run_forward_step<int32_t, int32_t>(p, st, in, out, batch, ws, stream, rb, search);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1056,6 +1060,47 @@ hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, v
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Geometry of the last forward pass when it runs the search: tiles of
+// kBoxTile samples, p.search_rows (> 0) rows per workgroup.
+static void search_geometry(const Plan &p, int &rows, int &threads) {
+  const int col_waves = kBoxTile / (256 * forward_vecs(p));
+  rows = p.search_rows;
+  threads = 64 * col_waves * rows;
+}
+
+bool search_fusable(const Plan &p, int max_log2) {
+  if (p.search_rows == 0) return false;
+  if (p.acc_dtype != FDMT_F32 || p.fwd_steps.empty() || max_log2 < 0 || max_log2 > kBoxMaxLog2) return false;
+  const int last = static_cast<int>(p.fwd_steps.size()) - 1;
+  const Step &st = p.fwd_steps[last];
+  if (st.kind != Step::Fused) return false;
+  const Pass &ps = p.fwd.passes[st.index];
+  if (!ps.gather || ps.from_input) return false;
+  int rows, threads;
+  search_geometry(p, rows, threads);
+  if (threads > kGatherThreads) return false;
+  const size_t lds = static_cast<size_t>(rows) * ((1 << max_log2) - 1 + kBoxTile) * 4 + 8 +
+                     static_cast<size_t>(threads / 64) * 24;
+  return lds <= 64 * 1024;
+}
+
+hipError_t launch_forward_search(const Plan &p, const void *in, float *out, int batch, void *ws, BoxPartial *part,
+                                 int max_log2, hipStream_t stream) {
+  const int last = static_cast<int>(p.fwd_steps.size()) - 1;
+  for (int i = 0; i < last; ++i) {
+    hipError_t e = run_step(p, false, i, in, out, batch, ws, stream);
+    if (e != hipSuccess) return e;
+  }
+  SearchTile st;
+  st.part = part;
+  st.max_log2 = max_log2;
+  st.ntiles = static_cast<int32_t>((p.nt + kBoxTile - 1) / kBoxTile);
+  search_geometry(p, st.rows, st.threads);
+  hipError_t e = run_step(p, false, last, in, out, batch, ws, stream, nullptr, &st);
+  if (e != hipSuccess) return e;
+  return launch_boxcar_edges(out, batch, p.tab.nd, p.nt, max_log2, part, stream);
 }
 
 hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch, void *ws,

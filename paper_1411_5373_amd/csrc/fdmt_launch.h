@@ -6,9 +6,20 @@
 
 #include <cstdint>
 
+#include "fdmt_boxcar.h"
 #include "fdmt_device.h"
 
 namespace fdmt {
+
+// Boxcar search fused into the last forward pass: where its tile partials
+// go (null: no search), the widths (2^0 .. 2^max_log2) and the tiles per row.
+struct SearchTile {
+  BoxPartial *part = nullptr;
+  int32_t max_log2 = 0;
+  int32_t ntiles = 0;
+  int32_t rows = 0;     // rows per workgroup of the pass (0: the plan's)
+  int32_t threads = 0;  // workgroup size of the pass (0: the plan's)
+};
 
 // Geometry of one gather launch: grid, stream, ragged map (used when
 // `ragged`), k or tree depth, runs of 4 samples per lane, rows per workgroup.
@@ -21,6 +32,7 @@ struct GatherLaunch {
   bool lagged = false;  // adjoint: lagged leaf list (subtrees listed once)
   int tiles_fastest = 0;  // adjoint: run each row group's time tiles back to back (uniform launches)
   int threads = kGatherThreads;  // workgroup size: 64 .. 1024, a multiple of 64 * rows_per_wg
+  SearchTile search;             // forward gathers: the fused boxcar search (last pass only)
 };
 
 // Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fdmt.h"
+#include "fdmt_launch.h"
 #include "fdmt_schedule.h"
 #include "fdmt_tables.h"
 
@@ -68,6 +69,8 @@ struct Plan {
   int gather_threads = 1024;   // workgroup size of the forward register gathers (64 .. 1024)
   int adjoint_threads = 1024;  // workgroup size of the adjoint register gathers (64 .. 1024)
   int adjoint_last_threads = 0;  // ... of the last adjoint pass (0: adjoint_threads)
+  int search_rows = 0;         // rows per workgroup of the last forward pass when it runs the
+                               // search (0: the search runs after the transform)
   int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: gather_rows)
   uint32_t adjoint_tile_major = 0;  // bit i: adjoint pass i runs each row group's tiles back to back
   const int2 *dev_sterms = nullptr;
@@ -102,11 +105,18 @@ void plan_steps(Plan &p);
 // Kernel sequences (fdmt_kernels.hip). All assume validated arguments; `rb`
 // (null: `batch` beams of p.nt samples) switches every launch to a ragged batch.
 hipError_t run_step(const Plan &p, bool adjoint, int step, const void *in, void *out, int batch,
-                    void *ws, hipStream_t stream, const RaggedBatch *rb = nullptr);
+                    void *ws, hipStream_t stream, const RaggedBatch *rb = nullptr,
+                    const SearchTile *search = nullptr);
 hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, void *ws,
                           hipStream_t stream, const RaggedBatch *rb = nullptr);
 hipError_t launch_adjoint(const Plan &p, const void *grad_out, void *grad_in, int batch, void *ws,
                           hipStream_t stream, const RaggedBatch *rb = nullptr);
+// Forward whose last pass also runs the boxcar search over its output tiles
+// (uniform batches; only when search_fusable): the tile partials of windows
+// inside each tile, then the edge kernel's windows across tile starts.
+bool search_fusable(const Plan &p, int max_log2);
+hipError_t launch_forward_search(const Plan &p, const void *in, float *out, int batch, void *ws, BoxPartial *part,
+                                 int max_log2, hipStream_t stream);
 // Time-tile width of a step's launches; 0 when the step has no ragged form.
 int step_tile(const Plan &p, bool adjoint, int step);
 // Output rows per workgroup of adjoint register-gather pass `pass`.

@@ -703,3 +703,35 @@ def test_two_c_recovers_pulse_at_labels():
         assert abs(i - dt) <= 2 and abs(j - T) <= 2, (i, j)
         assert y[i, j] >= 0.6 * amp * nf, y[i, j] / (amp * nf)
         x[:] = 0
+
+
+def test_boxcar_candidates_closed_form_and_pulses():
+    """Candidates (one per row, width and 2048-sample block whose peak S/N is
+    at least the threshold). A zero row with impulses A at t1 < t2 in
+    different blocks: for width w, b_w is A on [t_i, t_i + w - 1], mean
+    2wA/Nt and stdev sqrt(2wA^2/Nt - mean^2); each impulse's block is a
+    candidate at t_i with that S/N, no other block is. And pulses planted in
+    noise are found at their row, width and end time."""
+    from oracle import boxcar_candidates
+    nt, a, t1, t2 = 10000, 4.0, 100, 6000
+    y = np.zeros((2, nt))
+    y[1, [t1, t2]] = a
+    m = 3
+    c = boxcar_candidates(y, m, 5.0)
+    for j in range(m + 1):
+        w = 1 << j
+        mean = 2 * w * a / nt
+        sd = math.sqrt(2 * w * a * a / nt - mean * mean)
+        got = [x for x in c if x[2] == j]
+        assert [(x[1], x[3]) for x in got] == [(1, t1), (1, t2)]
+        for x in got:
+            assert x[4] == a and math.isclose(x[5], (a - mean) / sd, rel_tol=1e-12)
+    assert boxcar_candidates(y, m, 1e9) == []
+    rng = _rng(17)
+    z = rng.standard_normal((8, 12000))
+    z[3, 5000:5008] += 4.0           # an 8-sample pulse ending at 5007 (S/N about 11 at width 8)
+    c = boxcar_candidates(z, 5, 7.0)
+    assert c and all(x[1] == 3 for x in c)
+    best = max(c, key=lambda x: x[5])
+    assert best[2] == 3 and abs(best[3] - 5007) <= 1
+
