@@ -48,6 +48,7 @@ KERNEL_SOURCES = ("paper_1411_5373_amd/csrc/fdmt_kernels.hip",
                   "paper_1411_5373_amd/csrc/fdmt_narrow.hip",
                   "paper_1411_5373_amd/csrc/fdmt_adjoint.hip",
                   "paper_1411_5373_amd/csrc/fdmt_device.h",
+                  "paper_1411_5373_amd/csrc/fdmt_launch.h",
                   "paper_1411_5373_amd/csrc/fdmt_schedule.cpp",
                   "paper_1411_5373_amd/tuning/gfx950.json")
 ACCURACY_SAMPLES = 4096  # length of the causal slices checked against the oracle
@@ -449,6 +450,19 @@ def ragged_c4(F, torch, W, reps=5):
 
     fwd_ms = timed(lambda: r.forward(x, out=y, ws=ws))
     adj_ms = timed(lambda: r.adjoint(g, out=xb, ws=ws))
+    # one launch per pass: the passes' own times against the whole call (the
+    # difference is launch gaps), and the call split into two half batches
+    # (t1 + t2 - t = what one call costs beyond its work: launches plus each
+    # pass's fill and drain, the most a single persistent kernel could save)
+    fwd_kernels = [timed(lambda: r.run_step(False, i, x, y, ws)) for i in range(len(plan.steps(False)))]
+    half = len(lengths) // 2
+    halves = []
+    for sel in (lengths[:half], lengths[half:]):
+        rp = F.RaggedPlan(plan, sel)
+        n = sum(sel)
+        wsp = rp.workspace()
+        halves.append(timed(lambda: rp.forward(x[:w.nf * n], out=y[:w.nd * n], ws=wsp)))
+        del rp, wsp
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
@@ -468,6 +482,10 @@ def ragged_c4(F, torch, W, reps=5):
             "launches_forward_plus_adjoint": r.info()[2],
             "forward_ms": round(fwd_ms, 4), "forward_graph_ms": round(graph_ms, 4),
             "adjoint_ms": round(adj_ms, 4), "per_beam_loop_forward_ms": round(loop_ms, 4),
+            "forward_kernels_ms": [round(m, 4) for m in fwd_kernels],
+            "forward_launch_gaps_ms": round(fwd_ms - sum(fwd_kernels), 4),
+            "half_batches_forward_ms": [round(m, 4) for m in halves],
+            "per_call_fixed_ms": round(sum(halves) - fwd_ms, 4),
             "forward_dm_trial_samples_per_s": rate, "schedule": plan.options}
 
 
@@ -484,6 +502,8 @@ def main():
                     help="skip the ragged-batch and differentiable workloads")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one streaming copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--only", choices=("ragged", "differentiable"),
+                    help="only run this workload's leg and print its result (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -506,6 +526,10 @@ def main():
         F.copy_bytes(b, a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.only:
+        leg = ragged_c4 if args.only == "ragged" else differentiable_c5
+        print(json.dumps({args.only: leg(F, torch, W)}), flush=True)
         return
 
     copy = copy_ceiling(F, torch)

@@ -161,7 +161,9 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
 // A wave covers 256 * CV consecutive samples (4 per lane, CV runs 256 apart)
 // and stores them all, or in a lagged pass all but the last lane's last run:
 // those 4 samples only feed the lane exchange, and the next wave starts there.
-template <typename Tacc, int K, int CV, bool RAGGED, bool LAG>
+// NT: the output is not read again by this call (the pass into the channels),
+// so its full-run stores are non-temporal.
+template <typename Tacc, int K, int CV, bool RAGGED, bool LAG, bool NT>
 __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     const Tacc *__restrict__ src, Tacc *__restrict__ dst, const int4 *__restrict__ leaves,
     const int32_t *__restrict__ starts, const int32_t *__restrict__ order, int32_t nt_u, int32_t max_shift,
@@ -213,7 +215,10 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     if (LAG && c == CV - 1 && lane == 63) continue;
     Tacc *o = dst + bs.dst_off + out_row * bs.dst_stride + tc;
     if (tc + 4 <= nt) {
-      *reinterpret_cast<V *>(o) = sums.acc[0][c];
+      if constexpr (NT)
+        __builtin_nontemporal_store(sums.acc[0][c], reinterpret_cast<V *>(o));
+      else
+        *reinterpret_cast<V *>(o) = sums.acc[0][c];
     } else {
       for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = sums.acc[0][c][i];
     }
@@ -227,10 +232,16 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
                                  const int32_t *starts, const int32_t *order, int32_t nt, int32_t max_shift,
                                  int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                                  int32_t nrows) {
-#define FDMT_ADJ(KK, CC, RR, LL)                                                                         \
-  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL>), g.grid, dim3(g.threads), 0, g.stream, \
-                     src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,      \
+#define FDMT_ADJ_NT(KK, CC, RR, LL, NN)                                                                       \
+  hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL, NN>), g.grid, dim3(g.threads), 0, g.stream, \
+                     src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,          \
                      dst_bstride, nrows, g.rows_per_wg, g.tiles_fastest, g.rg)
+#define FDMT_ADJ(KK, CC, RR, LL)                           \
+  if (g.streaming) {                                       \
+    FDMT_ADJ_NT(KK, CC, RR, LL, true);                     \
+  } else {                                                 \
+    FDMT_ADJ_NT(KK, CC, RR, LL, false);                    \
+  }
 #define FDMT_ADJ_K(CC, RR)                                    \
   if (g.lagged) {                                             \
     switch (g.depth) {                                        \
@@ -257,6 +268,7 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
   }
 #undef FDMT_ADJ_K
 #undef FDMT_ADJ
+#undef FDMT_ADJ_NT
   return hipGetLastError();
 }
 

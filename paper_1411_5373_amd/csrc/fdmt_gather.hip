@@ -143,7 +143,10 @@ __device__ __forceinline__ void search_tile(const F4 (&out)[CV],
 // SEARCH (the last pass of a forward with the boxcar search, uniform
 // batches, FP32 output): after storing its outputs, the workgroup runs the
 // boxcar search over its tile of each of its rows in LDS (see search_tile).
-template <typename Tsrc, typename Tacc, typename Tdst, int K, int CV, bool RAGGED, bool SEARCH = false>
+// NT: the output is not read again by this call (the last pass), so its
+// full-run stores are non-temporal; the search pass always writes the output.
+template <typename Tsrc, typename Tacc, typename Tdst, int K, int CV, bool RAGGED, bool SEARCH = false,
+          bool NT = SEARCH>
 __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     const Tsrc *__restrict__ src, Tdst *__restrict__ dst, const int2 *__restrict__ terms,
     int32_t nt_u, int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u,
@@ -253,7 +256,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
       const int tc = t + 256 * c;
       Tdst *o = dst + bs.dst_off + r * bs.dst_stride + tc;
       if (tc + 4 <= nt) {
-        *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
+        if constexpr (NT)
+          __builtin_nontemporal_store(__builtin_convertvector(v[0][c], D4), reinterpret_cast<D4 *>(o));
+        else
+          *reinterpret_cast<D4 *>(o) = __builtin_convertvector(v[0][c], D4);
       } else {
         for (int i = 0; i < 4 && tc + i < nt; ++i) o[i] = static_cast<Tdst>(v[0][c][i]);
       }
@@ -500,10 +506,16 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
       return hipErrorInvalidValue;
     }
   }
-#define FDMT_GATHER(KK, CC, RR)                                                                         \
-  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0, \
-                     g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows, \
+#define FDMT_GATHER_NT(KK, CC, RR, NN)                                                                      \
+  hipLaunchKernelGGL((gather_pass_kernel<Tsrc, Tacc, Tdst, KK, CC, RR, false, NN>), g.grid, dim3(g.threads), 0, \
+                     g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows,     \
                      g.rows_per_wg, g.rg, g.search)
+#define FDMT_GATHER(KK, CC, RR)          \
+  if (g.streaming) {                     \
+    FDMT_GATHER_NT(KK, CC, RR, true);    \
+  } else {                               \
+    FDMT_GATHER_NT(KK, CC, RR, false);   \
+  }
 #define FDMT_GATHER_K(CC, RR)             \
   switch (g.depth) {                      \
     case 1: FDMT_GATHER(1, CC, RR); break; \
@@ -519,6 +531,7 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
   }
 #undef FDMT_GATHER_K
 #undef FDMT_GATHER
+#undef FDMT_GATHER_NT
   return hipGetLastError();
 }
 

@@ -777,6 +777,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           g.threads = threads;
+          g.streaming = st.dst == Buf::Out;
           if (search) g.search = *search;
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
@@ -860,9 +861,10 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
       Tacc *dp = static_cast<Tacc *>(dst.ptr);
       const int32_t nt32 = static_cast<int32_t>(nt);
       return for_each_launch(p, rb, st, true, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
-        const GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw, ps.lagged,
-                             st.index < 32 ? static_cast<int>((p.adjoint_tile_major >> st.index) & 1u) : 0,
-                             threads};
+        GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw, ps.lagged,
+                       st.index < 32 ? static_cast<int>((p.adjoint_tile_major >> st.index) & 1u) : 0,
+                       threads};
+        g.streaming = ps.to_input;
         return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, ps.max_shift, src.stride, src.bstride,
                                            dst.stride, dst.bstride, ps.nrows);
       });

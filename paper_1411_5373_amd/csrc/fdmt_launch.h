@@ -33,6 +33,7 @@ struct GatherLaunch {
   int tiles_fastest = 0;  // adjoint: run each row group's time tiles back to back (uniform launches)
   int threads = kGatherThreads;  // workgroup size: 64 .. 1024, a multiple of 64 * rows_per_wg
   SearchTile search;             // forward gathers: the fused boxcar search (last pass only)
+  bool streaming = false;        // output not read again by this call: non-temporal stores
 };
 
 // Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,
