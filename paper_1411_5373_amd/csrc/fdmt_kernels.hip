@@ -781,12 +781,15 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
           if (search) g.search = *search;
           if (narrow_in) {  // uint16 plane in: exact integer sums
             const uint16_t *sp = static_cast<const uint16_t *>(src.ptr);
-            // uint16 out: the integer-sum kernel (a lane's 8 samples are one
-            // 16-byte store). 4-byte planes: the 4-sample-run kernel, which
-            // timed faster there than the integer-sum kernel's wide loads.
+            // the integer-sum kernel (a lane's 8 samples are one 16-byte
+            // load per term); a pass that runs the search takes the
+            // 4-sample-run kernel, which has it
             if (narrow_out)
               return launch_narrow_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32, src.stride,
                                                     src.bstride, dst.stride, dst.bstride, ps.nblocks);
+            if (!search)
+              return launch_narrow_gather<Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.stride,
+                                                src.bstride, dst.stride, dst.bstride, ps.nblocks);
             return launch_gather<uint16_t, int32_t, Tacc>(g, sp, static_cast<Tacc *>(dst.ptr), tm, nt32, src.stride,
                                                           src.bstride, dst.stride, dst.bstride, ps.nblocks);
           }
