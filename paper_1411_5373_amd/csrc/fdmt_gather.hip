@@ -495,7 +495,7 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
     case 1: FDMT_SEARCH(1, CC); break;     \
     case 2: FDMT_SEARCH(2, CC); break;     \
     case 3: FDMT_SEARCH(3, CC); break;     \
-    case 4: FDMT_SEARCH(4, CC); break;     \
+    case 4: if (CC != 1) return hipErrorInvalidValue; FDMT_SEARCH(4, 1); break; \
     default: return hipErrorInvalidValue;  \
   }
       if (g.vecs == 2) { FDMT_SEARCH_K(2) } else { FDMT_SEARCH_K(1) }
@@ -521,7 +521,7 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
     case 1: FDMT_GATHER(1, CC, RR); break; \
     case 2: FDMT_GATHER(2, CC, RR); break; \
     case 3: FDMT_GATHER(3, CC, RR); break; \
-    case 4: FDMT_GATHER(4, CC, RR); break; \
+    case 4: if (CC != 1) return hipErrorInvalidValue; FDMT_GATHER(4, 1, RR); break; \
     default: return hipErrorInvalidValue; \
   }
   if (g.ragged) {
@@ -547,7 +547,7 @@ hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst,
     case 1: FDMT_IGATHER(1, CC, RR); break; \
     case 2: FDMT_IGATHER(2, CC, RR); break; \
     case 3: FDMT_IGATHER(3, CC, RR); break; \
-    case 4: FDMT_IGATHER(4, CC, RR); break; \
+    case 4: if (CC != 1) return hipErrorInvalidValue; FDMT_IGATHER(4, 1, RR); break; \
     default: return hipErrorInvalidValue;  \
   }
   if (g.ragged) {

@@ -608,7 +608,13 @@ constexpr int64_t kMaxGridY = 65535;
 
 // Runs of 4 samples per lane in the forward gathers: at most 2 (their 2^k
 // terms per run live in registers); the adjoint gather takes the plan's value.
-inline int forward_vecs(const Plan &p) { return p.gather_vecs < 2 ? p.gather_vecs : 2; }
+// Runs of 4 samples per lane of a forward gather pass: the plan's (1 or 2);
+// 1 for four-iteration passes, whose 16 terms of two runs each would not fit
+// the register budget of a 1024-thread workgroup.
+inline int forward_vecs(const Plan &p, const Pass &ps) {
+  if (ps.l1 - ps.l0 >= 4) return 1;
+  return p.gather_vecs < 2 ? p.gather_vecs : 2;
+}
 
 // Issues the launches of one step over time tiles of width `tile`. A uniform
 // batch is one launch: ceil(nt / tile) tiles in grid y, beams in grid z. A
@@ -737,7 +743,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         const int rpw = p.gather_rows;
-        const int cv = forward_vecs(p);
+        const int cv = forward_vecs(p, ps);
         const int tile = 256 * cv * (p.gather_threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
@@ -767,7 +773,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         // that runs the search may take its own
         const int rpw = search && search->rows ? search->rows : p.gather_rows;
         const int threads = search && search->threads ? search->threads : p.gather_threads;
-        const int cv = forward_vecs(p);  // runs of 4 samples per lane: 1 or 2
+        const int cv = forward_vecs(p, ps);  // runs of 4 samples per lane: 1 or 2
         const int tile = 256 * cv * (threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
@@ -1070,7 +1076,8 @@ hipError_t launch_forward(const Plan &p, const void *in, void *out, int batch, v
 // Geometry of the last forward pass when it runs the search: tiles of
 // kBoxTile samples, p.search_rows (> 0) rows per workgroup.
 static void search_geometry(const Plan &p, int &rows, int &threads) {
-  const int col_waves = kBoxTile / (256 * forward_vecs(p));
+  const Pass &ps = p.fwd.passes[p.fwd_steps.back().index];
+  const int col_waves = kBoxTile / (256 * forward_vecs(p, ps));
   rows = p.search_rows;
   threads = 64 * col_waves * rows;
 }
@@ -1127,7 +1134,6 @@ int adjoint_threads(const Plan &p, int pass) {
 
 int step_tile(const Plan &p, bool adjoint, int i) {
   const Step &st = adjoint ? p.adj_steps[i] : p.fwd_steps[i];
-  const int gather_tile = 256 * forward_vecs(p) * (p.gather_threads / 64 / p.gather_rows);
   switch (st.kind) {
     case Step::PadIn:
     case Step::Init:
@@ -1140,7 +1146,7 @@ int step_tile(const Plan &p, bool adjoint, int i) {
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;
-      return ps.gather ? gather_tile : ps.tile * p.rec_tiles;
+      return ps.gather ? 256 * forward_vecs(p, ps) * (p.gather_threads / 64 / p.gather_rows) : ps.tile * p.rec_tiles;
     }
   }
   return 0;

@@ -270,7 +270,7 @@ hipError_t launch_narrow(const GatherLaunch &g, const void *src, Tdst *dst, cons
     case 1: FDMT_NARROW(1, CC, RR); break; \
     case 2: FDMT_NARROW(2, CC, RR); break; \
     case 3: FDMT_NARROW(3, CC, RR); break; \
-    case 4: FDMT_NARROW(4, CC, RR); break; \
+    case 4: if (CC != 1) return hipErrorInvalidValue; FDMT_NARROW(4, 1, RR); break; \
     default: return hipErrorInvalidValue;  \
   }
   if (g.ragged) {
