@@ -723,7 +723,6 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
             case 2: FDMT_STAGED(true, 2); break;
             case 3: FDMT_STAGED(true, 3); break;
             case 4: FDMT_STAGED(true, 4); break;
-            case 5: FDMT_STAGED(true, 5); break;
             default: return hipErrorInvalidValue;
           }
         } else {
@@ -732,7 +731,6 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
             case 2: FDMT_STAGED(false, 2); break;
             case 3: FDMT_STAGED(false, 3); break;
             case 4: FDMT_STAGED(false, 4); break;
-            case 5: FDMT_STAGED(false, 5); break;
             default: return hipErrorInvalidValue;
           }
         }
@@ -968,8 +966,7 @@ hipError_t set_staged_lds_k(int lds) {
   const void *fns[] = {reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 1>),
                        reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 2>),
                        reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 3>),
-                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 4>),
-                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 5>)};
+                       reinterpret_cast<const void *>(&staged_pass_kernel<Tin, Tacc, FI, 4>)};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;

@@ -335,7 +335,9 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
         if (t.pre[k] != 0) return "the d_min pre-shift needs the first pass to gather from the input";
     if (kind == PassKind::Staged) {
       const int k = std::min(k_req, L - l0);
-      if (k > 5) return "at most 5 iterations per staged pass";
+      // five would hold 32 terms of 4 runs per thread: past the register
+      // budget of its workgroup (it spilled)
+      if (k > 4) return "at most 4 iterations per staged pass";
       if (p.tile % 256 != 0) return "staged passes need a tile that is a multiple of 256";
       Pass ps;
       ps.kind = PassKind::Staged;

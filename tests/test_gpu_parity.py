@@ -351,7 +351,7 @@ SCHEDULES = [
     dict(first_levels=1, later_levels=1, tile=256, lds_kib=16, max_block_rows=1),
     dict(first_levels=3, later_levels=2, tile=256, lds_kib=24, max_block_rows=5),
     dict(first_levels=4, later_levels=4, tile=256, lds_kib=64),
-    dict(first_levels=5, later_levels=5, tile=512, lds_kib=150, max_block_rows=128),
+    dict(first_levels=4, later_levels=4, tile=512, lds_kib=150, max_block_rows=128),
     dict(first_levels=2, later_levels=3, tile=1024, lds_kib=96),
     dict(first_levels=4, later_levels=3, stream_tiles=1),
     dict(first_levels=4, later_levels=4, stream_tiles=5),
