@@ -185,28 +185,85 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
         }
       }
     }
+    if constexpr (sizeof(Tdst) == 2) {
+      // uint16 output: the plan stores a plane as uint16 only when every
+      // element is below 2^16, and every term is non-negative, so every
+      // partial sum of a sample is below 2^16 too. Two samples then share a
+      // 32-bit word (one in each half) and one add serves both, with no
+      // carry between the halves: pk[m] holds the lane's samples 2m (low
+      // half) and 2m + 1 (high half), which is their uint16 layout.
+      uint32_t pk[S / 2];
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if constexpr (FROM_INPUT) {
-        // chain element i (sample t - shift - i) starts mis + chain - i bytes in
-        for (int i = 0; i <= chain[j]; ++i) {
-          const int o = mis[j] + chain[j] - i;
-          const int k = o >> 2;
+      for (int m = 0; m < S / 2; ++m) pk[m] = 0;
 #pragma unroll
-          for (int q4 = 0; q4 < CV; ++q4) {
-            const uint32_t lo = k ? w[j][q4 + 1] : w[j][q4];
-            const uint32_t hi = k ? w[j][q4 + 2] : w[j][q4 + 1];
-            const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+      for (int j = 0; j < N; ++j) {
+        if constexpr (FROM_INPUT) {
+          // bytes 0 and 2 of a word add into one word, bytes 1 and 3 into another
+          for (int i = 0; i <= chain[j]; ++i) {
+            const int o = mis[j] + chain[j] - i;
+            const int k = o >> 2;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[4 * q4 + q] += (x >> (8 * q)) & 0xffu;
+            for (int q4 = 0; q4 < CV; ++q4) {
+              const uint32_t lo = k ? w[j][q4 + 1] : w[j][q4];
+              const uint32_t hi = k ? w[j][q4 + 2] : w[j][q4 + 1];
+              const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+              pk[2 * q4] += x & 0x00ff00ffu;             // samples 4 q4 and 4 q4 + 2
+              pk[2 * q4 + 1] += (x >> 8) & 0x00ff00ffu;  // samples 4 q4 + 1 and 4 q4 + 3
+            }
           }
+        } else {
+#pragma unroll
+          for (int m = 0; m < S / 2; ++m) pk[m] += __builtin_amdgcn_alignbyte(w[j][m + 1], w[j][m], mis[j]);
         }
+      }
+      if constexpr (FROM_INPUT) {
+        // (even, odd) word pairs to sample order: bytes 0-1 of the even word
+        // and 0-1 of the odd word, then bytes 2-3 of each
+#pragma unroll
+        for (int q4 = 0; q4 < CV; ++q4) {
+          const uint32_t ev = pk[2 * q4], od = pk[2 * q4 + 1];
+          pk[2 * q4] = __builtin_amdgcn_perm(od, ev, 0x05040100u);
+          pk[2 * q4 + 1] = __builtin_amdgcn_perm(od, ev, 0x07060302u);
+        }
+      }
+      Tdst *o = dst + bs.dst_off + r * bs.dst_stride + t;
+      if (t + S <= nt) {
+        // 2 S bytes at an offset that is a multiple of 2 S
+        typedef uint32_t P __attribute__((ext_vector_type(S / 2), aligned(4)));
+        P v;
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) v[m] = pk[m];
+        *reinterpret_cast<P *>(o) = v;
       } else {
 #pragma unroll
-        for (int m = 0; m < S / 2; ++m) {
-          const uint32_t x = __builtin_amdgcn_alignbyte(w[j][m + 1], w[j][m], mis[j]);
-          acc[2 * m] += x & 0xffffu;
-          acc[2 * m + 1] += x >> 16;
+        for (int q = 0; q < S; ++q)
+          if (t + q < nt) o[q] = static_cast<Tdst>(q & 1 ? pk[q / 2] >> 16 : pk[q / 2] & 0xffffu);
+      }
+      return;
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if constexpr (FROM_INPUT) {
+          // chain element i (sample t - shift - i) starts mis + chain - i bytes in
+          for (int i = 0; i <= chain[j]; ++i) {
+            const int o = mis[j] + chain[j] - i;
+            const int k = o >> 2;
+#pragma unroll
+            for (int q4 = 0; q4 < CV; ++q4) {
+              const uint32_t lo = k ? w[j][q4 + 1] : w[j][q4];
+              const uint32_t hi = k ? w[j][q4 + 2] : w[j][q4 + 1];
+              const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[4 * q4 + q] += (x >> (8 * q)) & 0xffu;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < S / 2; ++m) {
+            const uint32_t x = __builtin_amdgcn_alignbyte(w[j][m + 1], w[j][m], mis[j]);
+            acc[2 * m] += x & 0xffffu;
+            acc[2 * m + 1] += x >> 16;
+          }
         }
       }
     }
