@@ -123,7 +123,7 @@ typedef struct {
                              forward gathers take at most 2, and 1 in passes of four
                              iterations (0 = default 1) */
   int32_t adjoint_last_rows; /* output rows (channels) per workgroup of the last adjoint
-                                pass: 1, 2, 4, 8 or 16 (0 = gather_rows). Channels of one
+                                pass: 1, 2, 4, 8 or 16 (0 = adjoint_rows). Channels of one
                                 sub-band read the same rows, so a workgroup of one whole
                                 sub-band reads them through one L1 */
   double gamma;           /* delay law dt ~ f^gamma (Sec. 4.2, other functional forms: the
@@ -149,7 +149,7 @@ typedef struct {
                               row; smaller workgroups let a CU start new work as single
                               waves finish */
   int32_t adjoint_threads; /* the same for the adjoint gathers into planes, at least
-                              64 * gather_rows (0 = default 1024) */
+                              64 * adjoint_rows (0 = default 1024) */
   int32_t adjoint_last_threads; /* the same for the last adjoint pass (into the channels), at
                                    least 64 times its rows per workgroup (0 = adjoint_threads) */
   int32_t rule;           /* delay-table rule (Sec. 4.2, rounding and binning): 0 = one C per
@@ -165,6 +165,15 @@ typedef struct {
                              workgroup's output tile in LDS, with that many rows per
                              workgroup and tiles of 2048 samples. Same results either way;
                              after the transform is the faster on MI355X at Nf = 4096 */
+  int32_t first_rows;     /* output rows per workgroup of a first pass that gathers from the
+                             input: 1, 2, 4, 8 or 16 (0 = gather_rows) */
+  int32_t first_threads;  /* its workgroup size: 64 .. 1024, a power of two, at least
+                             64 * its rows (0 = gather_threads). The first pass reads
+                             input channels and the later ones planes, so their best
+                             shapes differ */
+  int32_t adjoint_rows;   /* output rows per workgroup of the adjoint gathers into planes:
+                             1, 2, 4, 8 or 16 (0 = gather_rows); adjoint_threads must be at
+                             least 64 times it */
 } fdmt_options_t;
 
 /* Build a plan: the delay tables of every iteration (Sec. 4: the rows each

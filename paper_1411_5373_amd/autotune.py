@@ -2,11 +2,13 @@
 fastest per workload in a JSON cache that `Plan(..., tuned=True)` consults.
 
 Every candidate is a set of `fdmt_options_t` schedule fields (kernel form and
-iterations of each pass, tile width, LDS budget, rows and samples per gather
-workgroup, adjoint pass depths). Schedule fields never change results, only
-speed, so the tuner compares times alone. Forward and adjoint are tuned
-separately; the fields they share (the gather workgroup shape) are chosen to
-minimise their sum.
+iterations of each pass, tile width, LDS budget, rows, threads and samples per
+gather workgroup, adjoint pass depths). Schedule fields never change results,
+only speed, so the tuner compares times alone. Forward and adjoint are tuned
+separately: the forward's pass structure first, at one workgroup shape, then
+the workgroup shapes of its first and later passes; the adjoint's depths,
+last-pass shape and work order for each row count. The one field they share
+(samples per lane) is chosen to minimise their sum.
 
 Cache key: GPU architecture, Nf, Nd, band, the delay law's power when it is
 not -2, input and accumulation dtypes and Nt rounded up to a power of two.
@@ -36,14 +38,35 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 
 GATHER_ROWS = (4, 8)
 GATHER_VECS = (1, 2, 4)
+GATHER_THREADS = (512, 1024)
+# (first_rows, first_threads) of a first pass that gathers from the input;
+# (0, 0) = the later passes' shape
+FIRST_SHAPES = ((0, 0), (2, 512), (4, 512))
 GATHER_ROWS_DEFAULT = 8  # the library's gather_rows when the option is 0
 
 # Fields that shape only the forward or only the adjoint schedule.
 FORWARD_FIELDS = ("first_kernel", "first_levels", "later_kernel", "later_levels", "tile", "lds_kib",
-                  "max_block_rows", "stream_tiles")
+                  "max_block_rows", "stream_tiles", "gather_rows", "gather_threads", "first_rows",
+                  "first_threads")
 ADJOINT_FIELDS = ("adjoint_levels", "adjoint_last_levels", "adjoint_last_rows", "adjoint_tile_major",
-                  "adjoint_last_threads")
-SHARED_FIELDS = ("gather_rows", "gather_vecs")
+                  "adjoint_last_threads", "adjoint_rows")
+SHARED_FIELDS = ("gather_vecs",)
+
+
+def forward_shapes():
+    """Workgroup shapes of the forward gathers: rows and threads of the later
+    passes, rows and threads of a first pass from the input (0: the same)."""
+    out = []
+    for rows in GATHER_ROWS:
+        for threads in GATHER_THREADS:
+            if 64 * rows > threads:
+                continue
+            for first_rows, first_threads in FIRST_SHAPES:
+                shape = dict(gather_rows=rows, gather_threads=threads)
+                if first_rows:
+                    shape.update(first_rows=first_rows, first_threads=first_threads)
+                out.append(shape)
+    return out
 
 
 def forward_candidates():
@@ -67,13 +90,13 @@ def forward_candidates():
 TILE_MAJOR_MASKS = ("none", "ends", "all")
 
 
-def adjoint_candidates(gather_rows=GATHER_ROWS_DEFAULT):
-    """Adjoint pass depths, channels per workgroup of the last pass (the shared
-    gather shape, or a whole sub-band per workgroup), the last pass's
-    workgroup size (1024 threads, or 256 with at most 4 channels) and work
-    order."""
-    last_rows = [0] + [r for r in (8, 16) if r > gather_rows]
-    small = [r for r in ([0] if gather_rows <= 4 else []) + [2, 4] if r != gather_rows]
+def adjoint_candidates(rows=GATHER_ROWS_DEFAULT):
+    """Adjoint pass depths, channels per workgroup of the last pass (the
+    `rows` of the adjoint gathers into planes, or a whole sub-band per
+    workgroup), the last pass's workgroup size (1024 threads, or 256 with at
+    most 4 channels) and work order."""
+    last_rows = [0] + [r for r in (8, 16) if r > rows]
+    small = [r for r in ([0] if rows <= 4 else []) + [2, 4] if r != rows]
     shapes = [(r, 0) for r in last_rows] + [(r, 256) for r in small]
     out = []
     for a in (1, 2, 3):
@@ -203,50 +226,63 @@ def tune(nf, nt, nd, f_min, f_max, in_dtype=torch.float32, acc_dtype=torch.float
 
     tried = []
     best = {}
-    for rows, vecs in [(r, v) for r in GATHER_ROWS for v in GATHER_VECS]:
-        shared = dict(gather_rows=rows, gather_vecs=vecs)
+
+    def timed(direction, opts, make):
+        try:
+            p = make(**opts)
+            fn = runner(p, direction == "adjoint")
+        except B.FDMTError:
+            return None  # this schedule does not fit the shape (or the ragged form)
+        ms = _time(fn, reps)
+        tried.append({"direction": direction, "options": opts, "ms": round(ms, 4)})
+        if verbose:
+            print(f"{direction} {opts}: {ms:.4f} ms", flush=True)
+        return ms
+
+    def make_fwd(**o):
+        return B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, gamma=gamma, **o)
+
+    def make_adj(**o):
+        return B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma, **o)
+
+    for vecs in GATHER_VECS:
+        # forward: the pass structure at one workgroup shape, then the shapes
         fwd_best, adj_best = None, None
         for cand in forward_candidates():
-            opts = dict(cand, **shared)
-            try:
-                p = B.Plan(nf, nt, nd, f_min, f_max, in_dtype=in_dtype, acc_dtype=acc_dtype, gamma=gamma, **opts)
-                fn = runner(p, False)
-            except B.FDMTError:
-                continue  # this schedule does not fit the shape (or the ragged form)
-            ms = _time(fn, reps)
-            tried.append({"direction": "forward", "options": opts, "ms": round(ms, 4)})
-            if verbose:
-                print(f"forward {opts}: {ms:.4f} ms", flush=True)
-            if fwd_best is None or ms < fwd_best[0]:
-                fwd_best = (ms, cand)
-            del p, fn
-        for cand in adjoint_candidates(rows):
-            if lengths and cand["adjoint_tile_major"] != "none":
-                continue  # ragged launches take their work order from the tile maps
-            try:
-                def make(**o):
-                    return B.Plan(nf, nt, nd, f_min, f_max, in_dtype=acc_dtype, acc_dtype=acc_dtype, gamma=gamma,
-                                  **o, **shared)
-                cand = resolve_order(cand, make)
-                if cand is None:
+            opts = dict(cand, gather_vecs=vecs, gather_rows=GATHER_ROWS[0])
+            ms = timed("forward", opts, make_fwd)
+            if ms is not None and (fwd_best is None or ms < fwd_best[0]):
+                fwd_best = (ms, opts)
+        if fwd_best is not None:
+            structure = {k: v for k, v in fwd_best[1].items() if k not in ("gather_rows", "gather_threads")}
+            for shape in forward_shapes():
+                opts = dict(structure, **shape)
+                if opts == fwd_best[1]:
                     continue
-                opts = dict(cand, **shared)
-                p = make(**cand)
-                fn = runner(p, True)
-            except B.FDMTError:
-                continue
-            ms = _time(fn, reps)
-            tried.append({"direction": "adjoint", "options": opts, "ms": round(ms, 4)})
-            if verbose:
-                print(f"adjoint {opts}: {ms:.4f} ms", flush=True)
-            if adj_best is None or ms < adj_best[0]:
-                adj_best = (ms, cand)
-            del p, fn
+                ms = timed("forward", opts, make_fwd)
+                if ms is not None and ms < fwd_best[0]:
+                    fwd_best = (ms, opts)
+        # adjoint: depths, last-pass shape and work order per row count
+        for rows in GATHER_ROWS:
+            for cand in adjoint_candidates(rows):
+                if lengths and cand["adjoint_tile_major"] != "none":
+                    continue  # ragged launches take their work order from the tile maps
+                shared = dict(gather_vecs=vecs, adjoint_rows=rows)
+                try:
+                    c = resolve_order(cand, lambda **o: make_adj(**o, **shared))
+                except B.FDMTError:
+                    continue
+                if c is None:
+                    continue
+                opts = dict(c, **shared)
+                ms = timed("adjoint", opts, make_adj)
+                if ms is not None and (adj_best is None or ms < adj_best[0]):
+                    adj_best = (ms, opts)
         if fwd_best is None or adj_best is None:
             continue
         total = fwd_best[0] + adj_best[0]
         if not best or total < best["forward_ms"] + best["adjoint_ms"]:
-            best = {"options": dict(fwd_best[1], **adj_best[1], **shared),
+            best = {"options": dict(fwd_best[1], **adj_best[1]),
                     "forward_ms": round(fwd_best[0], 4), "adjoint_ms": round(adj_best[0], 4)}
     if not best:
         raise RuntimeError("no candidate schedule fits this workload")

@@ -59,7 +59,9 @@ class _Options(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("d_min", ctypes.c_int32),
                 ("adjoint_tile_major", ctypes.c_uint32), ("gather_threads", ctypes.c_int32),
                 ("adjoint_threads", ctypes.c_int32), ("adjoint_last_threads", ctypes.c_int32),
-                ("rule", ctypes.c_int32), ("search_rows", ctypes.c_int32)]
+                ("rule", ctypes.c_int32), ("search_rows", ctypes.c_int32),
+                ("first_rows", ctypes.c_int32), ("first_threads", ctypes.c_int32),
+                ("adjoint_rows", ctypes.c_int32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -172,7 +174,7 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
               first_kernel=0, later_kernel=0, stream_tiles=0, gather_rows=0, adjoint_levels=0,
               adjoint_last_levels=0, gather_vecs=0, adjoint_last_rows=0, gamma=0.0, d_min=0,
               adjoint_tile_major=0, gather_threads=0, adjoint_threads=0, adjoint_last_threads=0, rule=0,
-              search_rows=0):
+              search_rows=0, first_rows=0, first_threads=0, adjoint_rows=0):
     """Returns an opaque plan handle (int); raises FDMTError on failure."""
     h = ctypes.c_void_p()
     opt = _Options(int(in_dtype), int(acc_dtype), int(flags), int(first_levels),
@@ -181,7 +183,7 @@ def fdmt_plan(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, f
                    int(adjoint_levels), int(adjoint_last_levels), int(gather_vecs),
                    int(adjoint_last_rows), float(gamma), int(d_min), int(adjoint_tile_major),
                    int(gather_threads), int(adjoint_threads), int(adjoint_last_threads), int(rule),
-                   int(search_rows))
+                   int(search_rows), int(first_rows), int(first_threads), int(adjoint_rows))
     _check(load().fdmt_plan(ctypes.byref(h), int(nf), int(nt), int(nd), float(f_min), float(f_max),
                             ctypes.byref(opt)), "fdmt_plan")
     return h.value
@@ -204,7 +206,7 @@ def copy_bytes(dst, src):
 SCHEDULE_FIELDS = ("first_levels", "later_levels", "tile", "lds_kib", "max_block_rows", "first_kernel",
                    "later_kernel", "stream_tiles", "gather_rows", "adjoint_levels", "adjoint_last_levels",
                    "gather_vecs", "adjoint_last_rows", "adjoint_tile_major", "gather_threads", "adjoint_threads",
-                   "adjoint_last_threads", "search_rows")
+                   "adjoint_last_threads", "search_rows", "first_rows", "first_threads", "adjoint_rows")
 
 
 def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FDMT_F32, gamma=0.0, d_min=0,
@@ -212,7 +214,8 @@ def fdmt_tuned_options(nf, nt, nd, f_min, f_max, in_dtype=FDMT_F32, acc_dtype=FD
     """The autotuner's schedule for this workload through the C ABI: a dict of
     the schedule fields the cache sets (explicit nonzero fields kept as given),
     or None when the cache has no entry."""
-    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0, 0, 0, 0, int(rule), 0)
+    opt = _Options(int(in_dtype), int(acc_dtype), 0, *([0] * 13), float(gamma), int(d_min), 0, 0, 0, 0, int(rule), 0,
+                   0, 0, 0)
     for k, v in explicit.items():
         setattr(opt, k, int(v))
     found = ctypes.c_int32()

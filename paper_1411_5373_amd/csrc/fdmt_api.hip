@@ -212,19 +212,23 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
     return fail(FDMT_E_INVALID, "adjoint_levels must be in [1, 5], adjoint_last_levels in [1, 4]");
   if (o.gather_vecs < 0 || o.gather_vecs > 4 || o.gather_vecs == 3)
     return fail(FDMT_E_INVALID, "gather_vecs must be 1, 2 or 4");
-  if (o.adjoint_last_rows < 0 || o.adjoint_last_rows > 16 || (o.adjoint_last_rows & (o.adjoint_last_rows - 1)))
-    return fail(FDMT_E_INVALID, "adjoint_last_rows must be 1, 2, 4, 8 or 16");
-  for (int32_t th : {o.gather_threads, o.adjoint_threads, o.adjoint_last_threads})
+  for (int32_t rw : {o.adjoint_last_rows, o.first_rows, o.adjoint_rows})
+    if (rw < 0 || rw > 16 || (rw & (rw - 1)))
+      return fail(FDMT_E_INVALID, "adjoint_last_rows, first_rows and adjoint_rows must be 1, 2, 4, 8 or 16");
+  for (int32_t th : {o.gather_threads, o.adjoint_threads, o.adjoint_last_threads, o.first_threads})
     if (th < 0 || th > 1024 || (th && (th < 64 || (th & (th - 1)))))
-      return fail(FDMT_E_INVALID, "gather_threads, adjoint_threads and adjoint_last_threads must be 64, 128, 256, "
-                                  "512 or 1024");
+      return fail(FDMT_E_INVALID, "gather_threads, adjoint_threads, adjoint_last_threads and first_threads must be "
+                                  "64, 128, 256, 512 or 1024");
   {
     const int rows = o.gather_rows ? o.gather_rows : 8;
-    const int last_rows = o.adjoint_last_rows ? o.adjoint_last_rows : rows;
+    const int threads = o.gather_threads ? o.gather_threads : 1024;
+    const int adj_rows = o.adjoint_rows ? o.adjoint_rows : rows;
+    const int last_rows = o.adjoint_last_rows ? o.adjoint_last_rows : adj_rows;
     const int adj = o.adjoint_threads ? o.adjoint_threads : 1024;
-    if (64 * rows > (o.gather_threads ? o.gather_threads : 1024))
-      return fail(FDMT_E_INVALID, "gather_threads must be at least 64 * gather_rows");
-    if (64 * rows > adj) return fail(FDMT_E_INVALID, "adjoint_threads must be at least 64 * gather_rows");
+    if (64 * rows > threads) return fail(FDMT_E_INVALID, "gather_threads must be at least 64 * gather_rows");
+    if (64 * (o.first_rows ? o.first_rows : rows) > (o.first_threads ? o.first_threads : threads))
+      return fail(FDMT_E_INVALID, "the first pass's workgroup must hold at least 64 * its rows threads");
+    if (64 * adj_rows > adj) return fail(FDMT_E_INVALID, "adjoint_threads must be at least 64 * adjoint_rows");
     if (64 * last_rows > (o.adjoint_last_threads ? o.adjoint_last_threads : adj))
       return fail(FDMT_E_INVALID, "the last adjoint pass's workgroup must hold at least 64 * its rows threads");
   }
@@ -272,6 +276,9 @@ fdmt_status_t fdmt_plan(fdmt_plan_t *out, int32_t nf, int64_t nt, int32_t nd, do
   p.adjoint_last_threads = o.adjoint_last_threads;
   if (o.search_rows) p.search_rows = o.search_rows;
   p.adjoint_last_rows = o.adjoint_last_rows;
+  p.first_rows = o.first_rows;
+  p.first_threads = o.first_threads;
+  p.adjoint_rows = o.adjoint_rows;
   p.adjoint_tile_major = o.adjoint_tile_major;
   for (int64_t r : p.tab.total) p.rmax = r > p.rmax ? r : p.rmax;
   if (!(o.flags & FDMT_PLAN_UNFUSED)) {
@@ -489,8 +496,8 @@ fdmt_status_t fdmt_step_info(fdmt_plan_t p, int32_t adjoint, int32_t step, fdmt_
       info->level_first = ps.from_input ? 0 : ps.l0 + 1;
       info->level_last = ps.l1;
       const int64_t gt = fdmt::step_tile(P, false, step);  // samples per gather workgroup
-      info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + P.gather_rows - 1) / P.gather_rows) *
-                                                          ((nt + gt - 1) / gt))
+      const int rows = fdmt::forward_rows(P, ps);
+      info->work_items = ps.gather ? static_cast<int32_t>(((ps.nblocks + rows - 1) / rows) * ((nt + gt - 1) / gt))
                                    : static_cast<int32_t>(
                                          ps.nblocks *
                                          ((nt + ps.tile - 1) / ps.tile +
@@ -941,7 +948,10 @@ fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32
                           {"gather_threads", &opt->gather_threads, nullptr},
                           {"adjoint_threads", &opt->adjoint_threads, nullptr},
                           {"adjoint_last_threads", &opt->adjoint_last_threads, nullptr},
-                          {"search_rows", &opt->search_rows, nullptr}};
+                          {"search_rows", &opt->search_rows, nullptr},
+                          {"first_rows", &opt->first_rows, nullptr},
+                          {"first_threads", &opt->first_threads, nullptr},
+                          {"adjoint_rows", &opt->adjoint_rows, nullptr}};
   for (const auto &kv : o) {
     const Field *f = nullptr;
     for (const Field &c : fields)

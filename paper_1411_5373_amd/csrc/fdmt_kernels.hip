@@ -740,9 +740,9 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
       if (ps.gather && ps.from_input) {
         const int k = ps.l1 - ps.l0;
         if (k < 1 || k > 4) return hipErrorInvalidValue;
-        const int rpw = p.gather_rows;
+        const int rpw = forward_rows(p, ps);
         const int cv = forward_vecs(p, ps);
-        const int tile = 256 * cv * (p.gather_threads / 64 / rpw);
+        const int tile = 256 * cv * (forward_threads(p, ps) / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
         const int32_t nt32 = static_cast<int32_t>(nt);
         const int4 *tm = p.dev_iterms + ps.term_offset;
@@ -751,7 +751,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         const bool int_sums = p.int_sums[st.index];
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
-          g.threads = p.gather_threads;
+          g.threads = forward_threads(p, ps);
           if constexpr (std::is_same<Tin, uint8_t>::value) {
             if (narrow_out)  // exact integer sums below 2^16
               return launch_narrow_input_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
@@ -769,8 +769,8 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         if (k < 1 || k > 4) return hipErrorInvalidValue;
         // rows per workgroup (1, 2, 4, 8 or 16) and workgroup size; a pass
         // that runs the search may take its own
-        const int rpw = search && search->rows ? search->rows : p.gather_rows;
-        const int threads = search && search->threads ? search->threads : p.gather_threads;
+        const int rpw = search && search->rows ? search->rows : forward_rows(p, ps);
+        const int threads = search && search->threads ? search->threads : forward_threads(p, ps);
         const int cv = forward_vecs(p, ps);  // runs of 4 samples per lane: 1 or 2
         const int tile = 256 * cv * (threads / 64 / rpw);
         const unsigned gx = static_cast<unsigned>((ps.nblocks + rpw - 1) / rpw);
@@ -1122,7 +1122,16 @@ hipError_t launch_adjoint(const Plan &p, const void *gout, void *gin, int batch,
 }
 
 int adjoint_rows(const Plan &p, int pass) {
-  return p.adj.passes[pass].to_input && p.adjoint_last_rows ? p.adjoint_last_rows : p.gather_rows;
+  const int rows = p.adjoint_rows ? p.adjoint_rows : p.gather_rows;
+  return p.adj.passes[pass].to_input && p.adjoint_last_rows ? p.adjoint_last_rows : rows;
+}
+
+int forward_rows(const Plan &p, const Pass &ps) {
+  return ps.from_input && p.first_rows ? p.first_rows : p.gather_rows;
+}
+
+int forward_threads(const Plan &p, const Pass &ps) {
+  return ps.from_input && p.first_threads ? p.first_threads : p.gather_threads;
 }
 
 int adjoint_threads(const Plan &p, int pass) {
@@ -1143,7 +1152,8 @@ int step_tile(const Plan &p, bool adjoint, int i) {
     case Step::Fused: {
       const Pass &ps = p.fwd.passes[st.index];
       if (ps.kind == PassKind::Staged) return 0;
-      return ps.gather ? 256 * forward_vecs(p, ps) * (p.gather_threads / 64 / p.gather_rows) : ps.tile * p.rec_tiles;
+      return ps.gather ? 256 * forward_vecs(p, ps) * (forward_threads(p, ps) / 64 / forward_rows(p, ps))
+                       : ps.tile * p.rec_tiles;
     }
   }
   return 0;

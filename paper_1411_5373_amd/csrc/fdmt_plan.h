@@ -71,7 +71,10 @@ struct Plan {
   int adjoint_last_threads = 0;  // ... of the last adjoint pass (0: adjoint_threads)
   int search_rows = 0;         // rows per workgroup of the last forward pass when it runs the
                                // search (0: the search runs after the transform)
-  int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: gather_rows)
+  int adjoint_last_rows = 0;   // channels per workgroup of the last adjoint pass (0: adjoint rows)
+  int first_rows = 0;          // rows per workgroup of a first pass gathering from the input (0: gather_rows)
+  int first_threads = 0;       // ... its workgroup size (0: gather_threads)
+  int adjoint_rows = 0;        // rows per workgroup of the adjoint gathers into planes (0: gather_rows)
   uint32_t adjoint_tile_major = 0;  // bit i: adjoint pass i runs each row group's tiles back to back
   const int2 *dev_sterms = nullptr;
   const int32_t *dev_sheads = nullptr;
@@ -121,6 +124,9 @@ hipError_t launch_forward_search(const Plan &p, const void *in, float *out, int 
 int step_tile(const Plan &p, bool adjoint, int step);
 // Output rows per workgroup of adjoint register-gather pass `pass`.
 int adjoint_rows(const Plan &p, int pass);
+// Output rows and workgroup size of forward register-gather pass `ps`.
+int forward_rows(const Plan &p, const Pass &ps);
+int forward_threads(const Plan &p, const Pass &ps);
 // Workgroup size of adjoint register-gather pass `pass`.
 int adjoint_threads(const Plan &p, int pass);
 size_t workspace_bytes(const Plan &p, int batch);

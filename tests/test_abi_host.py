@@ -343,6 +343,38 @@ def test_adjoint_last_rows_shapes_only_the_last_pass():
         assert e.value.status == B.FDMT_E_INVALID
 
 
+def test_first_pass_and_adjoint_shapes():
+    """first_rows / first_threads shape only a first pass that gathers from the
+    input, adjoint_rows only the adjoint gathers into planes: work items follow,
+    every other step keeps its shape, and invalid shapes are refused."""
+    nf, nt, nd = 4096, 65536, 2048
+    kw = dict(first_kernel=3, first_levels=3, later_levels=3, gather_rows=8, gather_threads=512, gather_vecs=2)
+    base = F.Plan(nf, nt, nd, 1.2, 1.6, host_only=True, **kw)
+    shaped = F.Plan(nf, nt, nd, 1.2, 1.6, host_only=True, first_rows=2, first_threads=512, adjoint_rows=4, **kw)
+    f0, f1 = base.steps(), shaped.steps()
+    assert f0[0]["kind"] == f1[0]["kind"] == B.STEP_KINDS[6] and f0[0]["level_last"] == 3
+    rows0 = f0[0]["bytes_written"] // f0[0]["out_elem_bytes"] // nt
+    # 8 rows x 512 threads: one wave per row, 512-sample tiles; 2 rows: 4 waves per row, 2048 samples
+    assert f0[0]["work_items"] == -(-rows0 // 8) * (nt // 512)
+    assert f1[0]["work_items"] == -(-rows0 // 2) * (nt // 2048)
+    for s0, s1 in zip(f0[1:], f1[1:]):
+        assert s0["work_items"] == s1["work_items"]
+    # adjoint gathers into planes: two 4-sample runs per lane, 1024 threads, so
+    # (16 / rows) waves of 512 samples per row
+    for steps, r in ((base.steps(adjoint=True), 8), (shaped.steps(adjoint=True), 4)):
+        gathers = [st for st in steps[:-1] if st["kind"] == B.STEP_KINDS[8]]
+        assert gathers
+        for st in gathers:
+            n = st["bytes_written"] // (4 * nt)
+            assert st["work_items"] == -(-n // r) * -(-nt // (512 * 16 // r))
+    for bad in (dict(first_rows=3), dict(first_rows=32), dict(adjoint_rows=-1), dict(first_threads=100),
+                dict(first_threads=2048), dict(first_rows=16, first_threads=512),
+                dict(adjoint_rows=16, adjoint_threads=512)):
+        with pytest.raises(F.FDMTError) as e:
+            F.Plan(64, 1000, 64, 1.2, 1.6, host_only=True, **bad)
+        assert e.value.status == B.FDMT_E_INVALID, bad
+
+
 def test_uint8_plans_store_exact_uint16_planes():
     """Planes between two cache gathers of a uint8-input plan are uint16 while
     255 * (2^l + rows - 1) < 2^16 (plane l sums at most 2^l + dt samples)."""

@@ -371,6 +371,12 @@ SCHEDULES = [
     dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4, gather_threads=256),
     dict(first_levels=2, later_levels=3, first_kernel=3, gather_rows=1, gather_threads=64),
     dict(first_levels=4, later_levels=2, first_kernel=2, gather_rows=2, gather_threads=512),
+    # the first pass from the input with its own workgroup shape
+    dict(first_levels=3, later_levels=3, first_kernel=3, gather_vecs=2, gather_rows=8, gather_threads=512,
+         first_rows=2, first_threads=512),
+    dict(first_levels=2, later_levels=3, first_kernel=3, gather_rows=4, first_rows=16, first_threads=1024),
+    dict(first_levels=3, later_levels=2, first_kernel=3, gather_vecs=2, gather_rows=2, gather_threads=128,
+         first_rows=1, first_threads=64),
 ]
 
 
@@ -488,6 +494,10 @@ ADJOINT_SCHEDULES = [
          adjoint_last_threads=256, adjoint_tile_major=0b1001),
     dict(adjoint_levels=2, adjoint_last_levels=3, gather_rows=8, gather_vecs=1, adjoint_last_rows=2,
          adjoint_last_threads=128),
+    # adjoint rows per workgroup apart from the forward's
+    dict(adjoint_levels=3, adjoint_last_levels=3, gather_rows=8, adjoint_rows=4, gather_vecs=4,
+         adjoint_last_threads=256, adjoint_tile_major=0b1001),
+    dict(adjoint_levels=2, adjoint_last_levels=2, gather_rows=2, adjoint_rows=16, gather_vecs=2),
 ]
 
 

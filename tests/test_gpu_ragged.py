@@ -116,7 +116,9 @@ def test_ragged_adjoint_bitwise(nf, nd, band, unfused):
                                    dict(first_levels=3, first_kernel=3, gather_vecs=2, gather_rows=4),
                                    dict(first_levels=3, first_kernel=3, gather_vecs=4, gather_rows=8),
                                    dict(gather_vecs=4, gather_rows=4, adjoint_levels=3, adjoint_last_levels=3,
-                                        adjoint_last_rows=16)])
+                                        adjoint_last_rows=16),
+                                   dict(first_levels=3, first_kernel=3, gather_vecs=2, gather_rows=8,
+                                        gather_threads=512, first_rows=2, first_threads=512, adjoint_rows=4)])
 @pytest.mark.parametrize("nf,nd,band", [(256, 128, (1.2, 1.6)), (8, 300, (0.4, 0.8))])
 def test_ragged_other_kernel_forms(sched, nf, nd, band):
     """Other pass kernels: ragged forward and adjoint bit-identical to the oracle per beam."""
