@@ -131,14 +131,20 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
   typedef typename Vec4<Tacc>::type V;
   typedef Reg4<Tacc> R;
   constexpr int kChunk = adjoint_chunk(CV);
+  static_assert(2 * kChunk <= kAdjLeafPad, "leaf records are read up to two chunks past a list");
+  // A chunk's leaf records are one scalar load, issued a chunk ahead (records
+  // past the list are read, not used: the list is padded)
+  struct Chunk {
+    int4 e[kChunk];
+  };
+  Chunk cur = *reinterpret_cast<const Chunk *>(leaves + x0);
   for (int x = x0; x < x1; x += kChunk) {
     const int n = x1 - x < kChunk ? x1 - x : kChunk;
-    int4 e[kChunk];
+    const int4 *e = cur.e;
     R v[kChunk][CV];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
       if (j < n) {
-        e[j] = leaves[x + j];
         const Tacc *row = base + e[j].x * stride;
 #pragma unroll
         for (int c = 0; c < CV; ++c) {
@@ -152,9 +158,11 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
         }
       }
     }
+    const Chunk next = *reinterpret_cast<const Chunk *>(leaves + x + kChunk);
 #pragma unroll
     for (int j = 0; j < kChunk; ++j)
       if (j < n) sums.add(v[j], e[j].z, x + j == x0);
+    cur = next;
   }
 }
 

@@ -71,7 +71,7 @@ fdmt_status_t upload(fdmt::Plan &p) {
   const size_t off_iterms = reserve(p.fwd.iterms.size() * sizeof(fdmt::InTerm));
   const size_t off_stage = reserve(p.fwd.stage.size() * sizeof(fdmt::Rec));
   const size_t off_psums = reserve(p.fwd.psums.size() * sizeof(fdmt::Rec));
-  const size_t off_adj_leaves = reserve(p.adj.leaves.size() * sizeof(fdmt::AdjLeaf));
+  const size_t off_adj_leaves = reserve((p.adj.leaves.size() + fdmt::kAdjLeafPad) * sizeof(fdmt::AdjLeaf));
   const size_t off_adj_starts = reserve(p.adj.starts.size() * sizeof(int32_t));
   const size_t off_adj_order = reserve(p.adj.order.size() * sizeof(int32_t));
   const size_t off_sterms = reserve(p.fwd.sterms.size() * sizeof(fdmt::StagedTerm));

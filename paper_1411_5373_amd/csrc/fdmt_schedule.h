@@ -148,6 +148,9 @@ struct AdjLeaf {
   int32_t row, shift, branch;
   int32_t lags;  // lagged pass, a subtree's first leaf: its lags | its leaf count << 3; else 0
 };
+// Leaf records readable past the end of the list (zeros): the adjoint gather
+// loads the records of its next chunk before it knows whether there is one.
+constexpr int kAdjLeafPad = 16;
 
 struct AdjPass {
   int l_hi = 0, l_lo = 0;
