@@ -302,9 +302,9 @@ fdmt_status_t fdmt_plan_destroy(fdmt_plan_t p);
  * Each step is an ordinary launch over the flattened (beam, time tile) map,
  * not a persistent work-queue kernel: on MI355X, for 256 beams of Nf = 1024,
  * Nd = 512 and 3.1 M samples in all, the gaps between a forward's four
- * launches add about 0.01 ms to its 15 ms, and two half batches cost about as
- * much as one call, so a single resident kernel could save at most about
- * 0.1% while adding spin waits between passes.
+ * launches add about 0.01 ms to its 14 ms, and two half batches cost at most
+ * 0.05 ms more than one call, so a single resident kernel could save well
+ * under 1% while adding spin waits between passes.
  *
  * fdmt_ragged_plan errors: FDMT_E_INVALID (NULL pointer, nbeams < 1, an nt[b]
  * outside [0, 2^31 - 1], device mismatch), FDMT_E_UNSUPPORTED (host-only plan,
