@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
-  if (!RAGGED) bs.tile = item.y;
+  if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int t_wave = (bs.tile * col_waves + wave % col_waves) * kSpan;
   const int t = t_wave + lane * 4;

@@ -28,10 +28,12 @@ struct RaggedMap {
   const int2 *tiles;  // per tile of the launch: {beam, tile within the beam}
   int32_t src_rows, dst_rows;      // rows per beam of the source / destination buffer
   int32_t src_padded, dst_padded;  // 1: workspace plane (row stride = padded nt)
+  int32_t reverse;                 // uniform launches: run the time tiles last to first
 };
 
 struct BeamSpan {
   int nt, tile;                    // samples of the beam; tile index within the beam
+  int beam;                        // uniform batches: the beam (grid z, reversed with the tiles)
   int64_t src_off, dst_off;        // element offsets of the beam in src / dst
   int64_t src_stride, dst_stride;  // row strides (elements)
 };
@@ -46,6 +48,7 @@ __device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64
     const int4 bm = rg.beam[tb.x];
     b.nt = bm.x;
     b.tile = tb.y;
+    b.beam = 0;
     b.src_off = static_cast<int64_t>(rg.src_rows) * (rg.src_padded ? bm.w : bm.z);
     b.dst_off = static_cast<int64_t>(rg.dst_rows) * (rg.dst_padded ? bm.w : bm.z);
     b.src_stride = rg.src_padded ? bm.y : bm.x;
@@ -53,8 +56,9 @@ __device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64
   } else {
     b.nt = nt;
     b.tile = blockIdx.y;
-    b.src_off = blockIdx.z * src_bstride;
-    b.dst_off = blockIdx.z * dst_bstride;
+    b.beam = rg.reverse ? static_cast<int>(gridDim.z - 1 - blockIdx.z) : static_cast<int>(blockIdx.z);
+    b.src_off = b.beam * src_bstride;
+    b.dst_off = b.beam * dst_bstride;
     b.src_stride = src_stride;
     b.dst_stride = dst_stride;
   }

@@ -49,7 +49,8 @@ typedef float F4 __attribute__((ext_vector_type(4)));
 template <int CV>
 __device__ __forceinline__ void search_tile(const F4 (&out)[CV],
                                             const SearchTile &st, int wave, int lane, int col_waves,
-                                            int rows_per_wg, int r, bool row_ok, int tile, int nt, int nrows) {
+                                            int rows_per_wg, int r, bool row_ok, int tile, int nt, int nrows,
+                                            int beam) {
   extern __shared__ float sbuf[];
   struct Red {
     double s, q;
@@ -130,7 +131,7 @@ __device__ __forceinline__ void search_tile(const F4 (&out)[CV],
           a.t = x.t;
         }
       }
-      const int b = blockIdx.z;
+      const int b = beam;
       BoxPartial &p = st.part[((static_cast<int64_t>(b) * (m + 1) + j) * nrows + r) * st.ntiles + tile];
       p.sum = a.s;
       p.sumsq = a.q;
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   if (!SEARCH && r >= nrows) return;
   const bool row_ok = r < nrows;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
-  if (!RAGGED) bs.tile = item.y;
+  if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int64_t src_stride = bs.src_stride;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     F4 outf[CV];  // the values just stored (FP32 output)
 #pragma unroll
     for (int c = 0; c < CV; ++c) outf[c] = __builtin_convertvector(v[0][c], F4);
-    search_tile<CV>(outf, search, wave, lane, col_waves, rows_per_wg, r, row_ok, bs.tile, nt, nrows);
+    search_tile<CV>(outf, search, wave, lane, col_waves, rows_per_wg, r, row_ok, bs.tile, nt, nrows, bs.beam);
   }
 }
 
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
   const int r = g * rows_per_wg + wave / col_waves;
   if (r >= nrows) return;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
-  if (!RAGGED) bs.tile = item.y;
+  if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   // the input's rows are Nt samples apart; a plane's by its (padded) stride
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, FROM_INPUT ? nt_u : src_stride_u, src_bstride, dst_stride_u,
                                         dst_bstride);
-  if (!RAGGED) bs.tile = item.y;
+  if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int64_t src_stride = FROM_INPUT ? nt : bs.src_stride;
   const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
