@@ -601,3 +601,26 @@ def test_two_c_forward_and_adjoint(sched, nf, nt, nd, band, gamma, d_min):
     np.testing.assert_array_equal(pf.forward(_dev(xf)).cpu().numpy(), ofdmt(xf, *band, nd, tab, acc=np.float32))
     g = W.random_input((nd, nt), np.float32, seed=nd + 5)
     np.testing.assert_array_equal(pf.adjoint(_dev(g)).cpu().numpy(), oadj(g, *band, nf, tab, acc=np.float32))
+
+
+@pytest.mark.parametrize("sched", [dict(), dict(first_kernel=3, first_levels=3, later_levels=3, gather_vecs=4,
+                                            adjoint_levels=3, adjoint_last_levels=3)])
+def test_largest_channel_and_delay_counts(sched):
+    """The plan's largest Nf and Nd (65536 each: 16 iterations, 131071
+    partial-sum rows) over a short ragged record: uint8 -> int32 equals the
+    int64 oracle, FP32 input and the FP32 adjoint the binary32 oracle, bit for
+    bit."""
+    nf = nd = 65536
+    nt, band = 300, (1.2, 1.6)
+    print(f"largest Nf, Nd: {sched}", flush=True)
+    tab = build_tables(nf, nd, *band)
+    rng = np.random.default_rng(65536)
+    u8 = rng.integers(0, 256, (nf, nt), dtype=np.uint8)
+    p = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, **sched)
+    y = p.forward(_dev(u8)).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(y, ofdmt(u8.astype(np.int64), *band, nd, tab))
+    xf = rng.standard_normal((nf, nt)).astype(np.float32)
+    pf = F.Plan(nf, nt, nd, *band, **sched)
+    np.testing.assert_array_equal(pf.forward(_dev(xf)).cpu().numpy(), ofdmt(xf, *band, nd, tab, acc=np.float32))
+    g = rng.standard_normal((nd, nt)).astype(np.float32)
+    np.testing.assert_array_equal(pf.adjoint(_dev(g)).cpu().numpy(), oadj(g, *band, nf, tab, acc=np.float32))
