@@ -145,7 +145,7 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
       if (j < n) {
-        const Tacc *row = base + e[j].x * stride;
+        const Tacc *row = base + row_offset(e[j].x, stride);
 #pragma unroll
         for (int c = 0; c < CV; ++c) {
           const int ts = t + 256 * c + e[j].y;
@@ -179,18 +179,17 @@ __global__ __launch_bounds__(kGatherThreads) void adjoint_gather_kernel(
     int32_t rows_per_wg, int32_t tiles_fastest, RaggedMap rg) {
   typedef typename Vec4<Tacc>::type V;
   constexpr int kSpan = adjoint_wave_span(CV, LAG);
-  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int2 item = gather_item<RAGGED>(groups, tiles_fastest != 0);
+  const WaveLayout wl = wave_layout(wave, rows_per_wg, nrows);
+  const int col_waves = wl.col_waves;
+  const int2 item = gather_item<RAGGED>(wl.groups, tiles_fastest != 0);
   const int g = item.x;
-  const int r = g * rows_per_wg + wave / col_waves;
+  const int r = g * rows_per_wg + wl.row;
   if (r >= nrows) return;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, src_stride_u, src_bstride, dst_stride_u, dst_bstride);
   if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
-  const int t_wave = (bs.tile * col_waves + wave % col_waves) * kSpan;
+  const int t_wave = (bs.tile * col_waves + wl.col) * kSpan;
   const int t = t_wave + lane * 4;
   if (LAG ? t_wave >= nt : t >= nt) return;
   const Tacc *base = src + bs.src_off;
@@ -240,6 +239,9 @@ hipError_t launch_adjoint_gather(const GatherLaunch &g, const Tacc *src, Tacc *d
                                  const int32_t *starts, const int32_t *order, int32_t nt, int32_t max_shift,
                                  int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                                  int32_t nrows) {
+  if (!gather_shape_ok(g)) return hipErrorInvalidValue;
+  // the tile-major work order numbers the grid's workgroups in 32 bits
+  if (g.tiles_fastest && static_cast<uint64_t>(g.grid.x) * g.grid.y >= (1ull << 31)) return hipErrorInvalidValue;
 #define FDMT_ADJ_NT(KK, CC, RR, LL, NN)                                                                       \
   hipLaunchKernelGGL((adjoint_gather_kernel<Tacc, KK, CC, RR, LL, NN>), g.grid, dim3(g.threads), 0, g.stream, \
                      src, dst, leaves, starts, order, nt, max_shift, src_stride, src_bstride, dst_stride,          \

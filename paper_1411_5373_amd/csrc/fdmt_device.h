@@ -67,6 +67,13 @@ __device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Element offset of row `row` (>= 0) of rows `stride` (< 2^32) elements
+// apart: one 32 x 32 -> 64-bit product (two scalar instructions, where a
+// signed 64-bit product takes six).
+__device__ __forceinline__ int64_t row_offset(int row, int64_t stride) {
+  return static_cast<int64_t>(static_cast<uint64_t>(static_cast<uint32_t>(row)) * static_cast<uint32_t>(stride));
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; renumber them so each XCD
 // runs a contiguous range of work items (neighbouring blocks share leaf rows
 // and time halos through that XCD's L2).
@@ -77,6 +84,29 @@ __device__ __forceinline__ int xcd_local_order(int id, int n) {
 }
 
 
+
+// Place of a wave in a register-gather workgroup of blockDim.x threads that
+// holds rows_per_wg rows side by side, col_waves waves along time per row.
+// Workgroup sizes and rows per workgroup are powers of two (the launchers
+// check), so shifts stand in for the divisions, each of which would cost the
+// scalar unit about twenty instructions per wave.
+struct WaveLayout {
+  int col_waves;  // waves per row
+  int groups;     // row groups over nrows rows
+  int row;        // the wave's row within the workgroup
+  int col;        // the wave's place along time within its row
+};
+
+__device__ __forceinline__ WaveLayout wave_layout(int wave, int rows_per_wg, int nrows) {
+  const int lr = __builtin_ctz(static_cast<unsigned>(rows_per_wg));
+  const int lc = __builtin_ctz(blockDim.x) - 6 - lr;
+  WaveLayout w;
+  w.col_waves = 1 << lc;
+  w.groups = (nrows + rows_per_wg - 1) >> lr;
+  w.row = wave >> lc;
+  w.col = wave & (w.col_waves - 1);
+  return w;
+}
 
 // Work item (row group, time tile) of a register-gather launch over
 // groups x tiles workgroups. By default (and always for ragged launches,
@@ -92,11 +122,12 @@ __device__ __forceinline__ int2 gather_item(int groups, bool tiles_fastest) {
   if (RAGGED || !tiles_fastest) {
     return make_int2(xcd_local_order(blockIdx.x, groups), RAGGED ? -1 : static_cast<int>(blockIdx.y));
   } else {
-    const int tiles = gridDim.y;
-    const int64_t n = static_cast<int64_t>(groups) * tiles;
-    const int64_t id = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;  // dispatch order
-    const int64_t q = n >> 3, r = n & 7, x = id & 7, slot = id >> 3;
-    const int64_t item = x * q + (x < r ? x : r) + slot;
+    // 32-bit arithmetic: the launcher keeps groups x tiles below 2^31
+    const unsigned tiles = gridDim.y;
+    const unsigned n = static_cast<unsigned>(groups) * tiles;
+    const unsigned id = blockIdx.y * gridDim.x + blockIdx.x;  // dispatch order
+    const unsigned q = n >> 3, r = n & 7, x = id & 7, slot = id >> 3;
+    const unsigned item = x * q + (x < r ? x : r) + slot;
     return make_int2(static_cast<int>(item / tiles), static_cast<int>(item % tiles));
   }
 }

@@ -160,13 +160,12 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   // most terms, so repeats hit this CU's L1) over one tile of
   // 256 * CV * (blockDim.x / 64 / rows_per_wg) samples; a lane handles CV
   // runs of 4 samples, 256 apart.
-  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;  // waves per row
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int2 item = gather_item<RAGGED>(groups, false);
+  const WaveLayout wl = wave_layout(wave, rows_per_wg, nrows);
+  const int col_waves = wl.col_waves;  // waves per row
+  const int2 item = gather_item<RAGGED>(wl.groups, false);
   const int g = item.x;
-  const int r = g * rows_per_wg + wave / col_waves;
+  const int r = g * rows_per_wg + wl.row;
   // with the search every thread stays for its barriers: rows past the last
   // and samples past the record compute zeros and store nothing
   if (!SEARCH && r >= nrows) return;
@@ -175,7 +174,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
   if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int64_t src_stride = bs.src_stride;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int tw = (bs.tile * col_waves + wl.col) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
   if (!SEARCH && t >= nt) return;
   const Tsrc *base = src + bs.src_off;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
     int mis[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const char *p = reinterpret_cast<const char *>(base + e[j].x * src_stride + (t - e[j].y));
+      const char *p = reinterpret_cast<const char *>(base + row_offset(e[j].x, src_stride) + (t - e[j].y));
       mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
 #pragma unroll
       for (int c = 0; c < CV; ++c) {
@@ -230,12 +229,12 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
       for (int c = 0; c < CV; ++c)
         v[j][c] = t + 256 * c < nt
                       ? __builtin_convertvector(
-                            *reinterpret_cast<const S4 *>(base + e[j].x * src_stride + (t + 256 * c - e[j].y)), V)
+                            *reinterpret_cast<const S4 *>(base + row_offset(e[j].x, src_stride) + (t + 256 * c - e[j].y)), V)
                       : V(0);
   } else {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Tsrc *row = base + e[j].x * src_stride;
+      const Tsrc *row = base + row_offset(e[j].x, src_stride);
 #pragma unroll
       for (int c = 0; c < CV; ++c) {
         const int ts = t + 256 * c - e[j].y;
@@ -310,18 +309,17 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
   typedef typename Vec4<Tdst>::type D4;
   typedef typename In4<Tin>::type I4;
   constexpr int N = 1 << K;
-  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int2 item = gather_item<RAGGED>(groups, false);
+  const WaveLayout wl = wave_layout(wave, rows_per_wg, nrows);
+  const int col_waves = wl.col_waves;
+  const int2 item = gather_item<RAGGED>(wl.groups, false);
   const int g = item.x;
-  const int r = g * rows_per_wg + wave / col_waves;
+  const int r = g * rows_per_wg + wl.row;
   if (r >= nrows) return;
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, nt_u, src_bstride, dst_stride_u, dst_bstride);
   if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int tw = (bs.tile * col_waves + wl.col) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * 4;
   if (t >= nt) return;
   const Tin *base = src + bs.src_off;
@@ -349,7 +347,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
     int mis[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + static_cast<int64_t>(e[j].x) * nt +
+      const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + row_offset(e[j].x, nt) +
                          (t - e[j].y - e[j].z);
       mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
 #pragma unroll
@@ -392,7 +390,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
     int mis[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const char *p = reinterpret_cast<const char *>(base + static_cast<int64_t>(e[j].x) * nt +
+      const char *p = reinterpret_cast<const char *>(base + row_offset(e[j].x, nt) +
                                                      (t - e[j].y - e[j].z));
       mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
 #pragma unroll
@@ -432,7 +430,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
     for (int j = 0; j < N; ++j) {
 #pragma unroll
       for (int c = 0; c < CV; ++c) {
-        const Tin *p = base + static_cast<int64_t>(e[j].x) * nt + (t + 256 * c - e[j].y);
+        const Tin *p = base + row_offset(e[j].x, nt) + (t + 256 * c - e[j].y);
         V acc = __builtin_convertvector(*reinterpret_cast<const I4 *>(p), V);
         for (int d = 1; d <= e[j].z; ++d) acc = acc + __builtin_convertvector(*reinterpret_cast<const I4 *>(p - d), V);
         v[j][c] = acc;
@@ -441,7 +439,7 @@ __global__ __launch_bounds__(kGatherThreads) void input_gather_kernel(
   } else {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Tin *p = base + static_cast<int64_t>(e[j].x) * nt;
+      const Tin *p = base + row_offset(e[j].x, nt);
 #pragma unroll
       for (int c = 0; c < CV; ++c) {
         const int ts = t + 256 * c - e[j].y;
@@ -479,6 +477,7 @@ template <typename Tsrc, typename Tacc, typename Tdst>
 hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, const int2 *terms, int32_t nt,
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
+  if (!gather_shape_ok(g)) return hipErrorInvalidValue;
   if (g.search.part) {
     // the last forward pass with the boxcar search: FP32 output, uniform batches
     if constexpr (std::is_same<Tdst, float>::value) {
@@ -539,6 +538,7 @@ hipError_t launch_gather(const GatherLaunch &g, const Tsrc *src, Tdst *dst, cons
 template <typename Tin, typename Tacc, typename Tdst>
 hipError_t launch_input_gather(const GatherLaunch &g, const Tin *src, Tdst *dst, const int4 *terms, int32_t nt,
                                int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride, int32_t nrows) {
+  if (!gather_shape_ok(g)) return hipErrorInvalidValue;
 #define FDMT_IGATHER(KK, CC, RR)                                                                          \
   hipLaunchKernelGGL((input_gather_kernel<Tin, Tacc, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0, \
                      g.stream, src, dst, terms, nt, src_bstride, dst_stride, dst_bstride, nrows,          \

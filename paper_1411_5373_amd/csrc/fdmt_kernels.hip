@@ -759,6 +759,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           g.threads = forward_threads(p, ps);
+          g.short_chains = ps.max_chain <= 1;
           if constexpr (std::is_same<Tin, uint8_t>::value) {
             if (narrow_out)  // exact integer sums below 2^16
               return launch_narrow_input_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,
@@ -878,6 +879,8 @@ hipError_t run_adjoint_step(const Plan &p, const Step &st, const void *in, void 
         GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, ps.depth, cv, rpw, ps.lagged,
                        st.index < 32 ? static_cast<int>((p.adjoint_tile_major >> st.index) & 1u) : 0,
                        threads};
+        // the tile-major order numbers the workgroups in 32 bits
+        if (static_cast<uint64_t>(gx) * gy >= (1ull << 31)) g.tiles_fastest = 0;
         g.streaming = ps.to_input;
         return launch_adjoint_gather<Tacc>(g, sp, dp, lv, sr, od, nt32, ps.max_shift, src.stride, src.bstride,
                                            dst.stride, dst.bstride, ps.nrows);

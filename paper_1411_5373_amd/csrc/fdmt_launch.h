@@ -34,7 +34,16 @@ struct GatherLaunch {
   int threads = kGatherThreads;  // workgroup size: 64 .. 1024, a multiple of 64 * rows_per_wg
   SearchTile search;             // forward gathers: the fused boxcar search (last pass only)
   bool streaming = false;        // output not read again by this call: non-temporal stores
+  bool short_chains = false;     // uint8 first pass: no Option-1 chain longer than 1
 };
+
+// The register-gather kernels place their waves with shifts: the workgroup
+// size and the rows per workgroup must be powers of two, with 64 threads or
+// more per row.
+inline bool gather_shape_ok(const GatherLaunch &g) {
+  const auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  return pow2(g.threads) && pow2(g.rows_per_wg) && g.threads <= 1024 && 64 * g.rows_per_wg <= g.threads;
+}
 
 // Output samples per wave of the adjoint gather: 4 per lane in `cv` runs,
 // less the last lane's last run in a lagged pass (it only feeds the lane

@@ -59,6 +59,53 @@ __device__ __forceinline__ void load_words(uint32_t (&w)[M], const char *q) {
   }
 }
 
+// Adds one term of the uint8 first pass into a lane's packed sums: samples
+// 4 q4 and 4 q4 + 2 into pk[2 q4] (one per 16-bit half), 4 q4 + 1 and
+// 4 q4 + 3 into pk[2 q4 + 1]. The term's words w start at byte b before the
+// chain's earliest sample, and the chain has c + 1 elements, so element i of
+// sample 4 q4 + e is byte 4 q4 + b + c - i + e: the even pair takes the byte
+// pairs (u, u + 2) for u = b .. b + c of word pair (q4, q4 + 1), the odd pair
+// those for u = b + 1 .. b + c + 1. That is c + 2 byte-pair extractions (one
+// v_perm each) per group, the middle c shared. A pair stays inside its two
+// words while b + c <= 4; otherwise the words are first realigned to byte b.
+// SHORT (no chain of the pass longer than 1, so b + c <= 4 always) runs
+// without branches: the middle extraction's selector is swapped for one that
+// gives zeros when c = 0.
+template <bool SHORT, int CV, int W>
+__device__ __forceinline__ void add_byte_chain(uint32_t (&pk)[2 * CV], uint32_t (&w)[W], int b, int c) {
+  static_assert(W == CV + 2, "a byte term spans CV + 2 words");
+  // v_perm selector: byte u of {hi:lo} to the low half, byte u + 2 to the high
+  // half, zero bytes (selector 0x0c) above each
+  const auto sel = [](int u) { return 0x0c020c00u + static_cast<uint32_t>(u) * 0x10001u; };
+  if constexpr (SHORT) {
+    // sel(u + k) = sel(u) + k * 0x10001
+    const uint32_t s_lo = sel(b);
+    const uint32_t s_mid = c ? s_lo + 0x10001u : 0x0c0c0c0cu;
+    const uint32_t s_hi = s_lo + static_cast<uint32_t>(c + 1) * 0x10001u;
+#pragma unroll
+    for (int q4 = 0; q4 < CV; ++q4) {
+      const uint32_t lo = w[q4], hi = w[q4 + 1];
+      const uint32_t mid = __builtin_amdgcn_perm(hi, lo, s_mid);
+      pk[2 * q4] += mid + __builtin_amdgcn_perm(hi, lo, s_lo);
+      pk[2 * q4 + 1] += mid + __builtin_amdgcn_perm(hi, lo, s_hi);
+    }
+  } else {
+    if (b + c > 4) {
+#pragma unroll
+      for (int m = 0; m <= CV; ++m) w[m] = __builtin_amdgcn_alignbyte(w[m + 1], w[m], b);
+      b = 0;
+    }
+#pragma unroll
+    for (int q4 = 0; q4 < CV; ++q4) {
+      const uint32_t lo = w[q4], hi = w[q4 + 1];
+      uint32_t mid = 0;
+      for (int u = b + 1; u <= b + c; ++u) mid += __builtin_amdgcn_perm(hi, lo, sel(u));
+      pk[2 * q4] += mid + __builtin_amdgcn_perm(hi, lo, sel(b));
+      pk[2 * q4 + 1] += mid + __builtin_amdgcn_perm(hi, lo, sel(b + c + 1));
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T from_int(int32_t x) {
   return static_cast<T>(x);
@@ -92,22 +139,26 @@ __device__ __forceinline__ void store_lane(Tdst *o, const int32_t (&acc)[S], int
   }
 }
 
-template <bool FROM_INPUT, typename Tdst, int K, int CV, bool RAGGED>
+// SHORT: uint8 input into uint16 planes whose Option-1 chains are all at most
+// 1 long (the host knows this per pass); a template parameter rather than a
+// branch, as one kernel holding both byte-chain forms took 67 VGPRs against
+// 40-43 for either alone.
+template <bool FROM_INPUT, typename Tdst, int K, int CV, bool RAGGED, bool SHORT>
 __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
     const void *__restrict__ src_v, Tdst *__restrict__ dst, const void *__restrict__ terms_v, int32_t nt_u,
     int64_t src_stride_u, int64_t src_bstride, int64_t dst_stride_u, int64_t dst_bstride, int32_t nrows,
     int32_t rows_per_wg, RaggedMap rg) {
   typedef typename std::conditional<FROM_INPUT, uint8_t, uint16_t>::type Tsrc;
+  static_assert(!SHORT || (FROM_INPUT && sizeof(Tdst) == 2), "short chains: uint8 input into uint16 planes");
   constexpr int N = 1 << K;
   constexpr int S = NarrowShape<FROM_INPUT, CV>::S;
   constexpr int W = NarrowShape<FROM_INPUT, CV>::W;
-  const int waves = static_cast<int>(blockDim.x) / 64;
   const int wave = uniform(threadIdx.x / 64), lane = threadIdx.x % 64;
-  const int col_waves = waves / rows_per_wg;
-  const int groups = (nrows + rows_per_wg - 1) / rows_per_wg;
-  const int2 item = gather_item<RAGGED>(groups, false);
+  const WaveLayout wl = wave_layout(wave, rows_per_wg, nrows);
+  const int col_waves = wl.col_waves;
+  const int2 item = gather_item<RAGGED>(wl.groups, false);
   const int g = item.x;
-  const int r = g * rows_per_wg + wave / col_waves;
+  const int r = g * rows_per_wg + wl.row;
   if (r >= nrows) return;
   // the input's rows are Nt samples apart; a plane's by its (padded) stride
   BeamSpan bs = beam_span<RAGGED>(rg, nt_u, FROM_INPUT ? nt_u : src_stride_u, src_bstride, dst_stride_u,
@@ -115,7 +166,7 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   if (!RAGGED) bs.tile = rg.reverse ? static_cast<int>(gridDim.y) - 1 - item.y : item.y;
   const int nt = bs.nt;
   const int64_t src_stride = FROM_INPUT ? nt : bs.src_stride;
-  const int tw = (bs.tile * col_waves + wave % col_waves) * 256 * CV;  // first sample of the wave
+  const int tw = (bs.tile * col_waves + wl.col) * 256 * CV;  // first sample of the wave
   const int t = tw + lane * S;
   // Lanes past the record's end return early, except where the outputs pass
   // through LDS: there every lane stores 4 samples of another lane's range.
@@ -158,9 +209,10 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
     if constexpr (FROM_INPUT) {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const char *p = reinterpret_cast<const char *>(base + row[j] * src_stride + (t - shift[j] - chain[j]));
+        const char *p = reinterpret_cast<const char *>(base + row_offset(row[j], src_stride) + (t - shift[j] - chain[j]));
         mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
-        load_words<W>(w[j], p - mis[j]);
+        // a chain of at most 1 ends by byte 3 + 1 + S - 1 of the words: CV + 1 of them
+        load_words<SHORT ? CV + 1 : W>(w[j], p - mis[j]);
       }
     } else {
       // uint16: the wave's lanes cover one contiguous run of words, S / 2 per
@@ -171,7 +223,7 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
       static_assert(W == H + 1, "uint16 terms span S / 2 + 1 words");
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const char *p = reinterpret_cast<const char *>(base + row[j] * src_stride + (t - shift[j]));
+        const char *p = reinterpret_cast<const char *>(base + row_offset(row[j], src_stride) + (t - shift[j]));
         mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
         load_words<H>(w[j], p - mis[j]);
         w[j][H] = 0;
@@ -195,26 +247,14 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
       uint32_t pk[S / 2];
 #pragma unroll
       for (int m = 0; m < S / 2; ++m) pk[m] = 0;
+      if constexpr (FROM_INPUT) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        if constexpr (FROM_INPUT) {
-          // bytes 0 and 2 of a word add into one word, bytes 1 and 3 into another
-          for (int i = 0; i <= chain[j]; ++i) {
-            const int o = mis[j] + chain[j] - i;
-            const int k = o >> 2;
+        for (int j = 0; j < N; ++j) add_byte_chain<SHORT, CV>(pk, w[j], mis[j], chain[j]);
+      } else {
 #pragma unroll
-            for (int q4 = 0; q4 < CV; ++q4) {
-              const uint32_t lo = k ? w[j][q4 + 1] : w[j][q4];
-              const uint32_t hi = k ? w[j][q4 + 2] : w[j][q4 + 1];
-              const uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, o & 3);
-              pk[2 * q4] += x & 0x00ff00ffu;             // samples 4 q4 and 4 q4 + 2
-              pk[2 * q4 + 1] += (x >> 8) & 0x00ff00ffu;  // samples 4 q4 + 1 and 4 q4 + 3
-            }
-          }
-        } else {
+        for (int j = 0; j < N; ++j)
 #pragma unroll
           for (int m = 0; m < S / 2; ++m) pk[m] += __builtin_amdgcn_alignbyte(w[j][m + 1], w[j][m], mis[j]);
-        }
       }
       if constexpr (FROM_INPUT) {
         // (even, odd) word pairs to sample order: bytes 0-1 of the even word
@@ -271,7 +311,7 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
     // row edges: every sample checked against [0, nt)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const Tsrc *rp = base + row[j] * src_stride;
+      const Tsrc *rp = base + row_offset(row[j], src_stride);
       for (int i = 0; i <= chain[j]; ++i) {
 #pragma unroll
         for (int q = 0; q < S; ++q) {
@@ -314,12 +354,13 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
   }
 }
 
-template <bool FROM_INPUT, typename Tdst>
+template <bool FROM_INPUT, typename Tdst, bool SHORT = false>
 hipError_t launch_narrow(const GatherLaunch &g, const void *src, Tdst *dst, const void *terms, int32_t nt,
                          int64_t src_stride, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                          int32_t nrows) {
+  if (!gather_shape_ok(g)) return hipErrorInvalidValue;
 #define FDMT_NARROW(KK, CC, RR)                                                                                 \
-  hipLaunchKernelGGL((narrow_gather_kernel<FROM_INPUT, Tdst, KK, CC, RR>), g.grid, dim3(g.threads), 0,     \
+  hipLaunchKernelGGL((narrow_gather_kernel<FROM_INPUT, Tdst, KK, CC, RR, SHORT>), g.grid, dim3(g.threads), 0, \
                      g.stream, src, dst, terms, nt, src_stride, src_bstride, dst_stride, dst_bstride, nrows,   \
                      g.rows_per_wg, g.rg)
 #define FDMT_NARROW_K(CC, RR)              \
@@ -347,6 +388,10 @@ hipError_t launch_narrow_input_gather(const GatherLaunch &g, const uint8_t *src,
                                       int32_t nt, int64_t src_bstride, int64_t dst_stride, int64_t dst_bstride,
                                       int32_t nrows) {
   if (g.vecs != 1 && g.vecs != 2) return hipErrorInvalidValue;
+  if constexpr (sizeof(Tdst) == 2) {
+    if (g.short_chains)
+      return launch_narrow<true, Tdst, true>(g, src, dst, terms, nt, nt, src_bstride, dst_stride, dst_bstride, nrows);
+  }
   return launch_narrow<true, Tdst>(g, src, dst, terms, nt, nt, src_bstride, dst_stride, dst_bstride, nrows);
 }
 

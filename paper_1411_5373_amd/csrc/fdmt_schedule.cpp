@@ -449,6 +449,7 @@ std::string build_pass(Schedule &s, const Tables &t, const ScheduleParams &p, in
             // a position without a channel reads a zero row of the padded input
             s.iterms.push_back(InTerm{ch, x.shift + (ch < t.nf ? t.pre[ch] : 0), d, 0});
             ps.staged_rows += d + 1;
+            ps.max_chain = std::max(ps.max_chain, d);
           }
         } else {
           s.terms.insert(s.terms.end(), cur.begin(), cur.end());

@@ -83,6 +83,7 @@ struct Pass {
   int64_t psum_offset = 0;  // staged first pass: index of the first Schedule::psums record
   int lds_p = 0;            // staged first pass: LDS elements of the partial-sum rows
   int stage_ints = 0;       // staged: LDS ints of the staging-record area
+  int max_chain = 0;        // register pass from the input: longest Option-1 chain of its terms
 };
 
 struct ScheduleParams {
