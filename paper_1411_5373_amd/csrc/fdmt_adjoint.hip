@@ -137,32 +137,43 @@ __device__ __forceinline__ void gather_range(DepthSums<Tacc, K, CV> &sums, const
   struct Chunk {
     int4 e[kChunk];
   };
-  Chunk cur = *reinterpret_cast<const Chunk *>(leaves + x0);
-  for (int x = x0; x < x1; x += kChunk) {
-    const int n = x1 - x < kChunk ? x1 - x : kChunk;
-    const int4 *e = cur.e;
-    R v[kChunk][CV];
+  const auto load = [&](R (&v)[CV], const int4 &e) {
+    const Tacc *row = base + row_offset(e.x, stride);
+    const Tacc *p = row + (t + e.y);  // the runs at constant offsets from one address
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (j < n) {
-        const Tacc *row = base + row_offset(e[j].x, stride);
+    for (int c = 0; c < CV; ++c) {
+      const int ts = t + 256 * c + e.y;
+      if (INTERIOR || ts + 4 <= nt) {
+        v[c] = *reinterpret_cast<const V *>(p + 256 * c);
+      } else {
 #pragma unroll
-        for (int c = 0; c < CV; ++c) {
-          const int ts = t + 256 * c + e[j].y;
-          if (INTERIOR || ts + 4 <= nt) {
-            v[j][c] = *reinterpret_cast<const V *>(row + ts);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[j][c][i] = ts + i < nt ? row[ts + i] : Tacc(0);
-          }
-        }
+        for (int i = 0; i < 4; ++i) v[c][i] = ts + i < nt ? row[ts + i] : Tacc(0);
       }
     }
+  };
+  Chunk cur = *reinterpret_cast<const Chunk *>(leaves + x0);
+  int x = x0;
+  // Whole chunks load and add every leaf unconditionally: with per-leaf
+  // conditions the compiler cannot tell a skipped leaf's load from a pending
+  // one, and waited for the first leaf's loads before issuing the second's.
+  for (; x + kChunk <= x1; x += kChunk) {
+    R v[kChunk][CV];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) load(v[j], cur.e[j]);
     const Chunk next = *reinterpret_cast<const Chunk *>(leaves + x + kChunk);
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j)
-      if (j < n) sums.add(v[j], e[j].z, x + j == x0);
+    for (int j = 0; j < kChunk; ++j) sums.add(v[j], cur.e[j].z, x + j == x0);
     cur = next;
+  }
+  if (x < x1) {
+    const int n = x1 - x;
+    R v[kChunk][CV];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j)
+      if (j < n) load(v[j], cur.e[j]);
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j)
+      if (j < n) sums.add(v[j], cur.e[j].z, x + j == x0);
   }
 }
 
