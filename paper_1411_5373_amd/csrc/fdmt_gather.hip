@@ -222,6 +222,16 @@ __global__ __launch_bounds__(kGatherThreads) void gather_pass_kernel(
         v[j][c][2] = static_cast<Tacc>(hi & 0xffffu);
         v[j][c][3] = static_cast<Tacc>(hi >> 16);
       }
+  } else if (tw >= smax && tw + 256 * CV <= nt) {
+    // every term and run inside the record for the whole wave: no lane
+    // conditions, so no exec-mask branches around the loads
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Tsrc *p = base + row_offset(e[j].x, src_stride) + (t - e[j].y);
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        v[j][c] = __builtin_convertvector(*reinterpret_cast<const S4 *>(p + 256 * c), V);
+    }
   } else if (tw >= smax) {  // every term inside the record for the whole wave
 #pragma unroll
     for (int j = 0; j < N; ++j)

@@ -759,7 +759,7 @@ hipError_t run_forward_step(const Plan &p, const Step &st, const void *in, void 
         return for_each_launch(p, rb, st, false, tile, batch, [&](auto r, unsigned gy, unsigned gz, const RaggedMap &rg) {
           GatherLaunch g{dim3(gx, gy, gz), stream, rg, decltype(r)::value, k, cv, rpw};
           g.threads = forward_threads(p, ps);
-          g.short_chains = ps.max_chain <= 1;
+          g.max_chain = ps.max_chain;
           if constexpr (std::is_same<Tin, uint8_t>::value) {
             if (narrow_out)  // exact integer sums below 2^16
               return launch_narrow_input_gather<uint16_t>(g, sp, static_cast<uint16_t *>(dst.ptr), tm, nt32,

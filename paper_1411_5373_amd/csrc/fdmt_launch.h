@@ -34,7 +34,7 @@ struct GatherLaunch {
   int threads = kGatherThreads;  // workgroup size: 64 .. 1024, a multiple of 64 * rows_per_wg
   SearchTile search;             // forward gathers: the fused boxcar search (last pass only)
   bool streaming = false;        // output not read again by this call: non-temporal stores
-  bool short_chains = false;     // uint8 first pass: no Option-1 chain longer than 1
+  int max_chain = -1;            // first pass from the input: longest Option-1 chain (-1: not known)
 };
 
 // The register-gather kernels place their waves with shifts: the workgroup

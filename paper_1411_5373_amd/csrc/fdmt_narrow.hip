@@ -389,7 +389,7 @@ hipError_t launch_narrow_input_gather(const GatherLaunch &g, const uint8_t *src,
                                       int32_t nrows) {
   if (g.vecs != 1 && g.vecs != 2) return hipErrorInvalidValue;
   if constexpr (sizeof(Tdst) == 2) {
-    if (g.short_chains)
+    if (g.max_chain >= 0 && g.max_chain <= 1)
       return launch_narrow<true, Tdst, true>(g, src, dst, terms, nt, nt, src_bstride, dst_stride, dst_bstride, nrows);
   }
   return launch_narrow<true, Tdst>(g, src, dst, terms, nt, nt, src_bstride, dst_stride, dst_bstride, nrows);

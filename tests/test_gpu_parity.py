@@ -386,12 +386,12 @@ _ORACLE_CACHE = {}
 def _oracle_forward(kind, x, band, nd):
     """Oracle forward of a sweep input, kept per (kind, shape) across the sweep's
     schedules: 'f32'/'f16' in binary32 (the same additions as the kernels),
-    'u8' in int64."""
+    'u8' and 'i32' in int64."""
     key = (kind, x.shape, band, nd)
     if key not in _ORACLE_CACHE:
         if len(_ORACLE_CACHE) > 6:
             _ORACLE_CACHE.clear()
-        if kind == "u8":
+        if kind in ("u8", "i32"):
             _ORACLE_CACHE[key] = ofdmt(x.astype(np.int64), *band, nd)
         else:
             _ORACLE_CACHE[key] = ofdmt(x, *band, nd, acc=np.float32)
@@ -404,7 +404,7 @@ def _oracle_forward(kind, x, band, nd):
 def test_schedules_bit_identical(sched, nf, nt, nd, band):
     """Any fusion schedule (block splits, tiles, LDS budgets, kernel forms)
     gives the oracle's result bit for bit: FP32 and FP16 input against its
-    binary32 evaluation, uint8 input with int32 sums against int64."""
+    binary32 evaluation, uint8 and int32 input with int32 sums against int64."""
     print(f"schedule {sched} nf={nf} nt={nt} nd={nd}", flush=True)
     x = torch.randn(nf, nt, device=DEV, generator=torch.Generator(DEV).manual_seed(nf + nt))
     try:
@@ -422,6 +422,12 @@ def test_schedules_bit_identical(sched, nf, nt, nd, band):
     pi = F.Plan(nf, nt, nd, *band, in_dtype=torch.uint8, acc_dtype=torch.int32, **sched)
     yi = pi.forward(xi).cpu().numpy().astype(np.int64)
     np.testing.assert_array_equal(yi, _oracle_forward("u8", xi.cpu().numpy(), band, nd))
+    # int32 input (|x| <= 10^5: every path sum fits int32): exact against int64
+    xw = torch.randint(-100000, 100001, (nf, nt), device=DEV, dtype=torch.int32,
+                       generator=torch.Generator(DEV).manual_seed(nd + 1))
+    pw = F.Plan(nf, nt, nd, *band, in_dtype=torch.int32, acc_dtype=torch.int32, **sched)
+    yw = pw.forward(xw).cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(yw, _oracle_forward("i32", xw.cpu().numpy(), band, nd))
 
 
 @pytest.mark.parametrize("gamma", [-1.0, 2.0, -3.0])
