@@ -67,6 +67,17 @@ __device__ __forceinline__ BeamSpan beam_span(const RaggedMap &rg, int nt, int64
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// The 32-bit word at p, an address the same for every lane, through the scalar
+// data cache (a read of data that earlier kernels wrote; caches are
+// invalidated at each launch).
+__device__ __forceinline__ uint32_t scalar_word(const void *p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint64_t u = static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(a >> 32))))
+                         << 32 |
+                     static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(a)));
+  return *reinterpret_cast<const __attribute__((address_space(4))) uint32_t *>(u);
+}
+
 // Element offset of row `row` (>= 0) of rows `stride` (< 2^32) elements
 // apart: one 32 x 32 -> 64-bit product (two scalar instructions, where a
 // signed 64-bit product takes six).

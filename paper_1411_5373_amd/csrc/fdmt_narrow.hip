@@ -218,22 +218,28 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
       // uint16: the wave's lanes cover one contiguous run of words, S / 2 per
       // lane, so a lane loads only its own words; an odd-shifted term (2
       // bytes off) needs one word more, the next lane's first, taken across
-      // lanes (the last lane loads its own)
+      // lanes. The last lane's is the word just past the wave's run, at an
+      // address the same for every lane: one scalar load, where a vector
+      // load for that lane alone would take an address-unit slot per term.
       constexpr int H = S / 2;
       static_assert(W == H + 1, "uint16 terms span S / 2 + 1 words");
+      uint32_t past[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const char *p = reinterpret_cast<const char *>(base + row_offset(row[j], src_stride) + (t - shift[j]));
+        const Tsrc *rp = base + row_offset(row[j], src_stride);
+        const char *p = reinterpret_cast<const char *>(rp + (t - shift[j]));
         mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
         load_words<H>(w[j], p - mis[j]);
         w[j][H] = 0;
-        if (mis[j] && lane == 63) w[j][H] = *reinterpret_cast<const uint32_t *>(p - mis[j] + 4 * H);
+        past[j] = 0;
+        if (mis[j]) past[j] = scalar_word(reinterpret_cast<const char *>(rp + (tw + 64 * S - shift[j])) - mis[j]);
       }
+      const int next_lane = ((lane + 1) & 63) << 2;  // ds_bpermute byte address of lane + 1
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         if (mis[j]) {
-          const uint32_t next = __shfl_down(w[j][0], 1, 64);
-          if (lane != 63) w[j][H] = next;
+          const uint32_t next = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(next_lane, static_cast<int>(w[j][0])));
+          w[j][H] = lane == 63 ? past[j] : next;
         }
       }
     }
