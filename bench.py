@@ -15,8 +15,12 @@ ragged 256-beam workload and the batch-16 differentiable workload, and the
 forward transform with the boxcar search and candidate list fused into its
 last pass. `roofline` describes the step's longest kernel: its algorithmic bytes (every
 element it must read and write, once) over its average duration measured
-with HIP events on the launch stream, against the HBM peak and against the
-library's own streaming copy measured in the same run.
+with HIP events on the launch stream, against the HBM peak, against the
+library's own streaming copy measured in the same run, and against the
+library's read/write-mix stream moving that kernel's own read and written
+bytes (HBM writes are slower than reads, so a kernel that writes more than it
+reads has a lower ceiling than the copy); every step kernel gets the same
+three fractions.
 
 The CPU leg (skipped with --cpu-sample 0) runs the oracle: it times it on a
 bounded slice of the workload (`cpu_baseline`; the ragged and differentiable
@@ -270,6 +274,34 @@ def copy_ceiling(F, torch, nbytes=1 << 30, reps=10):
     ok = bool(torch.equal(a, b))
     del a, b
     return {"bytes_copied": nbytes, "ms": round(ms, 4), "gb_s": round(2 * nbytes / ms / 1e6, 1), "verified": ok}
+
+
+def mix_ceilings(F, torch, infos, reps=10):
+    """Per step kernel: bandwidth of the library's read/write-mix stream
+    moving the kernel's own algorithmic bytes (read once, written once). HBM
+    serves writes more slowly than reads, so a kernel that writes more than
+    it reads has a lower ceiling than the 1:1 copy."""
+    pairs = [(i["bytes_read"] // 16 * 16, i["bytes_written"] // 16 * 16) for _, i in infos]
+    src = torch.empty(max(r for r, _ in pairs), dtype=torch.uint8, device="cuda")
+    dst = torch.empty(max(wr for _, wr in pairs), dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for r, wr in pairs:
+        if not (r and wr and r <= 2 * wr and wr <= 2 * r):
+            out.append(None)
+            continue
+        a, b = src[:r], dst[:wr]
+        F.stream_mix(b, a)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            F.stream_mix(b, a)
+        ev1.record()
+        torch.cuda.synchronize()
+        out.append(round((r + wr) / (ev0.elapsed_time(ev1) / reps) / 1e6, 1))
+    del src, dst
+    return out
 
 
 def differentiable_c5(F, torch, W, reps=3):
@@ -568,11 +600,14 @@ def main():
     models = {d: {"compulsory_gb": round(compulsory[d] / 1e9, 3), "unfused_gb": round(unfused[d] / 1e9, 3),
                   "schedule_gb": round(b / 1e9, 3), "compulsory_gb_s": round(compulsory[d] / ms / 1e6, 1)}
               for d, b, ms in (("forward", fwd_bytes, fwd_ms), ("adjoint", adj_bytes, adj_ms))}
+    mixes = mix_ceilings(F, torch, infos)
     kernels = [{"direction": d, "kind": i["kind"], "levels": [i["level_first"], i["level_last"]],
                 "ms": round(m, 4), "alg_gb_s": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6, 1),
                 "frac_of_peak": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / HBM_PEAK_GBS, 3),
-                "frac_of_copy": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / copy["gb_s"], 3)}
-               for m, (d, i) in zip(per, infos)]
+                "frac_of_copy": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / copy["gb_s"], 3),
+                "mix_ceiling_gb_s": mx,
+                "frac_of_mix": round((i["bytes_read"] + i["bytes_written"]) / m / 1e6 / mx, 3) if mx else None}
+               for m, (d, i), mx in zip(per, infos, mixes)]
 
     out = {
         "metric": "DM-trial*samples/sec (forward + adjoint step), Nf=4096",
@@ -600,7 +635,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": key, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": alg, "launch_ms": round(per[j], 4),
-                     "copy_ceiling_gb_s": copy["gb_s"], "frac_of_copy": round(achieved / copy["gb_s"], 4)},
+                     "copy_ceiling_gb_s": copy["gb_s"], "frac_of_copy": round(achieved / copy["gb_s"], 4),
+                     "mix_ceiling_gb_s": mixes[j],
+                     "frac_of_mix": round(achieved / mixes[j], 4) if mixes[j] else None},
         "copy_ceiling": copy,
     }
     if not args.no_forms:

@@ -391,6 +391,20 @@ fdmt_status_t fdmt_boxcar_search(const float *plane, int32_t batch, int32_t nd, 
  * no-op. Allocates nothing. */
 fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* Streaming device kernel with a given read/write mix: reads read_bytes of src
+ * once and writes write_bytes of dst once, with the copy's access shape. Not
+ * part of the transform: its bandwidth is the practical ceiling of a kernel
+ * that moves the same bytes in each direction, since HBM serves writes more
+ * slowly than reads (a kernel writing more than it reads cannot reach the
+ * copy's rate). dst unit i (16 bytes) is src unit i, or i - read_units past
+ * the end of src, when writing at least as much as reading; otherwise src
+ * unit i xor src unit i + write_units (the latter only inside src).
+ * FDMT_E_INVALID for NULL, misaligned or overlapping buffers, byte counts not
+ * multiples of 16, or one count above twice the other; both counts 0 is a
+ * no-op. Allocates nothing. */
+fdmt_status_t fdmt_stream_mix(void *dst, size_t write_bytes, const void *src, size_t read_bytes,
+                              void *hip_stream);
+
 /* Tuned schedule lookup. The package's autotuner times candidate schedules
  * on the GPU and stores the fastest per workload in a JSON cache; this call
  * lets a C caller start from that schedule as the Python layer does. The

@@ -10,5 +10,5 @@ from .binding import (EXPORTED, FDMTError, FDMTFunction, Plan, RaggedPlan, boxca
                       fdmt_plan_tables, fdmt_ragged_adjoint, fdmt_ragged_destroy,
                       fdmt_ragged_forward, fdmt_ragged_info, fdmt_ragged_plan,
                       fdmt_ragged_run_step, fdmt_ragged_workspace_bytes, fdmt_run_step,
-                      fdmt_status_string, fdmt_step_count, fdmt_step_info, fdmt_workspace_bytes,
-                      library_path, load)
+                      fdmt_status_string, fdmt_step_count, fdmt_step_info, fdmt_stream_mix, fdmt_workspace_bytes,
+                      library_path, load, stream_mix)

@@ -30,7 +30,8 @@ EXPORTED = ("fdmt_plan", "fdmt_workspace_bytes", "fdmt_forward", "fdmt_adjoint",
             "fdmt_ragged_adjoint", "fdmt_ragged_run_step", "fdmt_ragged_info",
             "fdmt_ragged_destroy", "fdmt_boxcar_workspace_bytes", "fdmt_boxcar_search",
             "fdmt_fft_workspace_bytes", "fdmt_forward_fft", "fdmt_search_workspace_bytes", "fdmt_search_fused", "fdmt_forward_search",
-            "fdmt_boxcar_search_noalloc", "fdmt_copy_bytes", "fdmt_tuned_options", "fdmt_status_string",
+            "fdmt_boxcar_search_noalloc", "fdmt_copy_bytes", "fdmt_stream_mix", "fdmt_tuned_options",
+            "fdmt_status_string",
             "fdmt_last_error")
 
 STEP_KINDS = ("init", "iteration", "lds_levels", "iteration_adjoint", "init_adjoint", "gather",
@@ -141,6 +142,8 @@ def load():
     lib.fdmt_boxcar_search_noalloc.restype = ctypes.c_int
     lib.fdmt_copy_bytes.argtypes = [vp, vp, sz, vp]
     lib.fdmt_copy_bytes.restype = ctypes.c_int
+    lib.fdmt_stream_mix.argtypes = [vp, sz, vp, sz, vp]
+    lib.fdmt_stream_mix.restype = ctypes.c_int
     lib.fdmt_tuned_options.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, i64, i32, ctypes.c_double,
                                        ctypes.c_double, ctypes.POINTER(_Options), p_i32]
     lib.fdmt_tuned_options.restype = ctypes.c_int
@@ -200,6 +203,21 @@ def copy_bytes(dst, src):
     if dst.numel() * dst.element_size() != n or not (src.is_contiguous() and dst.is_contiguous()):
         raise ValueError("dst and src must be contiguous and of equal byte size")
     fdmt_copy_bytes(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n, _stream_handle(src.device))
+    return dst
+
+
+def fdmt_stream_mix(dst_ptr, write_bytes, src_ptr, read_bytes, stream):
+    _check(load().fdmt_stream_mix(dst_ptr, int(write_bytes), src_ptr, int(read_bytes), stream), "fdmt_stream_mix")
+
+
+def stream_mix(dst, src):
+    """The library's read/write-mix stream: reads all of src's bytes once and
+    writes all of dst's once (contiguous device tensors; each byte count a
+    multiple of 16 and at most twice the other), on the current stream."""
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst and src must be contiguous")
+    fdmt_stream_mix(ctypes.c_void_p(dst.data_ptr()), dst.numel() * dst.element_size(),
+                    ctypes.c_void_p(src.data_ptr()), src.numel() * src.element_size(), _stream_handle(src.device))
     return dst
 
 

@@ -881,6 +881,23 @@ fdmt_status_t fdmt_copy_bytes(void *dst, const void *src, size_t bytes, void *hi
   return FDMT_OK;
 }
 
+fdmt_status_t fdmt_stream_mix(void *dst, size_t write_bytes, const void *src, size_t read_bytes,
+                              void *hip_stream) {
+  if (write_bytes == 0 && read_bytes == 0) return FDMT_OK;
+  if (!dst || !src) return fail(FDMT_E_INVALID, "src or dst is NULL");
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) != 0)
+    return fail(FDMT_E_INVALID, "src and dst must be 16-byte aligned");
+  if ((write_bytes | read_bytes) & 15u) return fail(FDMT_E_INVALID, "byte counts must be multiples of 16");
+  if (write_bytes == 0 || read_bytes == 0 || write_bytes > 2 * read_bytes || read_bytes > 2 * write_bytes)
+    return fail(FDMT_E_INVALID, "each byte count must be at least half the other");
+  const uintptr_t d = reinterpret_cast<uintptr_t>(dst), s = reinterpret_cast<uintptr_t>(src);
+  if (d < s + read_bytes && s < d + write_bytes) return fail(FDMT_E_INVALID, "src and dst overlap");
+  const hipError_t e =
+      fdmt::launch_stream_mix(dst, write_bytes, src, read_bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(e, "stream mix launch");
+  return FDMT_OK;
+}
+
 fdmt_status_t fdmt_tuned_options(const char *cache_path, const char *arch, int32_t nf, int64_t nt, int32_t nd,
                                  double f_min, double f_max, fdmt_options_t *opt, int32_t *found) {
   if (found) *found = 0;

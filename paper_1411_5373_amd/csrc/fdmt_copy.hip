@@ -34,6 +34,34 @@ __global__ __launch_bounds__(kCopyThreads) void stream_copy_kernel(const U4 *__r
   }
 }
 
+// A stream with a given read/write mix: unit i of dst (i < nw) takes src unit
+// i, or i - nr past the source's end, when nw >= nr; when nr > nw it takes
+// src unit i xor unit i + nw (the latter only while inside the source). So
+// every source unit is read once, every destination unit written once, with
+// nr <= 2 nw and nw <= 2 nr. Same thread shape as the copy.
+__global__ __launch_bounds__(kCopyThreads) void stream_mix_kernel(const U4 *__restrict__ src, U4 *__restrict__ dst,
+                                                                  int64_t nw, int64_t nr) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * (kCopyThreads * kCopyUnits) + threadIdx.x;
+  U4 v[kCopyUnits];
+#pragma unroll
+  for (int k = 0; k < kCopyUnits; ++k) {
+    const int64_t i = base + k * kCopyThreads;
+    if (i < nw) {
+      if (nw >= nr) {
+        v[k] = src[i < nr ? i : i - nr];
+      } else {
+        v[k] = src[i];
+        if (i + nw < nr) v[k] ^= src[i + nw];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kCopyUnits; ++k) {
+    const int64_t i = base + k * kCopyThreads;
+    if (i < nw) dst[i] = v[k];
+  }
+}
+
 // The last bytes % 16 bytes.
 __global__ void copy_tail_kernel(const unsigned char *__restrict__ src, unsigned char *__restrict__ dst, int n) {
   if (static_cast<int>(threadIdx.x) < n) dst[threadIdx.x] = src[threadIdx.x];
@@ -53,6 +81,16 @@ hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStrea
     hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, stream,
                        static_cast<const unsigned char *>(src) + n16 * 16,
                        static_cast<unsigned char *>(dst) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_mix(void *dst, size_t write_bytes, const void *src, size_t read_bytes,
+                             hipStream_t stream) {
+  const int64_t nw = static_cast<int64_t>(write_bytes / 16), nr = static_cast<int64_t>(read_bytes / 16);
+  if (nw == 0) return hipSuccess;
+  const int64_t blocks = (nw + kCopyThreads * kCopyUnits - 1) / (kCopyThreads * kCopyUnits);
+  hipLaunchKernelGGL(stream_mix_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kCopyThreads), 0, stream,
+                     static_cast<const U4 *>(src), static_cast<U4 *>(dst), nw, nr);
   return hipGetLastError();
 }
 

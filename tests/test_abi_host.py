@@ -427,3 +427,20 @@ def test_fft_plan_rules():
     assert lib.fdmt_forward_fft(p.handle, x, o, 1, ws, 1 << 30, None) == B.FDMT_E_INVALID
     assert "FDMT_PLAN_FFT" in F.fdmt_last_error()
     assert lib.fdmt_forward_fft(None, x, o, 1, ws, 1 << 30, None) == B.FDMT_E_INVALID
+
+
+def test_stream_mix_argument_checks():
+    """The read/write-mix stream refuses what its kernel does not cover before
+    touching the device: NULL, misaligned or overlapping buffers, counts not
+    multiples of 16, one count above twice the other."""
+    lib = F.load()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    assert lib.fdmt_stream_mix(a, 0, b, 0, None) == B.FDMT_OK
+    assert lib.fdmt_stream_mix(None, 16, b, 16, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(ctypes.c_void_p((1 << 20) + 4), 16, b, 16, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(a, 24, b, 32, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(a, 16, b, 48, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(a, 48, b, 16, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(a, 16, b, 0, None) == B.FDMT_E_INVALID
+    assert lib.fdmt_stream_mix(a, 1 << 20, ctypes.c_void_p((1 << 20) + 4096), 1 << 20, None) == B.FDMT_E_INVALID
+    assert "overlap" in F.fdmt_last_error()

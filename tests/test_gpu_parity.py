@@ -569,6 +569,27 @@ def test_copy_bytes(nbytes):
     assert torch.equal(dst, src)
 
 
+@pytest.mark.parametrize("write_units,read_units", [(1, 1), (16, 10), (1000, 999), (1024, 640), (640, 1024),
+                                                    (4099, 2050), (2050, 4099)])
+def test_stream_mix(write_units, read_units):
+    """The read/write-mix stream the benchmark measures per-kernel ceilings
+    with writes every destination unit from the source as documented: unit i
+    of src (or i - read_units past its end) when writing at least as much as
+    reading, else unit i xor unit i + write_units."""
+    src = torch.randint(-2**31, 2**31 - 1, (read_units, 4), dtype=torch.int32, device=DEV)
+    dst = torch.zeros((write_units, 4), dtype=torch.int32, device=DEV)
+    F.stream_mix(dst, src)
+    s = src.cpu().numpy()
+    i = np.arange(write_units)
+    if write_units >= read_units:
+        want = s[np.where(i < read_units, i, i - read_units)]
+    else:
+        want = s[i].copy()
+        far = i + write_units < read_units
+        want[far] ^= s[(i + write_units)[far]]
+    np.testing.assert_array_equal(dst.cpu().numpy(), want)
+
+
 TWO_C_SCHEDULES = [dict(), dict(unfused=True),
                    dict(first_kernel=3, first_levels=3, later_levels=3, gather_rows=4, gather_vecs=4,
                         adjoint_levels=3, adjoint_last_levels=3, adjoint_last_threads=256, adjoint_tile_major=9),
