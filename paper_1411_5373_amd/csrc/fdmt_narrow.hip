@@ -209,8 +209,12 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
     if constexpr (FROM_INPUT) {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const char *p = reinterpret_cast<const char *>(base + row_offset(row[j], src_stride) + (t - shift[j] - chain[j]));
-        mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+        // the wave's first sample of the term, a wave-uniform address: its
+        // misalignment is every lane's (lanes are S bytes apart) and comes
+        // from scalar arithmetic, not a read back from a lane
+        const Tsrc *pw = base + row_offset(row[j], src_stride) + (tw - shift[j] - chain[j]);
+        mis[j] = static_cast<int>(reinterpret_cast<uintptr_t>(pw) & 3);
+        const char *p = reinterpret_cast<const char *>(pw + lane * S);
         // a chain of at most 1 ends by byte 3 + 1 + S - 1 of the words: CV + 1 of them
         load_words<SHORT ? CV + 1 : W>(w[j], p - mis[j]);
       }
@@ -227,8 +231,9 @@ __global__ __launch_bounds__(kGatherThreads) void narrow_gather_kernel(
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         const Tsrc *rp = base + row_offset(row[j], src_stride);
-        const char *p = reinterpret_cast<const char *>(rp + (t - shift[j]));
-        mis[j] = uniform(static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3));
+        const Tsrc *pw = rp + (tw - shift[j]);  // wave-uniform; lanes are 2 S bytes apart
+        mis[j] = static_cast<int>(reinterpret_cast<uintptr_t>(pw) & 3);
+        const char *p = reinterpret_cast<const char *>(pw + lane * S);
         load_words<H>(w[j], p - mis[j]);
         w[j][H] = 0;
         past[j] = 0;
