@@ -21,11 +21,12 @@ namespace {
 // but a lane owns S = 4 * CV consecutive samples, so a term is one wide load
 // per lane: W aligned words that cover the lane's bytes whatever their
 // misalignment, which is the same for every lane of a term (t is a multiple
-// of 4). Bytes take 16 bytes for 8 samples. uint16 take 20 bytes for 8
-// samples, of which a lane loads only its own 16 and takes the last word from
-// the next lane: one 16-byte load per term, which cut the uint16 passes of
-// the Nf=4096 step by 15-17% (taking the 8 bytes past the lane the same way
-// for byte input made that pass 25% slower: its loads are not the limit).
+// of 4). Bytes take 16 bytes for 8 samples (12 when no chain of the pass is
+// longer than 1). uint16 take 20 bytes for 8 samples, of which a lane loads
+// only its own 16 and takes the last word from the next lane: one 16-byte
+// load per term, which cut the uint16 passes of the Nf=4096 step by 15-17%
+// (taking the 8 bytes past the lane the same way for byte input made that
+// pass 25% slower: its loads are not the limit).
 template <bool FROM_INPUT, int CV>
 struct NarrowShape {
   static constexpr int S = 4 * CV;  // samples per lane
